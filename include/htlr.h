@@ -1,0 +1,214 @@
+/*
+ * htlr.h -- C ABI of the MI355X library for hierarchical Tucker low-rank
+ * (HTLR) matrices (Li & Liu, "Hierarchical Tucker Low-Rank Matrices:
+ * Construction and Matrix-Vector Multiplication", arXiv 2508.05958).
+ *
+ * The operator is the Nystrom discretisation of the integral equation
+ * a(x) u(x) + int_[0,1]^d k(x,y) u(y) dy = f(x)   (Sec. 1, eq. 1.1), i.e.
+ *
+ *     f_i = a_i u_i + sum_j K_ij |Omega_j| u_j                 (eq. 1.3 and
+ *     K_ij = k(x_i, x_j) (j != i),  K_ii |Omega_i| = int_Omega_i k(x_i,y) dy
+ *                                                      (eq. 1.4, Sec. 3.3)
+ *
+ * on a tensor grid {x_i} in [0,1]^d, compressed into an HTLR matrix
+ * (Def. 3.7): a 2^d cluster tree (Def. 2.1, 3.5), a block cluster tree under
+ * strong or weak admissibility (Defs. 2.2-2.4, 3.6), Tucker low-rank blocks
+ * from tensor Chebyshev interpolation on admissible leaves (eq. 3.4-3.6,
+ * Alg. 4.1) and dense blocks on inadmissible leaves (eq. 4.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Vectors are in natural grid order: multi-index (i_1,...,i_d), 0-based,
+ *   maps to i_1 + n*i_2 + n^2*i_3 (first index fastest, Sec. 2.1).
+ * - Several right-hand sides form an N x nrhs column-major array (each
+ *   right-hand side contiguous).
+ * - Pointers documented as "device" must point to GPU memory of the device
+ *   current at the call (for example torch.Tensor.data_ptr()).  Pointers
+ *   documented as "host" are read before the call returns.
+ * - A "stream" argument is a hipStream_t passed as void*; NULL is the null
+ *   stream.  Work enqueued on a stream completes asynchronously; the caller
+ *   keeps the device buffers alive until the stream has finished.
+ * - Every call returns an htlr_status; nothing crosses the ABI as an
+ *   exception.  On failure htlr_last_error() returns a message (thread
+ *   local, valid until the next call on the same thread).  A kernel fault
+ *   surfaces at the next synchronising call as HTLR_ERR_HIP.
+ */
+#ifndef HTLR_H
+#define HTLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct htlr_matrix_s* htlr_matrix; /* opaque; owns all its device memory */
+
+typedef enum {
+  HTLR_OK = 0,
+  HTLR_ERR_INVALID = -1,       /* bad argument (null pointer, size, order of nodes, ...) */
+  HTLR_ERR_UNSUPPORTED = -2,   /* valid request the GPU path does not implement */
+  HTLR_ERR_OOM = -3,           /* a device or host allocation failed */
+  HTLR_ERR_HIP = -4,           /* a HIP runtime call failed */
+  HTLR_ERR_NOT_CONVERGED = -5, /* solver stopped at its iteration limit */
+  HTLR_ERR_NUMERIC = -6        /* NaN/Inf in an input or a breakdown */
+} htlr_status;
+
+/* Kernel functions k(x, y), r = |x - y| (Euclidean).  The paper's Sec. 5 uses
+ * the Gaussian and single-layer-potential kernels; the unnormalised forms
+ * are used here.  HTLR_K_POLY_TEST is the polynomial
+ *   prod_l (1 + A_l (x_l - y_l))^(p-1),   A = (0.50, 0.30, 0.20),
+ * of degree p-1 in every coordinate, which Chebyshev interpolation with p
+ * points reproduces exactly (Lemma 3.1); it exists for testing. */
+typedef enum {
+  HTLR_K_INV_R = 0,      /* 1 / r                                   */
+  HTLR_K_NEG_LOG = 1,    /* -log r                                  */
+  HTLR_K_EXP = 2,        /* exp(-r)                                 */
+  HTLR_K_GAUSS = 3,      /* exp(-r^2 / (2 sigma^2)), sigma^2 = d     */
+  HTLR_K_POLY_TEST = 100
+} htlr_kernel;
+
+/* Arithmetic of a product.  HTLR_FP64: every step in double.  HTLR_FP32:
+ * far-field contractions and near field in float.  HTLR_BF16_CORE: as FP32,
+ * but the core apply multiplies bfloat16 cores by bfloat16 source tensors on
+ * the matrix cores with float accumulation. */
+typedef enum { HTLR_FP64 = 0, HTLR_FP32 = 1, HTLR_BF16_CORE = 2 } htlr_precision;
+
+/* Element type of the vectors passed to htlr_matvec. */
+typedef enum { HTLR_VEC_F64 = 0, HTLR_VEC_F32 = 1 } htlr_vec_dtype;
+
+typedef enum { HTLR_ADM_STRONG = 0, HTLR_ADM_WEAK = 1 } htlr_admissibility;
+
+typedef struct {
+  /* eta^2 of strong admissibility, max(diam) <= eta * dist (Def. 2.3),
+   * tested as max(diam^2) <= eta2 * dist^2; equality is admissible.
+   * <= 0 selects 1.0 ("dist >= box diameter"). */
+  double eta2;
+  int admissibility;     /* htlr_admissibility (Def. 2.3 or Def. 2.2)             */
+  int gl_order;          /* Gauss-Legendre points per dimension for the diagonal
+                            integrals of eq. 1.4; 0 selects 16 (d=2) or 8 (d=3)   */
+  const double* a;       /* host, N samples a(x_i) in natural order; NULL: a = 0   */
+  int precisions;        /* bit mask of (1 << htlr_precision) the matrix will be
+                            applied in; selects which core copies are kept;
+                            0 selects all three                                    */
+} htlr_build_opts;
+
+/* Builds the HTLR matrix of the Nystrom operator above (Alg. 4.1).
+ *
+ * points : host, d*n doubles, or NULL.  Node coordinates per dimension,
+ *          dimension-major: points[l*n + k] = x_{l;k}, strictly increasing
+ *          inside (0, 1).  The grid is their tensor product; cells Omega_i
+ *          are the products of the 1D Voronoi cells (midpoints between
+ *          neighbouring nodes, 0 and 1 at the ends; Sec. 2.2).  NULL means
+ *          the uniform cell-centred grid x_{l;k} = (k + 1/2)/n (Example 2.2).
+ *          A grid whose nodes equal the uniform ones to 1e-14 is treated as
+ *          uniform (translation-invariant cores, exact integer geometry).
+ * kernel : htlr_kernel.
+ * d      : 2 or 3.
+ * n      : points per dimension (N = n^d).
+ * p      : Chebyshev points per dimension (Tucker rank, Sec. 3.1), 1..12.
+ * leaf   : leaf threshold N_0 = leaf^d; a cluster is a leaf when it has at
+ *          most N_0 points (Sec. 2.2).  n must halve exactly down to the
+ *          leaf level, otherwise HTLR_ERR_UNSUPPORTED.
+ * opts   : host, may be NULL (all defaults).
+ * out    : host; receives the handle.  The handle keeps copies of points and
+ *          a; the caller may free them on return.
+ *
+ * Runs synchronously on the null stream of the current device. */
+htlr_status htlr_build(const double* points, htlr_kernel kernel, int d, int n, int p,
+                       int leaf, const htlr_build_opts* opts, htlr_matrix* out);
+
+/* Device bytes htlr_build would hold for the same arguments (cores, factors,
+ * geometry, near-field tables, block lists), without allocating; used for
+ * admission by memory footprint.  Work buffers of products and solves are
+ * reported by htlr_workspace_bytes. */
+htlr_status htlr_footprint(const double* points, htlr_kernel kernel, int d, int n, int p,
+                           int leaf, const htlr_build_opts* opts, size_t* bytes);
+
+/* Device bytes of the work buffers a product with nrhs right-hand sides in
+ * precision prec needs (allocated inside the handle on first use). */
+htlr_status htlr_workspace_bytes(htlr_matrix A, int nrhs, htlr_precision prec, size_t* bytes);
+
+/* f = A u (overwrites f) by the HTLR product (Alg. 4.2, eq. 4.3).
+ *
+ * u, f   : device, N x nrhs column-major, element type vec_dtype; must not
+ *          overlap.  HTLR_FP64 needs HTLR_VEC_F64; HTLR_FP32 and
+ *          HTLR_BF16_CORE need HTLR_VEC_F32.
+ * nrhs   : 1..64.
+ * stream : hipStream_t or NULL.
+ *
+ * Uses work buffers owned by the handle: products on one handle must be
+ * issued on one stream at a time. */
+htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_precision prec,
+                        htlr_vec_dtype vec_dtype, void* stream);
+
+/* Solver options (the paper has no solver: solving A u = f is the
+ * "backward evaluation" of Sec. 1).  Restarted GMRES(restart) with x0 = 0 and
+ * classical Gram-Schmidt with reorthogonalisation in double, wrapped in
+ * iterative refinement: the residual r = f - A x is formed with the FP64
+ * product, the correction solves A d = r with products in inner_prec. */
+typedef struct {
+  double tol;          /* stop when ||f - A x||_2 / ||f||_2 <= tol (FP64 residual); <=0: 1e-10 */
+  int restart;         /* Krylov dimension per cycle; <=0: 30 */
+  int max_outer;       /* refinement steps; <=0: 20 */
+  int max_inner;       /* inner iterations per refinement step; <=0: 300 */
+  int inner_prec;      /* htlr_precision of the inner products */
+  double inner_tol;    /* relative residual target of an inner solve; <=0: 1e-6 (FP32), 1e-2 (BF16), tol (FP64) */
+} htlr_solve_opts;
+
+typedef struct {
+  int outer_iters;      /* refinement steps taken */
+  int inner_iters;      /* total inner GMRES iterations */
+  int matvecs_fp64;     /* FP64 products used */
+  int matvecs_inner;    /* inner-precision products used */
+  double rel_residual;  /* final ||f - A x|| / ||f|| with the FP64 product */
+} htlr_solve_info;
+
+/* Solves A u = f.  f, u: device, N doubles (nrhs must be 1).  On
+ * HTLR_ERR_NOT_CONVERGED, u holds the best iterate and info its residual.
+ * f = 0 returns u = 0.  NaN/Inf in f returns HTLR_ERR_NUMERIC.  Allocates
+ * its Krylov basis (restart+1 vectors of N doubles) per call; synchronises
+ * the stream for the scalar Givens updates. */
+htlr_status htlr_solve(htlr_matrix A, const double* f, double* u, int nrhs,
+                       const htlr_solve_opts* opts, htlr_solve_info* info, void* stream);
+
+/* Structure statistics of a built matrix. */
+typedef struct {
+  int d, n, p, leaf_side, levels;     /* levels = depth L of the cluster tree        */
+  int uniform;                        /* 1: translation-invariant (uniform) grid       */
+  int64_t adm_pairs[16];              /* admissible leaves per level 0..15              */
+  int64_t unique_cores[16];           /* stored cores per level (uniform grids)         */
+  int64_t near_pairs;                 /* inadmissible leaves                            */
+  size_t device_bytes;                /* what htlr_footprint reports                    */
+  double diag0;                       /* D_0 = K_00 |Omega_0| (uniform: every D_i)       */
+} htlr_info_t;
+
+htlr_status htlr_info(htlr_matrix A, htlr_info_t* info);
+
+/* Releases the handle and all its device memory (synchronises the device). */
+void htlr_free(htlr_matrix A);
+
+const char* htlr_last_error(void);
+
+/* Host-only planner, for inspection and tests; touches no GPU.
+ * Counts the leaves of the block cluster tree (Def. 2.4) for the given grid
+ * (points as in htlr_build, may be NULL), per level. */
+htlr_status htlr_plan_counts(const double* points, int d, int n, int leaf, double eta2,
+                             int admissibility, int* levels, int64_t* adm_per_level /*[16]*/,
+                             int64_t* near_pairs);
+
+/* Host-only planner: the admissible (level >= 0) or inadmissible (level < 0)
+ * leaves of the block cluster tree as pairs of box indices at that level
+ * (box multi-index b, linear index b_1 + B b_2 + B^2 b_3, B boxes per
+ * dimension).  Writes up to cap pairs into tau[] and sigma[] (host), sorted
+ * by (tau, sigma), and the total into *count. */
+htlr_status htlr_plan_pairs(const double* points, int d, int n, int leaf, double eta2,
+                            int admissibility, int level, int32_t* tau, int32_t* sigma,
+                            int64_t cap, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTLR_H */

@@ -2,12 +2,12 @@
 
 The paper's experiments (Sec. 5) use a Gaussian kernel with bandwidth sqrt(d)
 and single-layer-potential kernels (-log r in 2D, 1/r in 3D).  The workloads
-use the unnormalised forms 1/r, -log r and exp(-r).  ``poly_test`` is a
-polynomial of degree p-1 in every coordinate of x and of y; Chebyshev
-interpolation with p points per dimension reproduces it exactly (Lemma 3.1:
-the (p+1)-th derivative bound vanishes), which pins the whole far field.
-It is deliberately anisotropic and non-symmetric so that swapped modes or a
-transposed core change the result.
+use the unnormalised forms 1/r, -log r and exp(-r).  ``poly_test`` is
+prod_l (1 + A_l (x_l - y_l))^(p-1), a polynomial of degree p-1 in every
+coordinate of x and of y; Chebyshev interpolation with p points per
+dimension reproduces it exactly (Lemma 3.1: the error bound vanishes), which
+pins the whole far field.  It is deliberately anisotropic and non-symmetric
+so that swapped modes or a transposed core change the result.
 
 Parity: pinned by closed-form values in tests/test_oracle_basics.py.
 """
@@ -15,8 +15,6 @@ import numpy as np
 
 # Coefficients of the polynomial test kernel, per dimension.
 POLY_A = (0.50, 0.30, 0.20)
-POLY_B = (0.25, 0.60, 0.10)
-POLY_C = (0.30, 0.20, 0.50)
 
 
 def evaluate(name: str, X: np.ndarray, Y: np.ndarray, p: int) -> np.ndarray:
@@ -36,8 +34,6 @@ def evaluate(name: str, X: np.ndarray, Y: np.ndarray, p: int) -> np.ndarray:
         d = X.shape[-1]
         out = 1.0
         for l in range(d):
-            base = 1.0 + POLY_A[l] * X[..., l] + POLY_B[l] * Y[..., l] \
-                + POLY_C[l] * X[..., l] * Y[..., l]
-            out = out * base ** (p - 1)
+            out = out * (1.0 + POLY_A[l] * diff[..., l]) ** (p - 1)
         return out
     raise ValueError(f"unknown kernel {name}")

@@ -1,0 +1,247 @@
+"""Python binding of the HTLR library for MI355X (libhtlr.so).
+
+Argument marshalling only: every step of construction, product and solve
+runs in the library's HIP kernels.  PyTorch supplies device memory and
+streams.  The names follow the C ABI in include/htlr.h.
+
+Loading fails loudly when the library has not been built
+(``python -m paper_2508_05958_amd.build`` or ``__graft_entry__.build()``);
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhtlr.so")
+
+HTLR_OK = 0
+STATUS = {0: "HTLR_OK", -1: "HTLR_ERR_INVALID", -2: "HTLR_ERR_UNSUPPORTED", -3: "HTLR_ERR_OOM",
+          -4: "HTLR_ERR_HIP", -5: "HTLR_ERR_NOT_CONVERGED", -6: "HTLR_ERR_NUMERIC"}
+KERNELS = {"inv_r": 0, "neg_log": 1, "exp": 2, "gauss": 3, "poly_test": 100}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+VEC_F64, VEC_F32 = 0, 1
+ADM = {"strong": 0, "weak": 1}
+
+
+class HTLRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _BuildOpts(ctypes.Structure):
+    _fields_ = [("eta2", ctypes.c_double), ("admissibility", ctypes.c_int), ("gl_order", ctypes.c_int),
+                ("a", ctypes.POINTER(ctypes.c_double)), ("precisions", ctypes.c_int)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_outer", ctypes.c_int),
+                ("max_inner", ctypes.c_int), ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("matvecs_fp64", ctypes.c_int),
+                ("matvecs_inner", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("p", ctypes.c_int), ("leaf_side", ctypes.c_int),
+                ("levels", ctypes.c_int), ("uniform", ctypes.c_int), ("adm_pairs", ctypes.c_int64 * 16),
+                ("unique_cores", ctypes.c_int64 * 16), ("near_pairs", ctypes.c_int64),
+                ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double)]
+
+
+_lib = None
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        L.htlr_last_error.restype = ctypes.c_char_p
+        L.htlr_build.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)]
+        L.htlr_footprint.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(_BuildOpts), ctypes.POINTER(ctypes.c_size_t)]
+        L.htlr_workspace_bytes.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.htlr_matvec.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
+        L.htlr_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(_SolveOpts),
+                                 ctypes.POINTER(_SolveInfo), _vp]
+        L.htlr_info.argtypes = [_vp, ctypes.POINTER(_Info)]
+        L.htlr_free.argtypes = [_vp]
+        L.htlr_free.restype = None
+        L.htlr_plan_counts.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]
+        L.htlr_plan_pairs.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        for name in ("htlr_build", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec", "htlr_solve",
+                     "htlr_info", "htlr_plan_counts", "htlr_plan_pairs"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HTLR_OK:
+        raise HTLRError(status, lib().htlr_last_error().decode())
+
+
+def _points_arg(points, d, n):
+    if points is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(d * n))
+    return arr, arr.ctypes.data_as(_c_dp)
+
+
+def _opts(eta2, admissibility, gl_order, a, precisions):
+    o = _BuildOpts()
+    o.eta2 = float(eta2)
+    o.admissibility = ADM[admissibility] if isinstance(admissibility, str) else int(admissibility)
+    o.gl_order = int(gl_order)
+    keep = None
+    if a is not None:
+        keep = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        o.a = keep.ctypes.data_as(_c_dp)
+    if isinstance(precisions, (list, tuple)):
+        precisions = sum(1 << PRECISIONS[p] for p in precisions)
+    o.precisions = int(precisions)
+    return o, keep
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+@dataclass
+class SolveInfo:
+    outer_iters: int
+    inner_iters: int
+    matvecs_fp64: int
+    matvecs_inner: int
+    rel_residual: float
+
+
+class HTLRMatrix:
+    """An HTLR matrix resident on the current GPU (wraps htlr_matrix)."""
+
+    def __init__(self, points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
+                 a=None, precisions=0):
+        self.d, self.n, self.p, self.leaf = d, n, p, leaf
+        self.N = n ** d
+        self.kernel = kernel
+        keep_pts, pts = _points_arg(points, d, n)
+        o, keep_a = _opts(eta2, admissibility, gl_order, a, precisions)
+        h = _vp()
+        kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        _check(lib().htlr_build(pts, kid, d, n, p, leaf, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        del keep_pts, keep_a
+
+    def matvec(self, u, f=None, prec="fp64", stream=None):
+        """f = A u for device tensors u (N,) or (N, nrhs), column-major for nrhs > 1."""
+        import torch
+        pr = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        dt = torch.float64 if pr == 0 else torch.float32
+        if u.dtype != dt or not u.is_cuda:
+            raise HTLRError(-1, f"u must be a {dt} CUDA tensor")
+        nrhs = 1 if u.dim() == 1 else u.shape[1]
+        if u.dim() == 2 and not (u.stride(0) == 1 and u.stride(1) == self.N):
+            raise HTLRError(-1, "u must be column-major (each right-hand side contiguous)")
+        if u.dim() == 1 and not u.is_contiguous():
+            raise HTLRError(-1, "u must be contiguous")
+        if f is None:
+            f = torch.empty_like(u)
+        _check(lib().htlr_matvec(self._h, u.data_ptr(), f.data_ptr(), nrhs, pr,
+                                 VEC_F64 if pr == 0 else VEC_F32, _stream_ptr(stream)))
+        return f
+
+    def solve(self, f, u=None, tol=1e-10, restart=30, max_outer=20, max_inner=300, inner_prec="fp32",
+              inner_tol=0.0, stream=None, check=True):
+        import torch
+        if u is None:
+            u = torch.zeros_like(f)
+        o = _SolveOpts(tol, restart, max_outer, max_inner,
+                       PRECISIONS[inner_prec] if isinstance(inner_prec, str) else int(inner_prec), inner_tol)
+        info = _SolveInfo()
+        st = lib().htlr_solve(self._h, f.data_ptr(), u.data_ptr(), 1, ctypes.byref(o), ctypes.byref(info),
+                              _stream_ptr(stream))
+        res = SolveInfo(info.outer_iters, info.inner_iters, info.matvecs_fp64, info.matvecs_inner,
+                        info.rel_residual)
+        if check:
+            _check(st)
+        return u, res, st
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(lib().htlr_info(self._h, ctypes.byref(i)))
+        return {"d": i.d, "n": i.n, "p": i.p, "leaf_side": i.leaf_side, "levels": i.levels,
+                "uniform": bool(i.uniform), "adm_pairs": list(i.adm_pairs[: i.levels + 1]),
+                "unique_cores": list(i.unique_cores[: i.levels + 1]), "near_pairs": i.near_pairs,
+                "device_bytes": i.device_bytes, "diag0": i.diag0}
+
+    def workspace_bytes(self, nrhs=1, prec="fp64") -> int:
+        b = ctypes.c_size_t()
+        _check(lib().htlr_workspace_bytes(self._h, nrhs, PRECISIONS[prec], ctypes.byref(b)))
+        return b.value
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().htlr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def htlr_build(points, kernel, d, n, p, leaf, **kw) -> HTLRMatrix:
+    return HTLRMatrix(points, kernel, d, n, p, leaf, **kw)
+
+
+def htlr_footprint(points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
+                   precisions=0) -> int:
+    keep_pts, pts = _points_arg(points, d, n)
+    o, _ = _opts(eta2, admissibility, gl_order, None, precisions)
+    b = ctypes.c_size_t()
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    _check(lib().htlr_footprint(pts, kid, d, n, p, leaf, ctypes.byref(o), ctypes.byref(b)))
+    return b.value
+
+
+def htlr_plan_counts(points, d, n, leaf, eta2=1.0, admissibility="strong"):
+    keep, pts = _points_arg(points, d, n)
+    L = ctypes.c_int()
+    adm = (ctypes.c_int64 * 16)()
+    near = ctypes.c_int64()
+    _check(lib().htlr_plan_counts(pts, d, n, leaf, float(eta2), ADM[admissibility], ctypes.byref(L), adm,
+                                  ctypes.byref(near)))
+    return L.value, list(adm[: L.value + 1]), near.value
+
+
+def htlr_plan_pairs(points, d, n, leaf, level, eta2=1.0, admissibility="strong"):
+    keep, pts = _points_arg(points, d, n)
+    cnt = ctypes.c_int64()
+    _check(lib().htlr_plan_pairs(pts, d, n, leaf, float(eta2), ADM[admissibility], level, None, None, 0,
+                                 ctypes.byref(cnt)))
+    tau = np.empty(cnt.value, dtype=np.int32)
+    sig = np.empty(cnt.value, dtype=np.int32)
+    _check(lib().htlr_plan_pairs(pts, d, n, leaf, float(eta2), ADM[admissibility], level,
+                                 tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 sig.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cnt.value, ctypes.byref(cnt)))
+    return tau, sig

@@ -1,0 +1,77 @@
+// Device-side helpers: kernel functions k(x - y), bfloat16 conversion.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "htlr.h"
+
+namespace htlr {
+
+__device__ __constant__ static const double kPolyADev[3] = {0.50, 0.30, 0.20};
+
+// Radial kernels as functions of r^2 (r = |x - y|).
+template <int KID>
+__device__ __forceinline__ double kr2(double r2, int d) {
+  if constexpr (KID == HTLR_K_INV_R) return 1.0 / sqrt(r2);
+  else if constexpr (KID == HTLR_K_NEG_LOG) return -0.5 * log(r2);
+  else if constexpr (KID == HTLR_K_EXP) return exp(-sqrt(r2));
+  else return exp(-r2 / (2.0 * d));
+}
+
+template <int KID>
+__device__ __forceinline__ float kr2(float r2, int d) {
+  if constexpr (KID == HTLR_K_INV_R) return rsqrtf(r2);
+  else if constexpr (KID == HTLR_K_NEG_LOG) return -0.5f * logf(r2);
+  else if constexpr (KID == HTLR_K_EXP) return expf(-sqrtf(r2));
+  else return expf(-r2 / (2.0f * d));
+}
+
+template <typename T>
+__device__ __forceinline__ T ipow(T b, int e) {
+  T r = T(1);
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// k evaluated at the difference vector (dx0, dx1, dx2); pm1 = p - 1 (poly).
+template <int KID, typename T>
+__device__ __forceinline__ T kvec(T dx0, T dx1, T dx2, int d, int pm1) {
+  if constexpr (KID == HTLR_K_POLY_TEST) {
+    T v = ipow(T(1) + T(kPolyADev[0]) * dx0, pm1) * ipow(T(1) + T(kPolyADev[1]) * dx1, pm1);
+    if (d == 3) v *= ipow(T(1) + T(kPolyADev[2]) * dx2, pm1);
+    return v;
+  } else {
+    T r2 = dx0 * dx0 + dx1 * dx1 + dx2 * dx2;
+    return kr2<KID>(r2, d);
+  }
+}
+
+// bfloat16 stored as uint16_t; round to nearest even.
+__device__ __host__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t x = __builtin_bit_cast(uint32_t, f);
+  if ((x & 0x7f800000u) == 0x7f800000u) return (uint16_t)((x >> 16) | ((x & 0xffffu) ? 0x40u : 0u));
+  x += 0x7fffu + ((x >> 16) & 1u);
+  return (uint16_t)(x >> 16);
+}
+
+__device__ __host__ __forceinline__ float bf2f(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+template <typename T> struct Acc { using type = T; };
+template <> struct Acc<uint16_t> { using type = float; };
+
+template <typename T> __device__ __forceinline__ T load_as(const T* p) { return *p; }
+__device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ double to_acc(double v) { return v; }
+__device__ __forceinline__ float to_acc(uint16_t v) { return bf2f(v); }
+
+template <typename T> __device__ __forceinline__ T from_acc(float v);
+template <> __device__ __forceinline__ float from_acc<float>(float v) { return v; }
+template <> __device__ __forceinline__ uint16_t from_acc<uint16_t>(float v) { return f2bf(v); }
+template <typename T> __device__ __forceinline__ T from_acc_d(double v);
+template <> __device__ __forceinline__ double from_acc_d<double>(double v) { return v; }
+
+}  // namespace htlr

@@ -1,0 +1,679 @@
+// HTLR matrix-vector product (Alg. 4.2, eq. 4.3) on the GPU.
+//
+// The recursion of Alg. 4.2 visits every leaf (tau, sigma) of the block
+// cluster tree once.  Here the leaves are processed level by level, and
+// each step is one launch over all boxes of a level:
+//
+//   near   f_tau  = a o u_tau + sum_{sigma in near(tau)} A_tau,sigma u_sigma
+//          (inadmissible leaves, eq. 4.1, kernel values made on the fly),
+//   up     W_sigma = (|Omega| o u_sigma) x_1 V_1^T ... x_d V_d^T,
+//   core   H_tau  = sum_{sigma in adm(tau)} G_tau,sigma x_{[d+1..2d],[1..d]} W_sigma,
+//   down   f_tau += H_tau x_1 U_1 ... x_d U_d,
+//
+// for every level that has admissible leaves.  W_sigma depends only on sigma,
+// so it is computed once per box instead of once per leaf; the sum over the
+// leaves of a row block is the same sum Alg. 4.2 forms, in a different order.
+// Every output element is written by exactly one thread of one launch, and
+// launches on a stream are ordered, so the product is deterministic.
+
+#include <algorithm>
+#include <cstring>
+
+#include "htlr_device.h"
+#include "htlr_handle.h"
+
+namespace htlr {
+
+htlr_status record(const Error& e);
+extern thread_local std::string g_last_error;
+
+constexpr int kThreads = 256;
+
+template <typename TW, typename T> __device__ __forceinline__ TW store_cast(T v) { return (TW)v; }
+template <> __device__ __forceinline__ uint16_t store_cast<uint16_t, float>(float v) { return f2bf(v); }
+
+__device__ __forceinline__ int64_t lin3(int i0, int i1, int i2, int n) {
+  return (int64_t)i0 + (int64_t)n * ((int64_t)i1 + (int64_t)n * i2);
+}
+
+// ---------------------------------------------------------------------------
+// Near field + diagonal, uniform grid: the kernel value between two points
+// depends on their integer index difference delta only.  Radial kernels read
+// h^d k(h sqrt(|delta|^2)) from a table indexed by |delta|^2 (entry 0 is the
+// diagonal integral D); the polynomial test kernel is evaluated directly.
+template <int KID, typename T, int RC>
+__global__ __launch_bounds__(kThreads) void k_near_uniform(
+    const T* __restrict__ u, T* __restrict__ f, const T* __restrict__ a, const int64_t* __restrict__ nptr,
+    const int32_t* __restrict__ nsrc, const T* __restrict__ table, int tsize, int d, int n, int m, int B,
+    int nrhs, T h, T w0, T D0, int pm1) {
+  extern __shared__ unsigned char smem_raw[];
+  T* tab = reinterpret_cast<T*>(smem_raw);
+  const bool radial = KID != HTLR_K_POLY_TEST;
+  T* us = tab + (radial ? ((tsize + 1) & ~1) : 0);
+  const int M = (d == 3) ? m * m * m : m * m;
+  const int tid = threadIdx.x;
+  const int tau = blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  int tb[3] = {tau % B, (tau / B) % B, d == 3 ? tau / (B * B) : 0};
+  if (radial)
+    for (int s = tid; s < tsize; s += kThreads) tab[s] = table[s];
+  constexpr int IPT = 4;  // up to 4 * 256 target points per leaf
+  T acc[IPT][RC];
+  int Ii[IPT][3];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    int i = tid + q * kThreads;
+    int i0 = i % m, i1 = (i / m) % m, i2 = (d == 3) ? i / (m * m) : 0;
+    Ii[q][0] = tb[0] * m + i0;
+    Ii[q][1] = tb[1] * m + i1;
+    Ii[q][2] = tb[2] * m + i2;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[q][r] = T(0);
+  }
+  for (int64_t e = nptr[tau]; e < nptr[tau + 1]; ++e) {
+    const int sg = nsrc[e];
+    const int sb[3] = {sg % B, (sg / B) % B, d == 3 ? sg / (B * B) : 0};
+    __syncthreads();
+    for (int idx = tid; idx < M * RC; idx += kThreads) {
+      int j = idx % M, r = idx / M;
+      int j0 = j % m, j1 = (j / m) % m, j2 = (d == 3) ? j / (m * m) : 0;
+      int64_t g = lin3(sb[0] * m + j0, sb[1] * m + j1, d == 3 ? sb[2] * m + j2 : 0, n);
+      if (d == 2) g = (int64_t)(sb[0] * m + j0) + (int64_t)n * (sb[1] * m + j1);
+      us[r * M + j] = (r0 + r < nrhs) ? u[(int64_t)(r0 + r) * ((int64_t)n * n * (d == 3 ? n : 1)) + g] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      if (tid + q * kThreads >= M) break;
+      int jj = 0;
+      const int nz = (d == 3) ? m : 1;
+      for (int j2 = 0; j2 < nz; ++j2) {
+        int d2 = (d == 3) ? Ii[q][2] - (sb[2] * m + j2) : 0;
+        for (int j1 = 0; j1 < m; ++j1) {
+          int d1 = Ii[q][1] - (sb[1] * m + j1);
+          int base = d2 * d2 + d1 * d1;
+          for (int j0 = 0; j0 < m; ++j0, ++jj) {
+            int d0 = Ii[q][0] - (sb[0] * m + j0);
+            T kv;
+            if constexpr (radial) {
+              kv = tab[base + d0 * d0];
+            } else {
+              if (d0 == 0 && d1 == 0 && d2 == 0) kv = D0;
+              else kv = w0 * kvec<KID, T>(h * d0, h * d1, h * d2, d, pm1);
+            }
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[q][r] += kv * us[r * M + jj];
+          }
+        }
+      }
+    }
+  }
+  const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    if (tid + q * kThreads >= M) break;
+    int64_t g = (d == 3) ? lin3(Ii[q][0], Ii[q][1], Ii[q][2], n) : (int64_t)Ii[q][0] + (int64_t)n * Ii[q][1];
+    T ai = a[g];
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r0 + r < nrhs) f[(int64_t)(r0 + r) * N + g] = acc[q][r] + ai * u[(int64_t)(r0 + r) * N + g];
+  }
+}
+
+// Near field + diagonal on a general tensor grid: kernel values evaluated from
+// coordinates relative to the target box, weights |Omega_j| and per-point
+// diagonal integrals D_i.
+template <int KID, typename T, int RC>
+__global__ __launch_bounds__(kThreads) void k_near_tensor(
+    const T* __restrict__ u, T* __restrict__ f, const T* __restrict__ a, const T* __restrict__ D,
+    const int64_t* __restrict__ nptr, const int32_t* __restrict__ nsrc, const double* __restrict__ x,
+    const T* __restrict__ wdim, int d, int n, int m, int B, int nrhs, int pm1) {
+  extern __shared__ unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);  // [3][m] source coordinates relative to the target box
+  T* us = cs + 3 * m;                      // [RC][M] weighted source values
+  const int M = (d == 3) ? m * m * m : m * m;
+  const int tid = threadIdx.x;
+  const int tau = blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+  int tb[3] = {tau % B, (tau / B) % B, d == 3 ? tau / (B * B) : 0};
+  double org[3];
+  for (int l = 0; l < 3; ++l) org[l] = l < d ? x[l * n + tb[l] * m] : 0.0;
+  constexpr int IPT = 4;
+  T acc[IPT][RC];
+  T xi[IPT][3];
+  int li[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    int i = tid + q * kThreads;
+    li[q] = i;
+    int ii[3] = {i % m, (i / m) % m, (d == 3) ? i / (m * m) : 0};
+    for (int l = 0; l < 3; ++l) xi[q][l] = l < d ? (T)(x[l * n + tb[l] * m + ii[l]] - org[l]) : T(0);
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[q][r] = T(0);
+  }
+  for (int64_t e = nptr[tau]; e < nptr[tau + 1]; ++e) {
+    const int sg = nsrc[e];
+    const int sb[3] = {sg % B, (sg / B) % B, d == 3 ? sg / (B * B) : 0};
+    __syncthreads();
+    for (int idx = tid; idx < 3 * m; idx += kThreads) {
+      int l = idx / m, j = idx % m;
+      cs[idx] = l < d ? (T)(x[l * n + sb[l] * m + j] - org[l]) : T(0);
+    }
+    for (int idx = tid; idx < M * RC; idx += kThreads) {
+      int j = idx % M, r = idx / M;
+      int jj[3] = {j % m, (j / m) % m, (d == 3) ? j / (m * m) : 0};
+      int gi[3] = {sb[0] * m + jj[0], sb[1] * m + jj[1], d == 3 ? sb[2] * m + jj[2] : 0};
+      int64_t g = (d == 3) ? lin3(gi[0], gi[1], gi[2], n) : (int64_t)gi[0] + (int64_t)n * gi[1];
+      T wj = wdim[gi[0]] * wdim[n + gi[1]];
+      if (d == 3) wj *= wdim[2 * n + gi[2]];
+      us[r * M + j] = (r0 + r < nrhs) ? wj * u[(int64_t)(r0 + r) * N + g] : T(0);
+    }
+    __syncthreads();
+    const bool self = (sg == tau);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      if (li[q] >= M) break;
+      int jj = 0;
+      const int nz = (d == 3) ? m : 1;
+      for (int j2 = 0; j2 < nz; ++j2) {
+        T dx2 = (d == 3) ? xi[q][2] - cs[2 * m + j2] : T(0);
+        for (int j1 = 0; j1 < m; ++j1) {
+          T dx1 = xi[q][1] - cs[m + j1];
+          for (int j0 = 0; j0 < m; ++j0, ++jj) {
+            if (self && jj == li[q]) continue;
+            T dx0 = xi[q][0] - cs[j0];
+            T kv = kvec<KID, T>(dx0, dx1, dx2, d, pm1);
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[q][r] += kv * us[r * M + jj];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    int i = li[q];
+    if (i >= M) break;
+    int ii[3] = {i % m, (i / m) % m, (d == 3) ? i / (m * m) : 0};
+    int gi[3] = {tb[0] * m + ii[0], tb[1] * m + ii[1], d == 3 ? tb[2] * m + ii[2] : 0};
+    int64_t g = (d == 3) ? lin3(gi[0], gi[1], gi[2], n) : (int64_t)gi[0] + (int64_t)n * gi[1];
+    T diag = a[g] + D[g];
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r0 + r < nrhs) f[(int64_t)(r0 + r) * N + g] = acc[q][r] + diag * u[(int64_t)(r0 + r) * N + g];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Up contraction: W_sigma = u~_sigma x_1 V_1^T ... x_d V_d^T, one block per
+// (box, right-hand side), slice by slice along the last dimension.
+// V is [m][p] (uniform: vstride = 0) or [d][B][m][p] (per box).
+template <typename T, typename TW>
+__global__ __launch_bounds__(kThreads) void k_up(const T* __restrict__ u, TW* __restrict__ W,
+                                                 const T* __restrict__ V, int uniform, int d, int n, int m,
+                                                 int B, int p, int nrhs) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sl = reinterpret_cast<T*>(smem_raw);   // slice, m*m (d=3) or m (d=2)
+  T* t1 = sl + (d == 3 ? m * m : m);         // p*m
+  T* t12 = t1 + p * m;                       // p*p
+  const int tid = threadIdx.x;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int P = (d == 3) ? p * p * p : p * p;
+  const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+  int bb[3] = {box % B, (box / B) % B, d == 3 ? box / (B * B) : 0};
+  auto Vk = [&](int k) -> const T* {
+    return uniform ? V : V + ((size_t)k * B + bb[k]) * (size_t)m * p;
+  };
+  const T* V0 = Vk(0);
+  const T* V1 = Vk(1);
+  const T* V2 = d == 3 ? Vk(2) : nullptr;
+  constexpr int WPT = 8;  // up to 8 * 256 core entries (p^d <= 2048)
+  T acc[WPT];
+#pragma unroll
+  for (int q = 0; q < WPT; ++q) acc[q] = T(0);
+  const T* ur = u + (int64_t)r * N;
+  if (d == 3) {
+    for (int j2 = 0; j2 < m; ++j2) {
+      __syncthreads();
+      for (int idx = tid; idx < m * m; idx += kThreads) {
+        int j0 = idx % m, j1 = idx / m;
+        sl[idx] = ur[lin3(bb[0] * m + j0, bb[1] * m + j1, bb[2] * m + j2, n)];
+      }
+      __syncthreads();
+      for (int idx = tid; idx < p * m; idx += kThreads) {
+        int s0 = idx % p, j1 = idx / p;
+        T v = T(0);
+        for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * sl[j1 * m + j0];
+        t1[idx] = v;  // [j1][s0]
+      }
+      __syncthreads();
+      for (int idx = tid; idx < p * p; idx += kThreads) {
+        int s0 = idx % p, s1 = idx / p;
+        T v = T(0);
+        for (int j1 = 0; j1 < m; ++j1) v += V1[j1 * p + s1] * t1[j1 * p + s0];
+        t12[idx] = v;  // [s1][s0]
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        int t = tid + q * kThreads;
+        if (t < P) acc[q] += V2[j2 * p + t / (p * p)] * t12[t % (p * p)];
+      }
+    }
+  } else {
+    for (int j1 = 0; j1 < m; ++j1) {
+      __syncthreads();
+      for (int j0 = tid; j0 < m; j0 += kThreads) sl[j0] = ur[(int64_t)(bb[0] * m + j0) + (int64_t)n * (bb[1] * m + j1)];
+      __syncthreads();
+      for (int s0 = tid; s0 < p; s0 += kThreads) {
+        T v = T(0);
+        for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * sl[j0];
+        t1[s0] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        int t = tid + q * kThreads;
+        if (t < P) acc[q] += V1[j1 * p + t / p] * t1[t % p];
+      }
+    }
+  }
+  TW* Wo = W + ((int64_t)box * nrhs + r) * P;
+#pragma unroll
+  for (int q = 0; q < WPT; ++q) {
+    int t = tid + q * kThreads;
+    if (t < P) Wo[t] = store_cast<TW>(acc[q]);
+  }
+}
+
+// Down expansion: f_tau += H_tau x_1 U_1 ... x_d U_d, one block per (box, rhs).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ H, T* __restrict__ f,
+                                                   const T* __restrict__ U, int uniform, int d, int n, int m,
+                                                   int B, int p, int nrhs) {
+  extern __shared__ unsigned char smem_raw[];
+  const int P = (d == 3) ? p * p * p : p * p;
+  T* hs = reinterpret_cast<T*>(smem_raw);  // P
+  T* z = hs + P;                           // p*p   [t1][t0]
+  T* y = z + p * p;                        // m*p   [i1][t0]
+  const int tid = threadIdx.x;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+  int bb[3] = {box % B, (box / B) % B, d == 3 ? box / (B * B) : 0};
+  auto Uk = [&](int k) -> const T* {
+    return uniform ? U : U + ((size_t)k * B + bb[k]) * (size_t)m * p;
+  };
+  const T* U0 = Uk(0);
+  const T* U1 = Uk(1);
+  const T* U2 = d == 3 ? Uk(2) : nullptr;
+  const T* Hb = H + ((int64_t)box * nrhs + r) * P;
+  for (int t = tid; t < P; t += kThreads) hs[t] = Hb[t];
+  T* fr = f + (int64_t)r * N;
+  if (d == 3) {
+    for (int i2 = 0; i2 < m; ++i2) {
+      __syncthreads();
+      for (int idx = tid; idx < p * p; idx += kThreads) {
+        T v = T(0);
+        for (int t2 = 0; t2 < p; ++t2) v += U2[i2 * p + t2] * hs[t2 * p * p + idx];
+        z[idx] = v;  // [t1][t0]
+      }
+      __syncthreads();
+      for (int idx = tid; idx < m * p; idx += kThreads) {
+        int t0 = idx % p, i1 = idx / p;
+        T v = T(0);
+        for (int t1 = 0; t1 < p; ++t1) v += U1[i1 * p + t1] * z[t1 * p + t0];
+        y[idx] = v;  // [i1][t0]
+      }
+      __syncthreads();
+      for (int idx = tid; idx < m * m; idx += kThreads) {
+        int i0 = idx % m, i1 = idx / m;
+        T v = T(0);
+        for (int t0 = 0; t0 < p; ++t0) v += U0[i0 * p + t0] * y[i1 * p + t0];
+        fr[lin3(bb[0] * m + i0, bb[1] * m + i1, bb[2] * m + i2, n)] += v;
+      }
+    }
+  } else {
+    for (int i1 = 0; i1 < m; ++i1) {
+      __syncthreads();
+      for (int t0 = tid; t0 < p; t0 += kThreads) {
+        T v = T(0);
+        for (int t1 = 0; t1 < p; ++t1) v += U1[i1 * p + t1] * hs[t1 * p + t0];
+        z[t0] = v;
+      }
+      __syncthreads();
+      for (int i0 = tid; i0 < m; i0 += kThreads) {
+        T v = T(0);
+        for (int t0 = 0; t0 < p; ++t0) v += U0[i0 * p + t0] * z[t0];
+        fr[(int64_t)(bb[0] * m + i0) + (int64_t)n * (bb[1] * m + i1)] += v;
+      }
+    }
+  }
+}
+
+// Core apply with one stored core per offset (uniform grids), plain VALU
+// version: one block per (target box, rhs chunk), one thread per core row t.
+// G layout: GT = true -> [core][s][t], false -> [core][t][s].
+template <typename TG, typename TW, typename TA, int RC, bool GT>
+__global__ __launch_bounds__(kThreads) void k_core_simple(
+    const TW* __restrict__ W, TA* __restrict__ H, const TG* __restrict__ G, const int64_t* __restrict__ ptr,
+    const int32_t* __restrict__ src, const int32_t* __restrict__ cid, int P, int nrhs) {
+  extern __shared__ unsigned char smem_raw[];
+  TA* ws = reinterpret_cast<TA*>(smem_raw);  // [RC][P]
+  const int tid = threadIdx.x;
+  const int tau = blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  constexpr int TPT = 8;
+  TA acc[TPT][RC];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q)
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[q][r] = TA(0);
+  const int64_t PP = (int64_t)P * P;
+  for (int64_t e = ptr[tau]; e < ptr[tau + 1]; ++e) {
+    const int64_t sg = src[e];
+    const TG* Gc = G + (int64_t)cid[e] * PP;
+    __syncthreads();
+    for (int idx = tid; idx < RC * P; idx += kThreads) {
+      int r = idx / P, s = idx % P;
+      ws[idx] = (r0 + r < nrhs) ? to_acc(W[(sg * nrhs + r0 + r) * P + s]) : TA(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      int t = tid + q * kThreads;
+      if (t >= P) break;
+      for (int s = 0; s < P; ++s) {
+        TA g = to_acc(GT ? Gc[(int64_t)s * P + t] : Gc[(int64_t)t * P + s]);
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[q][r] += g * ws[r * P + s];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    int t = tid + q * kThreads;
+    if (t >= P) break;
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r0 + r < nrhs) H[((int64_t)tau * nrhs + r0 + r) * P + t] = acc[q][r];
+  }
+}
+
+// Core apply on a general tensor grid: G(t, s) = k(xi_t - eta_s) generated on
+// the fly from the Chebyshev points of both boxes (relative to the target
+// box), one block per (target box, rhs chunk).
+template <int KID, typename T, int RC>
+__global__ __launch_bounds__(kThreads) void k_core_tensor(
+    const T* __restrict__ W, T* __restrict__ H, const double* __restrict__ cheb, const int64_t* __restrict__ ptr,
+    const int32_t* __restrict__ src, int d, int p, int B, int nrhs, int pm1) {
+  extern __shared__ unsigned char smem_raw[];
+  T* ws = reinterpret_cast<T*>(smem_raw);  // [RC][P]
+  const int P = (d == 3) ? p * p * p : p * p;
+  T* ce = ws + RC * P;                      // [3][p] source points relative to the target origin
+  const int tid = threadIdx.x;
+  const int tau = blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  int tb[3] = {tau % B, (tau / B) % B, d == 3 ? tau / (B * B) : 0};
+  const double org[3] = {cheb[(0 * B + tb[0]) * p], cheb[(1 * B + tb[1]) * p],
+                         d == 3 ? cheb[(2 * B + tb[2]) * p] : 0.0};
+  constexpr int TPT = 8;
+  T acc[TPT][RC];
+  T xt[TPT][3];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    int t = tid + q * kThreads;
+    int tt[3] = {t % p, (t / p) % p, (d == 3) ? t / (p * p) : 0};
+    for (int l = 0; l < 3; ++l) xt[q][l] = (l < d && t < P) ? (T)(cheb[(l * B + tb[l]) * p + tt[l]] - org[l]) : T(0);
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[q][r] = T(0);
+  }
+  for (int64_t e = ptr[tau]; e < ptr[tau + 1]; ++e) {
+    const int64_t sg = src[e];
+    const int sb[3] = {(int)(sg % B), (int)((sg / B) % B), d == 3 ? (int)(sg / (B * B)) : 0};
+    __syncthreads();
+    for (int idx = tid; idx < RC * P; idx += kThreads) {
+      int r = idx / P, s = idx % P;
+      ws[idx] = (r0 + r < nrhs) ? W[(sg * nrhs + r0 + r) * P + s] : T(0);
+    }
+    for (int idx = tid; idx < 3 * p; idx += kThreads) {
+      int l = idx / p, s = idx % p;
+      ce[idx] = l < d ? (T)(cheb[(l * B + sb[l]) * p + s] - org[l]) : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      int t = tid + q * kThreads;
+      if (t >= P) break;
+      int s = 0;
+      const int nz = (d == 3) ? p : 1;
+      for (int s2 = 0; s2 < nz; ++s2) {
+        T dx2 = (d == 3) ? xt[q][2] - ce[2 * p + s2] : T(0);
+        for (int s1 = 0; s1 < p; ++s1) {
+          T dx1 = xt[q][1] - ce[p + s1];
+          for (int s0 = 0; s0 < p; ++s0, ++s) {
+            T g = kvec<KID, T>(xt[q][0] - ce[s0], dx1, dx2, d, pm1);
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[q][r] += g * ws[r * P + s];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    int t = tid + q * kThreads;
+    if (t >= P) break;
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r0 + r < nrhs) H[((int64_t)tau * nrhs + r0 + r) * P + t] = acc[q][r];
+  }
+}
+
+#define HTLR_DISPATCH_KID(kid, ...)                                              \
+  switch (kid) {                                                                 \
+    case HTLR_K_INV_R: { constexpr int KID = HTLR_K_INV_R; __VA_ARGS__; break; } \
+    case HTLR_K_NEG_LOG: { constexpr int KID = HTLR_K_NEG_LOG; __VA_ARGS__; break; } \
+    case HTLR_K_EXP: { constexpr int KID = HTLR_K_EXP; __VA_ARGS__; break; }     \
+    case HTLR_K_GAUSS: { constexpr int KID = HTLR_K_GAUSS; __VA_ARGS__; break; } \
+    case HTLR_K_POLY_TEST: { constexpr int KID = HTLR_K_POLY_TEST; __VA_ARGS__; break; } \
+    default: fail(HTLR_ERR_INVALID, "unknown kernel");                          \
+  }
+
+#define HTLR_DISPATCH_RC(rc, ...)                                   \
+  switch (rc) {                                                     \
+    case 1: { constexpr int RC = 1; __VA_ARGS__; break; }           \
+    case 4: { constexpr int RC = 4; __VA_ARGS__; break; }           \
+    default: { constexpr int RC = 16; __VA_ARGS__; break; }         \
+  }
+
+constexpr size_t kLdsBudget = 64 * 1024;
+
+// Right-hand sides per block (1, 4 or 16): enough for nrhs, within the LDS budget.
+static int pick_rc(int nrhs, size_t fixed_bytes, size_t per_rc_bytes) {
+  int rc = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 16);
+  while (rc > 1 && fixed_bytes + rc * per_rc_bytes > kLdsBudget) rc = rc == 16 ? 4 : 1;
+  if (fixed_bytes + rc * per_rc_bytes > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "working set exceeds LDS");
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Work buffers
+
+static size_t elem_w(int prec) { return prec == HTLR_FP64 ? 8 : (prec == HTLR_FP32 ? 4 : 2); }
+static size_t elem_a(int prec) { return prec == HTLR_FP64 ? 8 : 4; }
+
+static size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
+  size_t tot = 0;
+  for (const LevelData& lv : A.levels) {
+    if (lv.npairs == 0) continue;
+    size_t cnt = (size_t)lv.nbox * nrhs * A.P;
+    tot += ((cnt * elem_w(prec) + 255) & ~size_t(255)) + ((cnt * elem_a(prec) + 255) & ~size_t(255));
+  }
+  return tot;
+}
+
+static void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
+  Workspace& ws = A.ws;
+  if (ws.nrhs >= nrhs && ws.prec == prec) return;
+  ws.W.clear();
+  ws.H.clear();
+  ws.W.resize(A.L + 1);
+  ws.H.resize(A.L + 1);
+  ws.bytes = 0;
+  for (const LevelData& lv : A.levels) {
+    if (lv.npairs == 0) continue;
+    size_t cnt = (size_t)lv.nbox * nrhs * A.P;
+    ws.W[lv.level].alloc(cnt * elem_w(prec));
+    ws.H[lv.level].alloc(cnt * elem_a(prec));
+    ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes;
+  }
+  ws.nrhs = nrhs;
+  ws.prec = prec;
+}
+
+// ---------------------------------------------------------------------------
+// Driver
+
+template <typename T>
+static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st) {
+  const int d = A.d, p = A.p, P = A.P, n = A.n, pm1 = p - 1;
+  const bool f64 = std::is_same<T, double>::value;
+  const Plan& pl = A.plan;
+  const int m = pl.m[A.L], B = pl.B[A.L];
+  const int M = d == 3 ? m * m * m : m * m;
+  if (M > 4 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "leaf boxes larger than 1024 points");
+  if (P > 8 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "p^d larger than 2048");
+  const T* a = f64 ? (const T*)A.a64.ptr : (const T*)A.a32.ptr;
+  const int64_t nleaf = A.levels[A.L].nbox;
+
+  // near field + diagonal (overwrites f)
+  if (A.uniform) {
+    const bool radial = A.kid != HTLR_K_POLY_TEST;
+    const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
+    const size_t fixed = (radial ? ((A.Tsize + 1) & ~1) : 0) * sizeof(T);
+    const int rc = pick_rc(nrhs, fixed, (size_t)M * sizeof(T));
+    const int nchunk = (nrhs + rc - 1) / rc;
+    size_t sh = fixed + (size_t)M * rc * sizeof(T);
+    HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_near_uniform<KID, T, RC>), dim3(nleaf, nchunk),
+                                                                   dim3(kThreads), sh, st, u, f, a,
+                                                                   A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(),
+                                                                   tab, A.Tsize, d, n, m, B, nrhs, (T)A.h, (T)A.w0,
+                                                                   (T)A.D0, pm1)));
+  } else {
+    const T* D = f64 ? (const T*)A.D64.ptr : (const T*)A.D32.ptr;
+    const T* wd = f64 ? (const T*)A.w64.ptr : (const T*)A.w32.ptr;
+    const int rc = pick_rc(nrhs, 3 * (size_t)m * sizeof(T), (size_t)M * sizeof(T));
+    const int nchunk = (nrhs + rc - 1) / rc;
+    size_t sh = (3 * (size_t)m + (size_t)M * rc) * sizeof(T);
+    HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_near_tensor<KID, T, RC>), dim3(nleaf, nchunk),
+                                                                   dim3(kThreads), sh, st, u, f, a, D,
+                                                                   A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(),
+                                                                   A.x64.as<double>(), wd, d, n, m, B, nrhs, pm1)));
+  }
+  HTLR_HIP(hipGetLastError());
+
+  // far field, level by level
+  for (LevelData& lv : A.levels) {
+    if (lv.npairs == 0) continue;
+    const int l = lv.level, lm = lv.m, lB = lv.B;
+    const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
+    const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
+    T* H = A.ws.H[l].as<T>();
+    size_t sh_up = ((size_t)(d == 3 ? lm * lm : lm) + (size_t)p * lm + (size_t)p * p) * sizeof(T);
+    if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
+    if (prec == HTLR_BF16_CORE) {
+      if constexpr (!std::is_same<T, double>::value) {
+        if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
+        if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
+        uint16_t* W16 = A.ws.W[l].as<uint16_t>();
+        hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, st, u, W16, V,
+                           1, d, n, lm, lB, p, nrhs);
+        HTLR_HIP(hipGetLastError());
+        const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
+        const int nchunk = (nrhs + rc - 1) / rc;
+        size_t sh = (size_t)rc * P * sizeof(float);
+        HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<uint16_t, uint16_t, float, RC, false>),
+                                                dim3(lv.nbox, nchunk), dim3(kThreads), sh, st, W16, H,
+                                                lv.Gm16.as<uint16_t>(), lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
+                                                lv.cid.as<int32_t>(), P, nrhs));
+        HTLR_HIP(hipGetLastError());
+      }
+    } else {
+    T* W = A.ws.W[l].as<T>();
+    hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, st, u, W, V, A.uniform ? 1 : 0, d,
+                       n, lm, lB, p, nrhs);
+    HTLR_HIP(hipGetLastError());
+    if (A.uniform) {
+      const T* G = f64 ? (const T*)lv.G64.ptr : (const T*)lv.G32.ptr;
+      if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
+      const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(T));
+      const int nchunk = (nrhs + rc - 1) / rc;
+      size_t sh = (size_t)rc * P * sizeof(T);
+      HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, true>), dim3(lv.nbox, nchunk), dim3(kThreads),
+                                              sh, st, W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
+                                              lv.cid.as<int32_t>(), P, nrhs));
+    } else {
+      const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T), (size_t)P * sizeof(T));
+      const int nchunk = (nrhs + rc - 1) / rc;
+      size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T);
+      HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_tensor<KID, T, RC>), dim3(lv.nbox, nchunk),
+                                                                     dim3(kThreads), sh, st, W, H, lv.cheb64.as<double>(),
+                                                                     lv.ptr.as<int64_t>(), lv.src.as<int32_t>(), d, p, lB,
+                                                                     nrhs, pm1)));
+    }
+    HTLR_HIP(hipGetLastError());
+    }
+    size_t sh_dn = ((size_t)P + (size_t)p * p + (size_t)lm * p) * sizeof(T);
+    if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
+    hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_dn, st, H, f, U, A.uniform ? 1 : 0, d, n,
+                       lm, lB, p, nrhs);
+    HTLR_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace htlr
+
+using namespace htlr;
+
+extern "C" {
+
+htlr_status htlr_workspace_bytes(htlr_matrix A, int nrhs, htlr_precision prec, size_t* bytes) {
+  if (!A || !bytes || nrhs < 1) { g_last_error = "invalid argument"; return HTLR_ERR_INVALID; }
+  *bytes = workspace_bytes(*A, nrhs, prec);
+  return HTLR_OK;
+}
+
+htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_precision prec,
+                        htlr_vec_dtype vec_dtype, void* stream) {
+  try {
+    g_last_error.clear();
+    if (!A || !u || !f) fail(HTLR_ERR_INVALID, "null argument");
+    if (nrhs < 1 || nrhs > 64) fail(HTLR_ERR_INVALID, "nrhs out of range (1..64)");
+    if (prec != HTLR_FP64 && prec != HTLR_FP32 && prec != HTLR_BF16_CORE) fail(HTLR_ERR_INVALID, "unknown precision");
+    if ((prec == HTLR_FP64) != (vec_dtype == HTLR_VEC_F64))
+      fail(HTLR_ERR_UNSUPPORTED, "FP64 products take f64 vectors, FP32/BF16 products take f32 vectors");
+    if (!(A->precisions & (1 << prec))) fail(HTLR_ERR_UNSUPPORTED, "matrix built without this precision");
+    const size_t esz = vec_dtype == HTLR_VEC_F64 ? 8 : 4;
+    const char* ub = (const char*)u;
+    const char* fb = (const char*)f;
+    const size_t span = (size_t)A->N * nrhs * esz;
+    if (ub < fb + span && fb < ub + span) fail(HTLR_ERR_INVALID, "u and f overlap");
+    int dev = 0;
+    HTLR_HIP(hipGetDevice(&dev));
+    if (dev != A->device) fail(HTLR_ERR_INVALID, "current device differs from the build device");
+    std::lock_guard<std::mutex> lk(A->ws_mu);
+    ensure_workspace(*A, nrhs, prec);
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == HTLR_FP64) run_matvec<double>(*A, (const double*)u, (double*)f, nrhs, prec, st);
+    else run_matvec<float>(*A, (const float*)u, (float*)f, nrhs, prec, st);
+    return HTLR_OK;
+  } catch (const Error& e) {
+    return record(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HTLR_ERR_INVALID;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP product (through the C ABI) against the CPU oracles.
+
+FP64 products must match the FP64 HTLR oracle (O2) to 1e-12 relative
+(2-norm over all compared rows and right-hand sides); FP32 and bfloat16-core
+products are compared with the GPU FP64 product at 1e-5 and 5e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import htlr_workloads as W
+from oracle import dense, geometry, htlr
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+BF16_TOL = 5e-3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _grid(d, n, kind):
+    if kind == "uniform":
+        return geometry.uniform_grid(d, n), None
+    x = W.warped_nodes(n)
+    return geometry.tensor_grid([x] * d), np.concatenate([x] * d)
+
+
+def _gpu_matvec(torch, M, u, prec="fp64"):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ut = torch.tensor(np.asfortranarray(u), dtype=dt, device="cuda")
+    if u.ndim == 2:
+        ut = ut.t().contiguous().t()          # column-major
+    f = M.matvec(ut, prec=prec)
+    torch.cuda.synchronize()
+    return f.cpu().numpy().astype(np.float64)
+
+
+def _build(H, pts, kernel, d, n, p, leaf, a, **kw):
+    return H.htlr_build(pts, kernel, d, n, p, leaf, a=a, **kw)
+
+
+CASES = [
+    # d, n, leaf, p, kernel, grid, nrhs
+    (2, 64, 8, 6, "neg_log", "uniform", 1),       # the 2D workload, full size
+    (2, 32, 4, 5, "inv_r", "uniform", 3),
+    (3, 16, 4, 4, "inv_r", "uniform", 1),
+    (3, 16, 4, 3, "exp", "uniform", 2),
+    (3, 16, 4, 4, "gauss", "uniform", 1),
+    (2, 48, 6, 8, "neg_log", "uniform", 1),       # p > leaf side
+    (2, 24, 3, 4, "exp", "warped", 1),
+    (3, 12, 3, 3, "inv_r", "warped", 2),
+    (3, 16, 4, 4, "poly_test", "uniform", 1),
+    (2, 24, 3, 4, "poly_test", "warped", 1),
+]
+
+
+@pytest.mark.parametrize("d,n,leaf,p,kernel,grid,nrhs", CASES)
+def test_fp64_matches_htlr_oracle(torch, d, n, leaf, p, kernel, grid, nrhs):
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] fp64 parity d={d} n={n} leaf={leaf} p={p} k={kernel} grid={grid} nrhs={nrhs}")
+    g, pts = _grid(d, n, grid)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    rng = np.random.default_rng(d * 1000 + n)
+    u = rng.standard_normal((g.N, nrhs)) if nrhs > 1 else rng.standard_normal(g.N)
+    M = _build(H, pts, kernel, d, n, p, leaf, a)
+    fg = _gpu_matvec(torch, M, u)
+    fo = htlr.HTLR(g, kernel, p, leaf, a).matvec(u)
+    assert _rel(fg, fo) <= FP64_TOL
+    if kernel == "poly_test":
+        assert _rel(fg, dense.matvec(g, kernel, p, a, u)) <= FP64_TOL
+
+
+def test_nothing_admissible_equals_dense(torch):
+    import paper_2508_05958_amd as H
+    _say("[gpu] nothing admissible, 3D n=8 leaf 4")
+    g, _ = _grid(3, 8, "uniform")
+    a = np.ones(g.N)
+    u = np.random.default_rng(0).standard_normal(g.N)
+    M = _build(H, None, "inv_r", 3, 8, 4, 4, a)
+    assert sum(M.info()["adm_pairs"]) == 0
+    assert _rel(_gpu_matvec(torch, M, u), dense.matvec(g, "inv_r", 4, a, u)) <= 1e-13
+
+
+def test_single_leaf_tree(torch):
+    import paper_2508_05958_amd as H
+    _say("[gpu] n == leaf (tree of one node)")
+    g, _ = _grid(2, 8, "uniform")
+    a = np.zeros(g.N)
+    u = np.random.default_rng(1).standard_normal(g.N)
+    M = _build(H, None, "neg_log", 2, 8, 4, 8, a)
+    assert _rel(_gpu_matvec(torch, M, u), dense.matvec(g, "neg_log", 4, a, u)) <= 1e-13
+
+
+@pytest.mark.parametrize("kind,eta2", [("weak", 1.0), ("strong", 3.0)])
+def test_admissibility_variants(torch, kind, eta2):
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] admissibility {kind} eta2={eta2}")
+    d, n, leaf, p = (2, 32, 4, 6) if kind == "weak" else (3, 16, 2, 3)
+    g, _ = _grid(d, n, "uniform")
+    kern = "gauss" if kind == "weak" else "inv_r"
+    a = np.ones(g.N)
+    u = np.random.default_rng(2).standard_normal(g.N)
+    M = _build(H, None, kern, d, n, p, leaf, a, eta2=eta2, admissibility=kind)
+    O = htlr.HTLR(g, kern, p, leaf, a, adm_kind=kind, eta2=eta2)
+    if d == 3:
+        leaves = O.tree.leaves()
+        pick = [leaves[i] for i in (0, 100, 311, 511)]
+        fg = _gpu_matvec(torch, M, u)[O.leaf_rows(pick)]
+        assert _rel(fg, O.matvec(u, pick)) <= FP64_TOL
+    else:
+        assert _rel(_gpu_matvec(torch, M, u), O.matvec(u)) <= FP64_TOL
+
+
+def test_w3d_fp64_sampled(torch):
+    """The 3D FP64 workload at full size (N = 64^3): sampled leaves against
+    O2, sampled rows against the dense product O1."""
+    import paper_2508_05958_amd as H
+    w = W.WORKLOADS["w3d_invr_n64"]
+    _say(f"[gpu] {w.name} full size, sampled")
+    g, _ = _grid(3, w.n, "uniform")
+    a = w.a()
+    u = w.rhs()
+    M = _build(H, None, w.kernel, 3, w.n, w.p, w.leaf, a)
+    fg = _gpu_matvec(torch, M, u)
+    O = htlr.HTLR(g, w.kernel, w.p, w.leaf, a)
+    leaves = O.tree.leaves()
+    pick = [leaves[i] for i in W.sample_leaves(w.seed, len(leaves), 3)]
+    assert _rel(fg[O.leaf_rows(pick)], O.matvec(u, pick)) <= FP64_TOL
+    rows = w.rows(256)
+    assert _rel(fg[rows], dense.matvec(g, w.kernel, w.p, a, u, rows=rows)) <= 1e-6
+
+
+@pytest.mark.parametrize("d,n,leaf,p,kernel,nrhs", [(3, 32, 8, 6, "inv_r", 4), (2, 64, 8, 6, "neg_log", 16),
+                                                     (3, 32, 4, 8, "inv_r", 16)])
+def test_reduced_precision_vs_fp64(torch, d, n, leaf, p, kernel, nrhs):
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] fp32/bf16 vs fp64 d={d} n={n} p={p} nrhs={nrhs}")
+    g, _ = _grid(d, n, "uniform")
+    a = np.ones(g.N)
+    u = np.random.default_rng(3).standard_normal((g.N, nrhs))
+    M = _build(H, None, kernel, d, n, p, leaf, a)
+    f64 = _gpu_matvec(torch, M, u, "fp64")
+    assert _rel(_gpu_matvec(torch, M, u, "fp32"), f64) <= FP32_TOL
+    assert _rel(_gpu_matvec(torch, M, u, "bf16"), f64) <= BF16_TOL
+
+
+def test_multi_rhs_equals_single(torch):
+    import paper_2508_05958_amd as H
+    _say("[gpu] multi-rhs == single-rhs columns")
+    g, _ = _grid(3, 16, "uniform")
+    a = np.ones(g.N)
+    u = np.random.default_rng(4).standard_normal((g.N, 5))
+    M = _build(H, None, "inv_r", 3, 16, 4, 4, a)
+    fm = _gpu_matvec(torch, M, u)
+    for r in range(5):
+        assert _rel(_gpu_matvec(torch, M, u[:, r].copy()), fm[:, r]) <= 1e-14
+
+
+def test_deterministic(torch):
+    import paper_2508_05958_amd as H
+    _say("[gpu] bitwise determinism")
+    g, _ = _grid(3, 32, "uniform")
+    u = np.random.default_rng(5).standard_normal(g.N)
+    M = _build(H, None, "inv_r", 3, 32, 6, 8, np.ones(g.N))
+    assert np.array_equal(_gpu_matvec(torch, M, u), _gpu_matvec(torch, M, u))
+
+
+def test_errors_are_status_codes(torch):
+    import paper_2508_05958_amd as H
+    _say("[gpu] error paths")
+    M = _build(H, None, "inv_r", 3, 16, 4, 4, None)
+    u = torch.zeros(16 ** 3, dtype=torch.float32, device="cuda")
+    with pytest.raises(H.HTLRError) as e:
+        M.matvec(u, prec="fp64")
+    assert e.value.status == -1
+    with pytest.raises(H.HTLRError):
+        H.htlr_build(None, "inv_r", 3, 16, 0, 4)

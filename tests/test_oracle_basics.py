@@ -99,10 +99,7 @@ def test_kernel_values_closed_form():
     assert kernels.evaluate("poly_test", x, y, 1) == 1.0
     # factorisation over dimensions, degree p-1 in each variable
     v = kernels.evaluate("poly_test", x, y, 3)
-    manual = 1.0
-    for l in range(3):
-        manual *= (1 + kernels.POLY_A[l] * x[l] + kernels.POLY_B[l] * y[l]
-                   + kernels.POLY_C[l] * x[l] * y[l]) ** 2
+    manual = (1 - 0.5 * 0.3) ** 2 * (1 - 0.3 * 0.4) ** 2 * 1.0
     assert v == pytest.approx(manual, rel=1e-14)
     # non-symmetric on purpose
     assert kernels.evaluate("poly_test", x, y, 3) != pytest.approx(kernels.evaluate("poly_test", y, x, 3))
@@ -139,7 +136,8 @@ def test_diagonal_constant_kernel_is_cell_volume():
 
 def test_diagonal_polynomial_exact():
     """poly_test with p = 3 is quadratic in each y_l: Gauss-Legendre of order 2
-    already integrates it exactly; compare with the antiderivative."""
+    already integrates it exactly; compare with the antiderivative
+    -(1 + A (x - y))^3 / (3 A)."""
     t = (np.arange(7) + 0.5) / 7
     x = t + 0.05 * np.sin(2 * np.pi * t)
     g = geometry.tensor_grid([x, x, x])
@@ -150,10 +148,10 @@ def test_diagonal_polynomial_exact():
         idx = g.multi_index(lin)
         exact = np.ones(len(lin))
         for l in range(3):
-            al = 1 + kernels.POLY_A[l] * P[:, l]
-            be = kernels.POLY_B[l] + kernels.POLY_C[l] * P[:, l]
+            A = kernels.POLY_A[l]
             lo, hi = g.edges[l][idx[l]], g.edges[l][idx[l] + 1]
-            exact *= ((al + be * hi) ** 3 - (al + be * lo) ** 3) / (3 * be)
+            F = lambda y: -(1 + A * (P[:, l] - y)) ** 3 / (3 * A)
+            exact *= F(hi) - F(lo)
         assert np.allclose(D, exact, rtol=1e-13)
 
 
