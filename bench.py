@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Benchmark of the HTLR matrix-vector product on one MI355X.
+
+A step is one HTLR product f = A u (near field + diagonal, up contraction,
+core apply and down expansion on every level) on a matrix already built and
+resident in HBM, with u resident in HBM.  Prints one JSON line.
+
+Default workload: d = 3, n = 64 (N = 262,144), k = 1/|x-y|, p = 6, leaf 8^3,
+a = 1, FP64, u ~ N(0,1) (seed 1).  A second block reports the N = 128^3,
+16-right-hand-side workload in FP32 and bfloat16-core precision.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HTLR matvec Gpt/s + solves/s at stated err vs FP64; p50/p99 solve latency"
+PEAK = {  # MI355X published peaks (dense), TFLOP/s
+    "fp64_vector": 78.6, "fp32_vector": 157.3, "fp64_mfma": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2500.0,
+}
+HBM_GBS = 8000.0
+KERNEL_LABEL = {"inv_r": "1/|x-y|", "neg_log": "-log|x-y|", "exp": "exp(-|x-y|)", "gauss": "exp(-|x-y|^2/(2d))"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="w3d_invr_n64")
+    ap.add_argument("--prec", default=None, help="fp64 | fp32 | bf16 (default: the workload's)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 128^3 mixed-precision block")
+    ap.add_argument("--cpu-leaves", type=int, default=32)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def algorithmic_work(info, w, nrhs):
+    """Algorithmic flops per launch of each product step (no padding)."""
+    P = w.p ** w.d
+    M = info["leaf_side"] ** w.d
+    work = {"near": 2.0 * info["near_pairs"] * M * M * nrhs}
+    for l, pairs in enumerate(info["adm_pairs"]):
+        if pairs:
+            work[f"core_l{l}"] = 2.0 * pairs * P * P * nrhs
+    return work
+
+
+def peak_for(step, prec):
+    if step == "near":
+        return ("alu", PEAK["fp64_vector"] if prec == "fp64" else PEAK["fp32_vector"])
+    return ("mfma", {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16": PEAK["bf16_mfma"]}[prec])
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2508_05958_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, prec, step, launches):
+    """HBM bytes per launch from committed counter summaries, if they were
+    taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_digest") != source_digest() or step not in t.get("kernels", {}):
+        return None
+    return t["kernels"][step]["hbm_bytes_per_launch"]
+
+
+def run_workload(H, torch, w, prec, steps, warmup, profile=True):
+    a = w.a()
+    t0 = time.time()
+    M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=a)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    info = M.info()
+    u = w.rhs()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ut = torch.tensor(u, dtype=dt, device="cuda")
+    if u.ndim == 2:
+        ut = torch.tensor(u.T.copy(), dtype=dt, device="cuda").t()   # column-major N x nrhs
+    nrhs = 1 if u.ndim == 1 else u.shape[1]
+    f = M.matvec(ut, prec=prec)
+    for _ in range(warmup):
+        M.matvec(ut, f, prec=prec)
+    torch.cuda.synchronize()
+    if profile:
+        M.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        M.matvec(ut, f, prec=prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = M.profile_read() if profile else {}
+    M.profile(False)
+    ms = (t1 - t0) / steps * 1e3
+    return M, info, f, u, nrhs, ms, prof, build_s
+
+
+def roofline(info, w, prec, nrhs, prof, workload):
+    work = algorithmic_work(info, w, nrhs)
+    per = {}
+    for step, (launches, total) in prof.items():
+        avg = total / max(launches, 1)
+        if step in work:
+            bound, peak = peak_for(step, prec)
+            ach = work[step] / (avg * 1e-3) / 1e12
+            per[step] = {"ms": avg, "bound": bound, "achieved_tflops": ach, "peak_tflops": peak,
+                         "frac": ach / peak}
+        else:
+            per[step] = {"ms": avg}
+    dom = max((s for s in per if s in work), key=lambda s: per[s]["ms"])
+    d = per[dom]
+    return {"kernel": dom, "bound": d["bound"], "achieved": round(d["achieved_tflops"], 3), "peak": d["peak_tflops"],
+            "unit": "TFLOP/s", "frac": round(d["frac"], 4),
+            "traffic": traffic_for(workload, prec, dom, prof[dom][0]),
+            "work_per_launch_flop": work[dom], "avg_launch_ms": round(d["ms"], 4)}, per
+
+
+def _oracle_leaf(args):
+    """CPU oracle rows of one leaf box (runs in a worker process)."""
+    wname, leaf_index = args
+    import numpy as np  # noqa: F401
+    import htlr_workloads as W
+    from oracle import geometry, htlr
+    w = W.WORKLOADS[wname]
+    g = geometry.uniform_grid(w.d, w.n) if w.grid == "uniform" else geometry.tensor_grid(w.nodes())
+    O = htlr.HTLR(g, w.kernel, w.p, w.leaf, w.a())
+    nd = O.tree.leaves()[leaf_index]
+    t0 = time.perf_counter()
+    rows = O.matvec(w.rhs(), [nd])
+    dt = time.perf_counter() - t0
+    return leaf_index, O.leaf_rows([nd]), rows, dt
+
+
+def cpu_baseline(w, count, f_gpu):
+    """The CPU FP64 HTLR oracle on a seeded sample of leaf boxes, one leaf per
+    worker process on the host cores; also returns its rows for the error."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import htlr_workloads as W
+    side = w.n
+    while side > w.leaf:
+        side //= 2
+    nleaves = (w.n // side) ** w.d
+    pick = W.sample_leaves(w.seed, nleaves, count)
+    cores = min(len(pick), os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_leaf, [(w.name, int(i)) for i in pick])
+    wall = time.perf_counter() - t0
+    rows = np.concatenate([r[1] for r in res])
+    vals = np.concatenate([r[2].reshape(len(r[1]), -1) for r in res])
+    npts = len(rows) * w.nrhs
+    fg = f_gpu.reshape(w.N, -1)[rows]
+    err = float(np.linalg.norm(fg - vals) / np.linalg.norm(vals))
+    return {"value": npts / wall / 1e9, "unit": "Gpt/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(pick)} seeded leaf boxes ({len(rows)} rows x {w.nrhs} rhs) of {w.name}, "
+                      f"plain NumPy FP64 HTLR (Alg. 4.2), one leaf per process, {wall:.1f} s wall"}, err
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import htlr_workloads as W
+    import paper_2508_05958_amd as H
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = W.WORKLOADS[args.workload]
+    prec = args.prec or ("fp64" if w.nrhs == 1 else "bf16")
+    print(f"[bench] {w.name} {prec}: build + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
+          flush=True)
+    M, info, f, u, nrhs, ms, prof, build_s = run_workload(H, torch, w, prec, args.steps, args.warmup)
+    value = w.N * nrhs / (ms * 1e-3) / 1e9
+    roof, per = roofline(info, w, prec, nrhs, prof, w.name)
+    f_host = f.detach().cpu().numpy()
+    if f_host.ndim == 2:
+        f_host = np.asfortranarray(f_host)
+    out = {
+        "metric": METRIC, "value": round(value, 6), "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-core/f32"}[prec],
+        "data": "synthetic (seeded uniform grid, random u)",
+        "config": {"workload": w.name, "d": w.d, "n": w.n, "N": w.N, "kernel": KERNEL_LABEL.get(w.kernel, w.kernel),
+                   "p": w.p, "leaf": w.leaf, "nrhs": nrhs, "precision": prec, "admissibility": "strong, eta=1",
+                   "parallelism": "1 GPU"},
+        "build_s": round(build_s, 3), "device_bytes": info["device_bytes"],
+        "roofline": roof, "kernels": per,
+    }
+    M.free()
+    del f
+    torch.cuda.empty_cache()
+    if args.copy_probe_mib:
+        x = torch.empty(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * x.numel() * 4
+        del x, y
+    if not args.no_extra:
+        x3 = W.WORKLOADS["w3d_invr_n128_r16"]
+        block = {}
+        print(f"[bench] {x3.name}: fp32 and bf16, 5 timed steps each", file=sys.stderr, flush=True)
+        ref = None
+        for pr in ("fp64", "fp32", "bf16"):
+            M3, info3, f3, u3, nr3, ms3, prof3, b3 = run_workload(H, torch, x3, pr, 2 if pr == "fp64" else 5, 1)
+            fh = f3.detach().double().cpu().numpy()
+            if ref is None:
+                ref = fh
+            err = float(np.linalg.norm(fh - ref) / np.linalg.norm(ref))
+            r3, per3 = roofline(info3, x3, pr, nr3, prof3, x3.name)
+            block[pr] = {"Gpt_s": round(x3.N * nr3 / (ms3 * 1e-3) / 1e9, 5), "ms_per_step": round(ms3, 3),
+                         "rel_err_vs_gpu_fp64": err, "build_s": round(b3, 3), "roofline": r3,
+                         "kernels": {k: round(v["ms"], 3) for k, v in per3.items()}}
+            M3.free()
+            del f3
+            torch.cuda.empty_cache()
+        out["w3d_invr_n128_r16"] = block
+    if not args.no_cpu:
+        print(f"[bench] cpu_baseline: oracle on {args.cpu_leaves} leaves", file=sys.stderr, flush=True)
+        cb, err = cpu_baseline(w, args.cpu_leaves, f_host)
+        out["cpu_baseline"] = cb
+        out["rel_err_vs_oracle_sampled"] = err
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

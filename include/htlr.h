@@ -186,6 +186,21 @@ typedef struct {
 
 htlr_status htlr_info(htlr_matrix A, htlr_info_t* info);
 
+/* Kernel timing of products, for measurement: while enabled, every launch of
+ * htlr_matvec on this handle is bracketed by hipEvents recorded on the
+ * launch stream.  htlr_profile_read synchronises those events and returns,
+ * per step name ("near", "up_l4", "core_l4", "down_l4", ...), the number of
+ * launches and their summed duration in milliseconds since the last reset.
+ * Enabling or disabling clears the record. */
+typedef struct {
+  char name[32];
+  int launches;
+  double total_ms;
+} htlr_profile_entry;
+
+htlr_status htlr_profile_enable(htlr_matrix A, int enable);
+htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, int* count);
+
 /* Releases the handle and all its device memory (synchronises the device). */
 void htlr_free(htlr_matrix A);
 

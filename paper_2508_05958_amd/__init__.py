@@ -56,6 +56,10 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double)]
 
 
+class _ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double)]
+
+
 _lib = None
 _c_dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -86,8 +90,11 @@ def lib() -> ctypes.CDLL:
         L.htlr_plan_pairs.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.htlr_profile_enable.argtypes = [_vp, ctypes.c_int]
+        L.htlr_profile_read.argtypes = [_vp, ctypes.POINTER(_ProfEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("htlr_build", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec", "htlr_solve",
-                     "htlr_info", "htlr_plan_counts", "htlr_plan_pairs"):
+                     "htlr_info", "htlr_plan_counts", "htlr_plan_pairs", "htlr_profile_enable",
+                     "htlr_profile_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -197,6 +204,18 @@ class HTLRMatrix:
         b = ctypes.c_size_t()
         _check(lib().htlr_workspace_bytes(self._h, nrhs, PRECISIONS[prec], ctypes.byref(b)))
         return b.value
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-launch hipEvent timing of products; clears the record."""
+        _check(lib().htlr_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{step name: (launches, total ms)} since the last profile() call."""
+        cnt = ctypes.c_int()
+        _check(lib().htlr_profile_read(self._h, None, 0, ctypes.byref(cnt)))
+        arr = (_ProfEntry * max(cnt.value, 1))()
+        _check(lib().htlr_profile_read(self._h, arr, cnt.value, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
 
     def free(self):
         if getattr(self, "_h", None):

@@ -62,17 +62,15 @@ htlr_status guarded(F&& f) {
 // ---------------------------------------------------------------------------
 // Construction kernels
 
-// One core per offset: G[c][s][t] (t fastest) and the transposed copy
-// Gm[c][t][s] (s fastest) used by the matrix-core product.
+// One core per offset: G[c][t][s] (s fastest).
 template <int KID>
 __global__ void k_core_build(const int* __restrict__ offs, const double* __restrict__ crel, double side,
-                             int d, int p, int P, int pm1, double* __restrict__ G,
-                             double* __restrict__ Gm) {
+                             int d, int p, int P, int pm1, double* __restrict__ G) {
   const int c = blockIdx.y;
   const int64_t PP = (int64_t)P * P;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < PP;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    int s = (int)(idx / P), t = (int)(idx % P);
+    int t = (int)(idx / P), s = (int)(idx % P);
     double dx[3] = {0.0, 0.0, 0.0};
     int tt = t, ss = s;
     for (int l = 0; l < d; ++l) {
@@ -81,9 +79,7 @@ __global__ void k_core_build(const int* __restrict__ offs, const double* __restr
       ss /= p;
       dx[l] = (crel[tl] - crel[sl]) - offs[3 * c + l] * side;
     }
-    double v = kvec<KID, double>(dx[0], dx[1], dx[2], d, pm1);
-    G[c * PP + idx] = v;
-    if (Gm) Gm[c * PP + (int64_t)t * P + s] = v;
+    G[c * PP + idx] = kvec<KID, double>(dx[0], dx[1], dx[2], d, pm1);
   }
 }
 
@@ -329,14 +325,13 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
       const bool want64 = A.precisions & (1 << HTLR_FP64);
       const bool want32 = A.precisions & (1 << HTLR_FP32);
       const bool want16 = A.precisions & (1 << HTLR_BF16_CORE);
-      DevBuf tmp64, tmpm;
-      DevBuf& G64 = want64 ? lv.G64 : tmp64;
-      if (want64) bd.alloc(lv.G64, csz * sizeof(double));
-      if (want32) bd.alloc(lv.G32, csz * sizeof(float));
+      DevBuf tmp64;
+      DevBuf& G64 = want64 ? lv.Gm64 : tmp64;
+      if (want64) bd.alloc(lv.Gm64, csz * sizeof(double));
+      if (want32) bd.alloc(lv.Gm32, csz * sizeof(float));
       if (want16) bd.alloc(lv.Gm16, csz * sizeof(uint16_t));
       if (!bd.dry) {
         if (!want64) tmp64.alloc(csz * sizeof(double));
-        tmpm.alloc(csz * sizeof(double));
         DevBuf doff, dcrel;
         Builder t2{&A, false};
         t2.upload(doff, lv.offsets);
@@ -347,15 +342,13 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
         int bx = (int)std::min<int64_t>((PP + 255) / 256, 1024);
         HTLR_DISPATCH_KID(A.kid, hipLaunchKernelGGL(k_core_build<KID>, dim3(bx, lv.ncore), dim3(256), 0, 0,
                                                     doff.as<int>(), dcrel.as<double>(), m * A.h, d, p, P,
-                                                    pm1, G64.as<double>(), tmpm.as<double>()));
+                                                    pm1, G64.as<double>()));
         HTLR_HIP(hipGetLastError());
         int nb = (int)std::min<int64_t>(((int64_t)csz + 255) / 256, 65535);
-        if (want32)
+        if (want32 || want16)
           hipLaunchKernelGGL(k_downcast, dim3(nb), dim3(256), 0, 0, G64.as<double>(), (int64_t)csz,
-                             lv.G32.as<float>(), (uint16_t*)nullptr);
-        if (want16)
-          hipLaunchKernelGGL(k_downcast, dim3(nb), dim3(256), 0, 0, tmpm.as<double>(), (int64_t)csz,
-                             (float*)nullptr, lv.Gm16.as<uint16_t>());
+                             want32 ? lv.Gm32.as<float>() : (float*)nullptr,
+                             want16 ? lv.Gm16.as<uint16_t>() : (uint16_t*)nullptr);
         HTLR_HIP(hipGetLastError());
         HTLR_HIP(hipDeviceSynchronize());
       }

@@ -1,0 +1,393 @@
+// Core apply on the matrix cores (uniform grids).
+//
+// For one level, H_tau = sum_{sigma in adm(tau)} G_{sigma - tau} W_sigma
+// (Alg. 4.2: H = G x_{[d+1..2d],[1..d]} W, summed over the admissible leaves
+// of a row block).  On a uniform grid the cores depend only on the offset
+// Delta = sigma - tau, and the admissible offsets of a box depend only on its
+// parity class (tau mod 2, which fixes the parent offsets of Def. 2.4) and on
+// the domain boundary.  So a set of boxes of one class shares one list of
+// offsets, and the level becomes an implicit GEMM:
+//
+//   rows    t          (p^d core rows),
+//   columns (tau, r)   (boxes of a tile x right-hand sides),
+//   K       (Delta, s) (offsets of the tile x p^d core columns),
+//
+// with the B operand gathered from W_{tau + Delta}; a column whose source box
+// falls outside the domain reads a zero tensor.  Each workgroup owns a
+// 128 x 128 output tile and accumulates it over the tile's whole K range
+// (owner computes, no atomics, deterministic).  Operands are staged through
+// LDS in 64-byte K slices with double buffering; 4 waves each compute a
+// 64 x 64 sub-tile with 32x32 (bf16, f32) or 16x16 (f64) MFMA instructions.
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <set>
+
+#include "htlr_device.h"
+#include "htlr_handle.h"
+
+namespace htlr {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 128;   // output rows per workgroup
+constexpr int kBN = 128;   // output columns per workgroup
+constexpr int kCB = 64;    // bytes of K per row per stage
+
+template <typename TE> struct AccT { using type = float; };
+template <> struct AccT<double> { using type = double; };
+
+template <typename TE>
+__global__ __launch_bounds__(256) void k_core_mfma(
+    const TE* __restrict__ G, const TE* __restrict__ W, const TE* __restrict__ zero,
+    typename AccT<TE>::type* __restrict__ H, const int32_t* __restrict__ tile_tau,
+    const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
+    int nitems, int ksplit, int64_t part_stride, int P, int nrhs, int NB, int B) {
+  using TA = typename AccT<TE>::type;
+  constexpr int E = 16 / sizeof(TE);      // elements per 16-byte chunk
+  constexpr int KBE = kCB / sizeof(TE);   // K elements per stage
+  constexpr int LDW = KBE + E;            // padded LDS row (80 bytes)
+  __shared__ __align__(16) TE As[2][kBM * LDW];
+  __shared__ __align__(16) TE Bs[2][kBN * LDW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // Work item of this workgroup.  Workgroups are dealt to the 8 XCDs round
+  // robin; consecutive items (one parity class, one row block) go to one XCD
+  // so that the workgroups sharing an L2 stream the same cores.
+  const int per_xcd = (nitems + 7) / 8;
+  const int q = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (q >= nitems) return;
+  const int item = items[q];
+  const int tile = item >> 12;
+  const int m0 = ((item >> 6) & 63) * kBM;
+  const int split = item & 63;
+  const int part = tid & 3;               // 16-byte chunk within a 64-byte row slice
+  const int sr[2] = {tid >> 2, (tid >> 2) + 64};
+
+  // columns staged by this thread: box, rhs, target coordinates
+  int ctau[2], cr[2], cx[2][3];
+  for (int h = 0; h < 2; ++h) {
+    int col = sr[h];
+    int b = col / nrhs;
+    cr[h] = col % nrhs;
+    ctau[h] = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
+    int t = ctau[h] < 0 ? 0 : ctau[h];
+    cx[h][0] = t % B;
+    cx[h][1] = (t / B) % B;
+    cx[h][2] = t / (B * B);
+  }
+
+  int64_t e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+  {
+    const int64_t chunk = (e1 - e0 + ksplit - 1) / ksplit;
+    const int64_t lo = e0 + split * chunk;
+    e1 = lo + chunk < e1 ? lo + chunk : e1;
+    e0 = lo < e1 ? lo : e1;
+  }
+  H += split * part_stride;   // partial sums of split > 0 go to separate buffers
+  const int ksteps = (P + KBE - 1) / KBE;
+  const int64_t nstage = (e1 - e0) * ksteps;
+  const int64_t PP = (int64_t)P * P;
+
+  const TE* gA = G;
+  const TE* gB[2] = {zero, zero};
+  uint4 ra[2], rb[2];
+  const uint4 z4 = make_uint4(0, 0, 0, 0);
+
+  auto set_delta = [&](int64_t e) {
+    int4 o = tile_off[e];
+    gA = G + (int64_t)o.x * PP;
+    for (int h = 0; h < 2; ++h) {
+      int sx = cx[h][0] + o.y, sy = cx[h][1] + o.z, sz = cx[h][2] + o.w;
+      bool ok = ctau[h] >= 0 && sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B;
+      int64_t sg = (int64_t)sx + (int64_t)B * (sy + (int64_t)B * sz);
+      gB[h] = ok ? W + (sg * nrhs + cr[h]) * P : zero;
+    }
+  };
+  auto gload = [&](int k0) {
+    const int k = k0 + part * E;
+    const bool kin = k < P;
+    for (int h = 0; h < 2; ++h) {
+      const int row = m0 + sr[h];
+      ra[h] = (kin && row < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)row * P + k) : z4;
+      rb[h] = kin ? *reinterpret_cast<const uint4*>(gB[h] + k) : z4;
+    }
+  };
+  auto sstore = [&](int buf) {
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<uint4*>(&As[buf][sr[h] * LDW + part * E]) = ra[h];
+      *reinterpret_cast<uint4*>(&Bs[buf][sr[h] * LDW + part * E]) = rb[h];
+    }
+  };
+
+  const int wm = wv >> 1, wn = wv & 1;
+  constexpr bool k16 = std::is_same<TE, double>::value;   // 16x16 tiles for f64
+  constexpr int TI = k16 ? 4 : 2;                          // sub-tiles per wave per dim
+  using AccV = typename std::conditional<k16, f64x4, f32x16>::type;
+  AccV acc[TI][TI];
+  for (int i = 0; i < TI; ++i)
+    for (int j = 0; j < TI; ++j) acc[i][j] = AccV{};
+
+  auto compute = [&](int buf) {
+    const TE* Asb = As[buf];
+    const TE* Bsb = Bs[buf];
+    if constexpr (std::is_same<TE, uint16_t>::value) {
+      for (int kk = 0; kk < KBE; kk += 16) {
+        bf16x8 a[2], b[2];
+        for (int i = 0; i < 2; ++i)
+          a[i] = *reinterpret_cast<const bf16x8*>(&Asb[(wm * 64 + i * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+        for (int j = 0; j < 2; ++j)
+          b[j] = *reinterpret_cast<const bf16x8*>(&Bsb[(wn * 64 + j * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else if constexpr (std::is_same<TE, float>::value) {
+      for (int kk = 0; kk < KBE; kk += 2) {
+        float a[2], b[2];
+        for (int i = 0; i < 2; ++i) a[i] = Asb[(wm * 64 + i * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
+        for (int j = 0; j < 2; ++j) b[j] = Bsb[(wn * 64 + j * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      for (int kk = 0; kk < KBE; kk += 4) {
+        double a[4], b[4];
+        for (int i = 0; i < 4; ++i) a[i] = Asb[(wm * 64 + i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
+        for (int j = 0; j < 4; ++j) b[j] = Bsb[(wn * 64 + j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+
+  if (nstage > 0) {
+    set_delta(e0);
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    int64_t e = e0;
+    int ks = 0;
+    for (int64_t st = 0; st < nstage; ++st) {
+      const int cur = (int)(st & 1);
+      int64_t en = e;
+      int ksn = ks + 1;
+      if (ksn == ksteps) { ksn = 0; ++en; }
+      const bool more = st + 1 < nstage;
+      if (more) {
+        if (ksn == 0) set_delta(en);
+        gload(ksn * KBE);
+      }
+      compute(cur);
+      if (more) sstore(cur ^ 1);
+      __syncthreads();
+      e = en;
+      ks = ksn;
+    }
+  }
+
+  // write the owned output tile
+  for (int i = 0; i < TI; ++i)
+    for (int j = 0; j < TI; ++j) {
+      if constexpr (k16) {
+        const int col = wn * 64 + j * 16 + (lane & 15);
+        const int b = col / nrhs, r = col % nrhs;
+        const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
+        if (t < 0) continue;
+        TA* Ho = H + ((int64_t)t * nrhs + r) * P;
+        for (int v = 0; v < 4; ++v) {
+          // f64 16x16x4 accumulator: register v holds row lane/16 + 4 v
+          const int row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
+          if (row < P) Ho[row] = acc[i][j][v];
+        }
+      } else {
+        const int col = wn * 64 + j * 32 + (lane & 31);
+        const int b = col / nrhs, r = col % nrhs;
+        const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
+        if (t < 0) continue;
+        TA* Ho = H + ((int64_t)t * nrhs + r) * P;
+        for (int v = 0; v < 16; ++v) {
+          const int row = m0 + wm * 64 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+          if (row < P) Ho[row] = acc[i][j][v];
+        }
+      }
+    }
+}
+
+inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t m = 0;
+  for (int b = 0; b < 21; ++b)
+    m |= ((uint64_t)((x >> b) & 1) << (3 * b)) | ((uint64_t)((y >> b) & 1) << (3 * b + 1)) |
+         ((uint64_t)((z >> b) & 1) << (3 * b + 2));
+  return m;
+}
+
+}  // namespace
+
+// Whether the matrix-core path serves this matrix and precision.
+bool core_mfma_ok(const htlr_matrix_impl& A, int prec) {
+  if (!A.uniform || A.P < 64) return false;
+  const int E = prec == HTLR_FP64 ? 2 : (prec == HTLR_FP32 ? 4 : 8);
+  return A.P % E == 0;
+}
+
+// Work lists for tiles of nb boxes of one parity class, built on first use.
+static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
+  for (auto& t : lv.tiles)
+    if (t.nb == nb) return t;
+  const int d = A.d, B = lv.B;
+  const Csr& cs = A.plan.adm[lv.level];
+  std::vector<int32_t> tau;
+  std::vector<int64_t> ptr{0};
+  std::vector<int4> off;
+  // core id per offset, from the CSR entries of this level
+  std::map<std::array<int, 3>, int> cid;
+  for (int c = 0; c < lv.ncore; ++c)
+    cid[{lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]}] = c;
+  const int ncls = 1 << d;
+  std::vector<int64_t> class_start{0};
+  int64_t maxlist = 0;
+  for (int cls = 0; cls < ncls; ++cls) {
+    std::vector<std::pair<uint64_t, int32_t>> boxes;
+    for (int64_t t = 0; t < lv.nbox; ++t) {
+      int x = (int)(t % B), y = (int)((t / B) % B), z = (int)(t / ((int64_t)B * B));
+      int c = (x & 1) | ((y & 1) << 1) | (d == 3 ? ((z & 1) << 2) : 0);
+      if (c != cls) continue;
+      boxes.push_back({morton3(x >> 1, y >> 1, z >> 1), (int32_t)t});
+    }
+    std::sort(boxes.begin(), boxes.end());
+    for (size_t s = 0; s < boxes.size(); s += nb) {
+      std::set<std::array<int, 3>> offs;
+      std::vector<int32_t> members;
+      for (size_t q = s; q < std::min(boxes.size(), s + (size_t)nb); ++q) {
+        int64_t t = boxes[q].second;
+        members.push_back((int32_t)t);
+        int tx = (int)(t % B), ty = (int)((t / B) % B), tz = (int)(t / ((int64_t)B * B));
+        for (int64_t e = cs.ptr[t]; e < cs.ptr[t + 1]; ++e) {
+          int64_t sg = cs.src[e];
+          offs.insert({(int)(sg % B) - tx, (int)((sg / B) % B) - ty, (int)(sg / ((int64_t)B * B)) - tz});
+        }
+      }
+      // every member's own list must equal the tile list restricted to the domain
+      for (int32_t t : members) {
+        int tx = t % B, ty = (t / B) % B, tz = t / (B * B);
+        int64_t inside = 0;
+        for (auto& o : offs) {
+          int sx = tx + o[0], sy = ty + o[1], sz = tz + o[2];
+          if (sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B) ++inside;
+        }
+        if (inside != cs.ptr[t + 1] - cs.ptr[t])
+          fail(HTLR_ERR_UNSUPPORTED, "admissible offsets differ inside a parity class");
+      }
+      for (int q = 0; q < nb; ++q) tau.push_back(q < (int)members.size() ? members[q] : -1);
+      for (auto& o : offs) off.push_back(make_int4(cid.at(o), o[0], o[1], o[2]));
+      ptr.push_back((int64_t)off.size());
+      maxlist = std::max<int64_t>(maxlist, (int64_t)offs.size());
+    }
+    class_start.push_back((int64_t)ptr.size() - 1);
+  }
+  lv.tiles.emplace_back();
+  LevelData::Tiles& T = lv.tiles.back();
+  T.nb = nb;
+  T.ntile = (int64_t)ptr.size() - 1;
+  T.class_start = class_start;
+  T.maxlist = maxlist;
+  T.tau.alloc(tau.size() * sizeof(int32_t));
+  T.ptr.alloc(ptr.size() * sizeof(int64_t));
+  T.off.alloc(std::max<size_t>(off.size(), 1) * sizeof(int4));
+  HTLR_HIP(hipMemcpy(T.tau.ptr, tau.data(), tau.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HTLR_HIP(hipMemcpy(T.ptr.ptr, ptr.data(), ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  if (!off.empty()) HTLR_HIP(hipMemcpy(T.off.ptr, off.data(), off.size() * sizeof(int4), hipMemcpyHostToDevice));
+  A.device_bytes += T.tau.bytes + T.ptr.bytes + T.off.bytes;
+  return T;
+}
+
+int core_mfma_nb(int nrhs) {
+  int nb = 1;
+  while (nb * 2 * nrhs <= kBN) nb *= 2;
+  return nb;
+}
+
+// Sums the K-split partial results in a fixed order: H = sum_s part_s.
+template <typename TA>
+__global__ void k_reduce_parts(const TA* __restrict__ parts, TA* __restrict__ H, int64_t n, int ksplit,
+                               int64_t stride) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    TA v = parts[i];
+    for (int s = 1; s < ksplit; ++s) v += parts[s * stride + i];
+    H[i] = v;
+  }
+}
+
+// Number of K splits that gives the level enough workgroups to fill the GPU.
+static int pick_ksplit(int64_t base_wgs, int64_t max_list) {
+  int ks = 1;
+  while (ks < 64 && base_wgs * ks < 2048 && max_list / (ks * 2) >= 4) ks *= 2;
+  return ks;
+}
+
+void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
+                      int nrhs, hipStream_t st, DevBuf& parts) {
+  if (nrhs > kBN) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
+  const int nb = core_mfma_nb(nrhs);
+  LevelData::Tiles& T = tiles_for(A, lv, nb);
+  if (T.ntile == 0) return;
+  const int nmb = (A.P + kBM - 1) / kBM;
+  const int ks = pick_ksplit(T.ntile * nmb, T.maxlist);
+  if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
+  // work items ordered (class, row block, split, tile)
+  if (T.items_ks != ks) {
+    std::vector<int32_t> items;
+    for (size_t c = 0; c + 1 < T.class_start.size(); ++c)
+      for (int mb = 0; mb < nmb; ++mb)
+        for (int s = 0; s < ks; ++s)
+          for (int64_t t = T.class_start[c]; t < T.class_start[c + 1]; ++t)
+            items.push_back((int32_t)((t << 12) | (mb << 6) | s));
+    T.items.alloc(items.size() * sizeof(int32_t));
+    HTLR_HIP(hipMemcpy(T.items.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    T.nitems = (int)items.size();
+    T.items_ks = ks;
+  }
+  const size_t esz = prec == HTLR_FP64 ? 8 : 4;
+  const int64_t helems = lv.nbox * (int64_t)nrhs * A.P;
+  void* Hout = H;
+  if (ks > 1) {
+    const size_t need = (size_t)helems * ks * esz;
+    if (parts.bytes < need) parts.alloc(need);
+    Hout = parts.ptr;
+  }
+  const unsigned nwg = (unsigned)(((T.nitems + 7) / 8) * 8);
+  const int32_t* tau = T.tau.as<int32_t>();
+  const int64_t* ptr = T.ptr.as<int64_t>();
+  const int4* off = T.off.as<int4>();
+  const int32_t* items = T.items.as<int32_t>();
+  if (prec == HTLR_BF16_CORE)
+    hipLaunchKernelGGL(k_core_mfma<uint16_t>, dim3(nwg), dim3(256), 0, st, lv.Gm16.as<uint16_t>(), (const uint16_t*)W,
+                       (const uint16_t*)zero, (float*)Hout, tau, ptr, off, items, T.nitems, ks, helems, A.P, nrhs, nb,
+                       lv.B);
+  else if (prec == HTLR_FP32)
+    hipLaunchKernelGGL(k_core_mfma<float>, dim3(nwg), dim3(256), 0, st, lv.Gm32.as<float>(), (const float*)W,
+                       (const float*)zero, (float*)Hout, tau, ptr, off, items, T.nitems, ks, helems, A.P, nrhs, nb,
+                       lv.B);
+  else
+    hipLaunchKernelGGL(k_core_mfma<double>, dim3(nwg), dim3(256), 0, st, lv.Gm64.as<double>(), (const double*)W,
+                       (const double*)zero, (double*)Hout, tau, ptr, off, items, T.nitems, ks, helems, A.P, nrhs, nb,
+                       lv.B);
+  HTLR_HIP(hipGetLastError());
+  if (ks > 1) {
+    const int blocks = (int)std::min<int64_t>((helems + 255) / 256, 4096);
+    if (prec == HTLR_FP64)
+      hipLaunchKernelGGL(k_reduce_parts<double>, dim3(blocks), dim3(256), 0, st, (const double*)parts.ptr, (double*)H,
+                         helems, ks, helems);
+    else
+      hipLaunchKernelGGL(k_reduce_parts<float>, dim3(blocks), dim3(256), 0, st, (const float*)parts.ptr, (float*)H,
+                         helems, ks, helems);
+    HTLR_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace htlr

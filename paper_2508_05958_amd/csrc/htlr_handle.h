@@ -56,10 +56,20 @@ struct LevelData {
   DevBuf cheb64, cheb32;             // tensor grids: Chebyshev points [d][B][p]
   int ncore = 0;                     // uniform grids: one core per offset
   std::vector<int> offsets;          // 3 ints per core: sigma - tau in boxes
-  DevBuf G64, G32, G16;              // cores, layout [core][s][t] (t fastest)
-  DevBuf Gm16, Gm32, Gm64;           // cores for the matrix-core kernel, layout [core][t][s]
-  DevBuf tile_ptr, tile_list;        // matrix-core kernel work lists (uniform)
-  int ntile_cls = 0;                 // tiles per parity class
+  DevBuf Gm16, Gm32, Gm64;           // cores, layout [core][t][s] (s fastest)
+  // matrix-core kernel work lists, per number of boxes per tile (uniform grids)
+  struct Tiles {
+    int nb = 0;
+    int64_t ntile = 0;
+    DevBuf tau;                      // [ntile][nb] target boxes (-1 = empty slot)
+    DevBuf ptr;                      // [ntile + 1] into off
+    DevBuf off;                      // int4 (core id, offset x, y, z) per entry
+    std::vector<int64_t> class_start;  // first tile of each parity class
+    int64_t maxlist = 0;             // longest offset list of a tile
+    DevBuf items;                    // work items (tile << 12 | row block << 6 | split)
+    int nitems = 0, items_ks = 0;
+  };
+  std::vector<Tiles> tiles;
 };
 
 struct Workspace {
@@ -67,7 +77,30 @@ struct Workspace {
   int prec = -1;
   std::vector<DevBuf> W, H, W16;     // per level
   DevBuf zero;                       // a zero source tensor (matrix-core kernel)
+  DevBuf parts;                      // K-split partial sums (matrix-core kernel)
   size_t bytes = 0;
+};
+
+// hipEvent pairs around product launches, for measurement.
+struct Profiler {
+  bool on = false;
+  struct Rec { std::string name; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    HTLR_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void clear() {
+    for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+    recs.clear();
+  }
+  ~Profiler() {
+    clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 struct htlr_matrix_impl {
@@ -90,7 +123,12 @@ struct htlr_matrix_impl {
   size_t device_bytes = 0;
   std::mutex ws_mu;
   Workspace ws;
+  Profiler prof;
 };
+
+bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
+void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
+                      int nrhs, hipStream_t st, DevBuf& parts);
 
 }  // namespace htlr
 

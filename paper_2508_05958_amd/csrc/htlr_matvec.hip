@@ -120,6 +120,129 @@ __global__ __launch_bounds__(kThreads) void k_near_uniform(
   }
 }
 
+// Near field + diagonal, uniform 3D grid with leaves of side m <= 8, one
+// wave per (target leaf, rhs chunk).  Each lane owns one row of targets
+// (i1, i2) and all m targets i0 along x.  For a source row (j1, j2) the
+// m x m block between the target and source rows depends only on i0 - j0
+// (the grid is uniform), so the 2m-1 kernel values are read once and reused
+// for m*m*RC FMAs.
+// With NW waves per leaf, wave w takes every NW-th source box and the
+// partial sums are added in wave order through LDS.
+template <int KID, typename T, int RC, int NW>
+__global__ __launch_bounds__(64 * NW) void k_near_rows(
+    const T* __restrict__ u, T* __restrict__ f, const T* __restrict__ a, const int64_t* __restrict__ nptr,
+    const int32_t* __restrict__ nsrc, const T* __restrict__ table, int tsize, int n, int m, int B, int nrhs, T h,
+    T w0, T D0, int pm1) {
+  constexpr int MM = 8;
+  extern __shared__ unsigned char smem_raw[];
+  T* tab = reinterpret_cast<T*>(smem_raw);
+  constexpr bool radial = KID != HTLR_K_POLY_TEST;
+  const int M = m * m * m;
+  const int wv = threadIdx.x >> 6;
+  T* us_all = tab + (radial ? ((tsize + 1) & ~1) : 0);  // NW x [MM*64][RC], also the reduction buffer
+  T* us = us_all + (size_t)wv * MM * 64 * RC;            // this wave's [M][RC]
+  const int lane = threadIdx.x & 63;
+  const int tau = blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  const int64_t N = (int64_t)n * n * n;
+  const int tb0 = tau % B, tb1 = (tau / B) % B, tb2 = tau / (B * B);
+  if (radial)
+    for (int s = threadIdx.x; s < tsize; s += 64 * NW) tab[s] = table[s];
+  const bool active = lane < m * m;
+  const int i1 = lane % m, i2 = lane / m;
+  const int I1 = tb1 * m + i1, I2 = tb2 * m + i2;
+  T acc[MM][RC];
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[i][r] = T(0);
+  const int64_t ebeg = nptr[tau], eend = nptr[tau + 1];
+  for (int64_t e0 = ebeg; e0 < eend; e0 += NW) {
+    const int64_t e = e0 + wv;
+    const bool have = e < eend;
+    const int sg = have ? nsrc[e] : 0;
+    const int sb0 = sg % B, sb1 = (sg / B) % B, sb2 = sg / (B * B);
+    __syncthreads();
+    for (int idx = lane; have && idx < M * RC; idx += 64) {
+      const int j = idx % M, r = idx / M;
+      const int j0 = j % m, j1 = (j / m) % m, j2 = j / (m * m);
+      us[j * RC + r] = (r0 + r < nrhs)
+                           ? u[(int64_t)(r0 + r) * N + lin3(sb0 * m + j0, sb1 * m + j1, sb2 * m + j2, n)]
+                           : T(0);
+    }
+    __syncthreads();
+    if (!active || !have) continue;
+    const int D = (tb0 - sb0) * m;   // I0 - J0 = D + (i0 - j0)
+    for (int j2 = 0; j2 < m; ++j2) {
+      const int d2 = I2 - (sb2 * m + j2);
+      for (int j1 = 0; j1 < m; ++j1) {
+        const int d1 = I1 - (sb1 * m + j1);
+        T tv[2 * MM - 1];
+        if constexpr (radial) {
+          const int base = d1 * d1 + d2 * d2;
+#pragma unroll
+          for (int k = 0; k < 2 * MM - 1; ++k) {
+            const int dl = k - (MM - 1);
+            const int dd = D + dl;
+            tv[k] = (dl > -m && dl < m) ? tab[base + dd * dd] : T(0);
+          }
+        } else {
+          const T f12 = w0 * ipow(T(1) + T(kPolyADev[1]) * (h * d1), pm1) * ipow(T(1) + T(kPolyADev[2]) * (h * d2), pm1);
+#pragma unroll
+          for (int k = 0; k < 2 * MM - 1; ++k) {
+            const int dl = k - (MM - 1);
+            const int dd = D + dl;
+            const bool in = dl > -m && dl < m;
+            const bool self = dd == 0 && d1 == 0 && d2 == 0;
+            tv[k] = !in ? T(0) : (self ? D0 : f12 * ipow(T(1) + T(kPolyADev[0]) * (h * dd), pm1));
+          }
+        }
+        const T* ur = us + (size_t)(m * j1 + m * m * j2) * RC;
+#pragma unroll
+        for (int j0 = 0; j0 < MM; ++j0) {
+          if (j0 >= m) break;
+          T uv[RC];
+#pragma unroll
+          for (int r = 0; r < RC; ++r) uv[r] = ur[j0 * RC + r];
+#pragma unroll
+          for (int i0 = 0; i0 < MM; ++i0) {
+            const T t = tv[i0 - j0 + MM - 1];
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[i0][r] += t * uv[r];
+          }
+        }
+      }
+    }
+  }
+  if constexpr (NW > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int i0 = 0; i0 < MM; ++i0)
+#pragma unroll
+      for (int r = 0; r < RC; ++r) us[(i0 * RC + r) * 64 + lane] = acc[i0][r];
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int i0 = 0; i0 < MM; ++i0)
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        T v = T(0);
+        for (int w = 0; w < NW; ++w) v += us_all[(size_t)w * MM * 64 * RC + (i0 * RC + r) * 64 + lane];
+        acc[i0][r] = v;
+      }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int i0 = 0; i0 < MM; ++i0) {
+    if (i0 >= m) break;
+    const int64_t g = lin3(tb0 * m + i0, I1, I2, n);
+    const T ai = a[g];
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r0 + r < nrhs) f[(int64_t)(r0 + r) * N + g] = acc[i0][r] + ai * u[(int64_t)(r0 + r) * N + g];
+  }
+}
+
 // Near field + diagonal on a general tensor grid: kernel values evaluated from
 // coordinates relative to the target box, weights |Omega_j| and per-point
 // diagonal integrals D_i.
@@ -528,12 +651,35 @@ static void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
     ws.H[lv.level].alloc(cnt * elem_a(prec));
     ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes;
   }
+  ws.zero.alloc((size_t)A.P * sizeof(double));
+  HTLR_HIP(hipMemset(ws.zero.ptr, 0, ws.zero.bytes));
+  ws.bytes += ws.zero.bytes;
   ws.nrhs = nrhs;
   ws.prec = prec;
 }
 
 // ---------------------------------------------------------------------------
 // Driver
+
+// Brackets one launch with events when the handle's profiler is on.
+struct ProfScope {
+  Profiler& p;
+  hipStream_t st;
+  bool on;
+  Profiler::Rec rec;
+  ProfScope(htlr_matrix_impl& A, const char* name, int level, hipStream_t s) : p(A.prof), st(s), on(A.prof.on) {
+    if (!on) return;
+    rec.name = level >= 0 ? std::string(name) + "_l" + std::to_string(level) : std::string(name);
+    rec.a = p.get();
+    rec.b = p.get();
+    HTLR_HIP(hipEventRecord(rec.a, st));
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.b, st);
+    p.recs.push_back(rec);
+  }
+};
 
 template <typename T>
 static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st) {
@@ -548,7 +694,43 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   const int64_t nleaf = A.levels[A.L].nbox;
 
   // near field + diagonal (overwrites f)
-  if (A.uniform) {
+  {
+  ProfScope ps(A, "near", -1, st);
+  if (A.uniform && d == 3 && m <= 8) {
+    const bool radial = A.kid != HTLR_K_POLY_TEST;
+    const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
+    const size_t fixed = (radial ? ((A.Tsize + 1) & ~1) : 0) * sizeof(T);
+    int rc = f64 ? (nrhs <= 1 ? 1 : (nrhs <= 2 ? 2 : 4)) : (nrhs <= 1 ? 1 : (nrhs <= 2 ? 2 : (nrhs <= 4 ? 4 : 8)));
+    const size_t per_wave = (size_t)8 * 64 * sizeof(T);   // [MM*64] x rc
+    while (rc > 1 && fixed + per_wave * rc > kLdsBudget) rc /= 2;
+    const int nchunk = (nrhs + rc - 1) / rc;
+    // waves per leaf: enough waves to fill the GPU, within the LDS budget
+    int nw = 1;
+    while (nw < 4 && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+    const size_t sh = fixed + per_wave * rc * nw;
+    if (sh > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "near-field working set exceeds LDS");
+#define HTLR_NEAR_ROWS(RCV, NWV)                                                                                  \
+  HTLR_DISPATCH_KID(A.kid, hipLaunchKernelGGL((k_near_rows<KID, T, RCV, NWV>), dim3(nleaf, nchunk), dim3(64 * NWV), sh, \
+                                              st, u, f, a, A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), tab,   \
+                                              A.Tsize, n, m, B, nrhs, (T)A.h, (T)A.w0, (T)A.D0, pm1))
+#define HTLR_NEAR_NW(RCV)                                  \
+  switch (nw) {                                            \
+    case 1: HTLR_NEAR_ROWS(RCV, 1); break;                 \
+    case 2: HTLR_NEAR_ROWS(RCV, 2); break;                 \
+    default: HTLR_NEAR_ROWS(RCV, 4); break;                \
+  }
+    switch (rc) {
+      case 1: HTLR_NEAR_NW(1); break;
+      case 2: HTLR_NEAR_NW(2); break;
+      case 4: HTLR_NEAR_NW(4); break;
+      default:
+        if constexpr (!std::is_same<T, double>::value) { HTLR_NEAR_NW(8); }
+        else fail(HTLR_ERR_INVALID, "near-field chunk size");
+        break;
+    }
+#undef HTLR_NEAR_NW
+#undef HTLR_NEAR_ROWS
+  } else if (A.uniform) {
     const bool radial = A.kid != HTLR_K_POLY_TEST;
     const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
     const size_t fixed = (radial ? ((A.Tsize + 1) & ~1) : 0) * sizeof(T);
@@ -572,6 +754,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
                                                                    A.x64.as<double>(), wd, d, n, m, B, nrhs, pm1)));
   }
   HTLR_HIP(hipGetLastError());
+  }
 
   // far field, level by level
   for (LevelData& lv : A.levels) {
@@ -587,9 +770,14 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
         if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
         if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
         uint16_t* W16 = A.ws.W[l].as<uint16_t>();
+        { ProfScope ps(A, "up", l, st);
         hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, st, u, W16, V,
                            1, d, n, lm, lB, p, nrhs);
-        HTLR_HIP(hipGetLastError());
+        HTLR_HIP(hipGetLastError()); }
+        ProfScope ps(A, "core", l, st);
+        if (core_mfma_ok(A, prec)) {
+          launch_core_mfma(A, lv, prec, W16, H, A.ws.zero.ptr, nrhs, st, A.ws.parts);
+        } else {
         const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
         const int nchunk = (nrhs + rc - 1) / rc;
         size_t sh = (size_t)rc * P * sizeof(float);
@@ -598,19 +786,24 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
                                                 lv.Gm16.as<uint16_t>(), lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
                                                 lv.cid.as<int32_t>(), P, nrhs));
         HTLR_HIP(hipGetLastError());
+        }
       }
     } else {
     T* W = A.ws.W[l].as<T>();
+    { ProfScope ps(A, "up", l, st);
     hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, st, u, W, V, A.uniform ? 1 : 0, d,
                        n, lm, lB, p, nrhs);
-    HTLR_HIP(hipGetLastError());
-    if (A.uniform) {
-      const T* G = f64 ? (const T*)lv.G64.ptr : (const T*)lv.G32.ptr;
+    HTLR_HIP(hipGetLastError()); }
+    ProfScope ps(A, "core", l, st);
+    if (A.uniform && core_mfma_ok(A, prec)) {
+      launch_core_mfma(A, lv, prec, W, H, A.ws.zero.ptr, nrhs, st, A.ws.parts);
+    } else if (A.uniform) {
+      const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
       if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
       const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(T));
       const int nchunk = (nrhs + rc - 1) / rc;
       size_t sh = (size_t)rc * P * sizeof(T);
-      HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, true>), dim3(lv.nbox, nchunk), dim3(kThreads),
+      HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, false>), dim3(lv.nbox, nchunk), dim3(kThreads),
                                               sh, st, W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
                                               lv.cid.as<int32_t>(), P, nrhs));
     } else {
@@ -626,6 +819,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     }
     size_t sh_dn = ((size_t)P + (size_t)p * p + (size_t)lm * p) * sizeof(T);
     if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
+    ProfScope ps(A, "down", l, st);
     hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_dn, st, H, f, U, A.uniform ? 1 : 0, d, n,
                        lm, lB, p, nrhs);
     HTLR_HIP(hipGetLastError());
@@ -673,6 +867,43 @@ htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_pr
   } catch (const std::exception& e) {
     g_last_error = e.what();
     return HTLR_ERR_INVALID;
+  }
+}
+
+htlr_status htlr_profile_enable(htlr_matrix A, int enable) {
+  if (!A) { g_last_error = "null handle"; return HTLR_ERR_INVALID; }
+  std::lock_guard<std::mutex> lk(A->ws_mu);
+  A->prof.clear();
+  A->prof.on = enable != 0;
+  return HTLR_OK;
+}
+
+htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, int* count) {
+  if (!A || !count) { g_last_error = "null argument"; return HTLR_ERR_INVALID; }
+  try {
+    std::lock_guard<std::mutex> lk(A->ws_mu);
+    std::vector<std::string> names;
+    std::vector<double> tot;
+    std::vector<int> cnt;
+    for (auto& r : A->prof.recs) {
+      HTLR_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HTLR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      size_t k = std::find(names.begin(), names.end(), r.name) - names.begin();
+      if (k == names.size()) { names.push_back(r.name); tot.push_back(0.0); cnt.push_back(0); }
+      tot[k] += ms;
+      cnt[k] += 1;
+    }
+    *count = (int)names.size();
+    for (int i = 0; i < (int)names.size() && i < cap && out; ++i) {
+      std::memset(out[i].name, 0, sizeof(out[i].name));
+      std::strncpy(out[i].name, names[i].c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = cnt[i];
+      out[i].total_ms = tot[i];
+    }
+    return HTLR_OK;
+  } catch (const Error& e) {
+    return record(e);
   }
 }
 
