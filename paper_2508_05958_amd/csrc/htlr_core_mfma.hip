@@ -42,8 +42,19 @@ constexpr int kCB = 64;    // bytes of K per row per stage
 template <typename TE> struct AccT { using type = float; };
 template <> struct AccT<double> { using type = double; };
 
+// Source tensor of one staged column for offset o, or the zero tensor when
+// the column is empty or its source box lies outside the domain.
 template <typename TE>
-__global__ __launch_bounds__(256) void k_core_mfma(
+__device__ __forceinline__ const TE* col_src(const TE* W, const TE* zero, int ct, int cx, int cy, int cz, int cr,
+                                             int4 o, int B, int nrhs, int P) {
+  const int sx = cx + o.y, sy = cy + o.z, sz = cz + o.w;
+  const bool ok = ct >= 0 && sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B;
+  const int64_t sg = (int64_t)sx + (int64_t)B * (sy + (int64_t)B * sz);
+  return ok ? W + (sg * nrhs + cr) * P : zero;
+}
+
+template <typename TE>
+__global__ __launch_bounds__(256, 2) void k_core_mfma(
     const TE* __restrict__ G, const TE* __restrict__ W, const TE* __restrict__ zero,
     typename AccT<TE>::type* __restrict__ H, const int32_t* __restrict__ tile_tau,
     const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
@@ -67,20 +78,17 @@ __global__ __launch_bounds__(256) void k_core_mfma(
   const int m0 = ((item >> 6) & 63) * kBM;
   const int split = item & 63;
   const int part = tid & 3;               // 16-byte chunk within a 64-byte row slice
-  const int sr[2] = {tid >> 2, (tid >> 2) + 64};
+  const int sr0 = tid >> 2, sr1 = (tid >> 2) + 64;
+  const int arow0 = m0 + sr0, arow1 = m0 + sr1;
 
-  // columns staged by this thread: box, rhs, target coordinates
-  int ctau[2], cr[2], cx[2][3];
-  for (int h = 0; h < 2; ++h) {
-    int col = sr[h];
-    int b = col / nrhs;
-    cr[h] = col % nrhs;
-    ctau[h] = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
-    int t = ctau[h] < 0 ? 0 : ctau[h];
-    cx[h][0] = t % B;
-    cx[h][1] = (t / B) % B;
-    cx[h][2] = t / (B * B);
-  }
+  // the two columns staged by this thread: target box, rhs, box coordinates
+  const int b0 = sr0 / nrhs, b1 = sr1 / nrhs;
+  const int cr0 = sr0 % nrhs, cr1 = sr1 % nrhs;
+  const int ct0 = (b0 < NB) ? tile_tau[(int64_t)tile * NB + b0] : -1;
+  const int ct1 = (b1 < NB) ? tile_tau[(int64_t)tile * NB + b1] : -1;
+  const int t0c = ct0 < 0 ? 0 : ct0, t1c = ct1 < 0 ? 0 : ct1;
+  const int cx0 = t0c % B, cy0 = (t0c / B) % B, cz0 = t0c / (B * B);
+  const int cx1 = t1c % B, cy1 = (t1c / B) % B, cz1 = t1c / (B * B);
 
   int64_t e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
   {
@@ -93,82 +101,51 @@ __global__ __launch_bounds__(256) void k_core_mfma(
   const int ksteps = (P + KBE - 1) / KBE;
   const int64_t nstage = (e1 - e0) * ksteps;
   const int64_t PP = (int64_t)P * P;
-
-  const TE* gA = G;
-  const TE* gB[2] = {zero, zero};
-  uint4 ra[2], rb[2];
   const uint4 z4 = make_uint4(0, 0, 0, 0);
 
-  auto set_delta = [&](int64_t e) {
-    int4 o = tile_off[e];
-    gA = G + (int64_t)o.x * PP;
-    for (int h = 0; h < 2; ++h) {
-      int sx = cx[h][0] + o.y, sy = cx[h][1] + o.z, sz = cx[h][2] + o.w;
-      bool ok = ctau[h] >= 0 && sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B;
-      int64_t sg = (int64_t)sx + (int64_t)B * (sy + (int64_t)B * sz);
-      gB[h] = ok ? W + (sg * nrhs + cr[h]) * P : zero;
-    }
-  };
-  auto gload = [&](int k0) {
-    const int k = k0 + part * E;
-    const bool kin = k < P;
-    for (int h = 0; h < 2; ++h) {
-      const int row = m0 + sr[h];
-      ra[h] = (kin && row < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)row * P + k) : z4;
-      rb[h] = kin ? *reinterpret_cast<const uint4*>(gB[h] + k) : z4;
-    }
-  };
-  auto sstore = [&](int buf) {
-    for (int h = 0; h < 2; ++h) {
-      *reinterpret_cast<uint4*>(&As[buf][sr[h] * LDW + part * E]) = ra[h];
-      *reinterpret_cast<uint4*>(&Bs[buf][sr[h] * LDW + part * E]) = rb[h];
-    }
-  };
+  const TE* gA = G;
+  const TE* gB0 = zero;
+  const TE* gB1 = zero;
+  uint4 ra0 = z4, ra1 = z4, rb0 = z4, rb1 = z4;
 
   const int wm = wv >> 1, wn = wv & 1;
   constexpr bool k16 = std::is_same<TE, double>::value;   // 16x16 tiles for f64
   constexpr int TI = k16 ? 4 : 2;                          // sub-tiles per wave per dim
   using AccV = typename std::conditional<k16, f64x4, f32x16>::type;
   AccV acc[TI][TI];
+#pragma unroll
   for (int i = 0; i < TI; ++i)
+#pragma unroll
     for (int j = 0; j < TI; ++j) acc[i][j] = AccV{};
 
-  auto compute = [&](int buf) {
-    const TE* Asb = As[buf];
-    const TE* Bsb = Bs[buf];
-    if constexpr (std::is_same<TE, uint16_t>::value) {
-      for (int kk = 0; kk < KBE; kk += 16) {
-        bf16x8 a[2], b[2];
-        for (int i = 0; i < 2; ++i)
-          a[i] = *reinterpret_cast<const bf16x8*>(&Asb[(wm * 64 + i * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-        for (int j = 0; j < 2; ++j)
-          b[j] = *reinterpret_cast<const bf16x8*>(&Bsb[(wn * 64 + j * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-    } else if constexpr (std::is_same<TE, float>::value) {
-      for (int kk = 0; kk < KBE; kk += 2) {
-        float a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = Asb[(wm * 64 + i * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
-        for (int j = 0; j < 2; ++j) b[j] = Bsb[(wn * 64 + j * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-    } else {
-      for (int kk = 0; kk < KBE; kk += 4) {
-        double a[4], b[4];
-        for (int i = 0; i < 4; ++i) a[i] = Asb[(wm * 64 + i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
-        for (int j = 0; j < 4; ++j) b[j] = Bsb[(wn * 64 + j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-    }
-  };
+#define HTLR_SET_DELTA(EIDX)                                             \
+  {                                                                      \
+    const int4 o_ = tile_off[EIDX];                                      \
+    gA = G + (int64_t)o_.x * PP;                                         \
+    gB0 = col_src(W, zero, ct0, cx0, cy0, cz0, cr0, o_, B, nrhs, P);     \
+    gB1 = col_src(W, zero, ct1, cx1, cy1, cz1, cr1, o_, B, nrhs, P);     \
+  }
+#define HTLR_GLOAD(K0)                                                                                       \
+  {                                                                                                          \
+    const int k_ = (K0) + part * E;                                                                          \
+    const bool kin_ = k_ < P;                                                                                \
+    ra0 = (kin_ && arow0 < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)arow0 * P + k_) : z4;         \
+    ra1 = (kin_ && arow1 < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)arow1 * P + k_) : z4;         \
+    rb0 = kin_ ? *reinterpret_cast<const uint4*>(gB0 + k_) : z4;                                             \
+    rb1 = kin_ ? *reinterpret_cast<const uint4*>(gB1 + k_) : z4;                                             \
+  }
+#define HTLR_SSTORE(BUF)                                                       \
+  {                                                                            \
+    *reinterpret_cast<uint4*>(&As[BUF][sr0 * LDW + part * E]) = ra0;           \
+    *reinterpret_cast<uint4*>(&As[BUF][sr1 * LDW + part * E]) = ra1;           \
+    *reinterpret_cast<uint4*>(&Bs[BUF][sr0 * LDW + part * E]) = rb0;           \
+    *reinterpret_cast<uint4*>(&Bs[BUF][sr1 * LDW + part * E]) = rb1;           \
+  }
 
   if (nstage > 0) {
-    set_delta(e0);
-    gload(0);
-    sstore(0);
+    HTLR_SET_DELTA(e0);
+    HTLR_GLOAD(0);
+    HTLR_SSTORE(0);
     __syncthreads();
     int64_t e = e0;
     int ks = 0;
@@ -179,19 +156,63 @@ __global__ __launch_bounds__(256) void k_core_mfma(
       if (ksn == ksteps) { ksn = 0; ++en; }
       const bool more = st + 1 < nstage;
       if (more) {
-        if (ksn == 0) set_delta(en);
-        gload(ksn * KBE);
+        if (ksn == 0) HTLR_SET_DELTA(en);
+        HTLR_GLOAD(ksn * KBE);
       }
-      compute(cur);
-      if (more) sstore(cur ^ 1);
+      const TE* Asb = As[cur];
+      const TE* Bsb = Bs[cur];
+      if constexpr (std::is_same<TE, uint16_t>::value) {
+#pragma unroll
+        for (int kk = 0; kk < KBE; kk += 16) {
+          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Asb[(wm * 64 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Asb[(wm * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+          const bf16x8 bb0 = *reinterpret_cast<const bf16x8*>(&Bsb[(wn * 64 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+          const bf16x8 bb1 = *reinterpret_cast<const bf16x8*>(&Bsb[(wn * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bb0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bb1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bb0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bb1, acc[1][1], 0, 0, 0);
+        }
+      } else if constexpr (std::is_same<TE, float>::value) {
+#pragma unroll
+        for (int kk = 0; kk < KBE; kk += 2) {
+          const float a0 = Asb[(wm * 64 + (lane & 31)) * LDW + kk + (lane >> 5)];
+          const float a1 = Asb[(wm * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
+          const float bb0 = Bsb[(wn * 64 + (lane & 31)) * LDW + kk + (lane >> 5)];
+          const float bb1 = Bsb[(wn * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
+          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bb0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bb1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bb0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bb1, acc[1][1], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KBE; kk += 4) {
+          double a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = Asb[(wm * 64 + i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = Bsb[(wn * 64 + j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      if (more) HTLR_SSTORE(cur ^ 1);
       __syncthreads();
       e = en;
       ks = ksn;
     }
   }
+#undef HTLR_SET_DELTA
+#undef HTLR_GLOAD
+#undef HTLR_SSTORE
 
   // write the owned output tile
+#pragma unroll
   for (int i = 0; i < TI; ++i)
+#pragma unroll
     for (int j = 0; j < TI; ++j) {
       if constexpr (k16) {
         const int col = wn * 64 + j * 16 + (lane & 15);
@@ -199,6 +220,7 @@ __global__ __launch_bounds__(256) void k_core_mfma(
         const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
         if (t < 0) continue;
         TA* Ho = H + ((int64_t)t * nrhs + r) * P;
+#pragma unroll
         for (int v = 0; v < 4; ++v) {
           // f64 16x16x4 accumulator: register v holds row lane/16 + 4 v
           const int row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
@@ -210,6 +232,7 @@ __global__ __launch_bounds__(256) void k_core_mfma(
         const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
         if (t < 0) continue;
         TA* Ho = H + ((int64_t)t * nrhs + r) * P;
+#pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int row = m0 + wm * 64 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
           if (row < P) Ho[row] = acc[i][j][v];
