@@ -243,6 +243,85 @@ __global__ __launch_bounds__(64 * NW) void k_near_rows(
   }
 }
 
+// Near field + diagonal on the matrix cores: uniform 3D grid, leaves of 8^3
+// points, radial kernel, float.  For a target leaf and a chunk of 16
+// right-hand sides, f_tau (512 x 16) += K_tau,sigma (512 x 512) u_sigma
+// (512 x 16) for every near sigma, with 16x16x4 f32 MFMA: A = kernel values
+// K(i, j) = T[|I - J|^2] read from the LDS table, B = u_sigma staged in LDS.
+// Each of the 4 waves owns 128 target rows (8 MFMA tiles).
+typedef float htlr_f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_near_mfma(const float* __restrict__ u, float* __restrict__ f,
+                                                    const float* __restrict__ a, const int64_t* __restrict__ nptr,
+                                                    const int32_t* __restrict__ nsrc, const float* __restrict__ table,
+                                                    int tsize, int n, int B, int nrhs) {
+  constexpr int m = 8, M = 512;
+  extern __shared__ unsigned char smem_raw[];
+  float* tab = reinterpret_cast<float*>(smem_raw);
+  const int tpad = (tsize + 3) & ~3;
+  float* us = tab + tpad;                 // [M][16]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tau = blockIdx.x;
+  const int r0 = blockIdx.y * 16;
+  const int64_t N = (int64_t)n * n * n;
+  const int tb0 = tau % B, tb1 = (tau / B) % B, tb2 = tau / (B * B);
+  for (int s = tid; s < tsize; s += 256) tab[s] = table[s];
+  // A rows of this lane: i = wv*128 + t*16 + (lane & 15), t = 0..7
+  //   ix = lane & 7, iy = (2 t + ((lane >> 3) & 1)) & 7, iz = 2 wv + t / 4
+  const int l15 = lane & 15;
+  const int Ix = tb0 * m + (l15 & 7);
+  int Iy[4], Iz[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Iy[t] = tb1 * m + ((2 * t + (l15 >> 3)) & 7);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) Iz[t] = tb2 * m + 2 * wv + t;
+  htlr_f32x4 acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = htlr_f32x4{0.f, 0.f, 0.f, 0.f};
+  const int jl = lane >> 4, rl = lane & 15;
+  for (int64_t e = nptr[tau]; e < nptr[tau + 1]; ++e) {
+    const int sg = nsrc[e];
+    const int sb0 = sg % B, sb1 = (sg / B) % B, sb2 = sg / (B * B);
+    __syncthreads();
+    for (int idx = tid; idx < M * 16; idx += 256) {
+      const int j = idx % M, r = idx / M;
+      us[j * 16 + r] = (r0 + r < nrhs)
+                           ? u[(int64_t)(r0 + r) * N + lin3(sb0 * m + (j & 7), sb1 * m + ((j >> 3) & 7), sb2 * m + (j >> 6), n)]
+                           : 0.f;
+    }
+    __syncthreads();
+    for (int j0 = 0; j0 < M; j0 += 4) {
+      const int j = j0 + jl;
+      const int dx = Ix - (sb0 * m + (j & 7));
+      const int jy = sb1 * m + ((j >> 3) & 7), jz = sb2 * m + (j >> 6);
+      const float b = us[j * 16 + rl];
+      const int dx2 = dx * dx;
+      int dy2[4], dz2[2];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) { const int d = Iy[t] - jy; dy2[t] = d * d; }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) { const int d = Iz[t] - jz; dz2[t] = d * d; }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float av = tab[dx2 + dy2[t & 3] + dz2[t >> 2]];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // D layout of 16x16x4 f32: register v holds row 4 (lane / 16) + v, column lane % 16
+  const int r = lane & 15;
+  if (r0 + r >= nrhs) return;
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = wv * 128 + t * 16 + 4 * (lane >> 4) + v;
+      const int64_t g = lin3(tb0 * m + (i & 7), tb1 * m + ((i >> 3) & 7), tb2 * m + (i >> 6), n);
+      const int64_t o = (int64_t)(r0 + r) * N + g;
+      f[o] = acc[t][v] + a[g] * u[o];
+    }
+}
+
 // Near field + diagonal on a general tensor grid: kernel values evaluated from
 // coordinates relative to the target box, weights |Omega_j| and per-point
 // diagonal integrals D_i.
@@ -696,7 +775,14 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   // near field + diagonal (overwrites f)
   {
   ProfScope ps(A, "near", -1, st);
-  if (A.uniform && d == 3 && m <= 8) {
+  const bool near_mfma = !f64 && A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST && nrhs >= 8;
+  if (near_mfma) {
+    const size_t sh = (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(float) + (size_t)512 * 16 * sizeof(float);
+    if (sh > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "near-field working set exceeds LDS");
+    hipLaunchKernelGGL(k_near_mfma, dim3(nleaf, (nrhs + 15) / 16), dim3(256), sh, st, (const float*)u, (float*)f,
+                       (const float*)a, A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), A.T32.as<float>(), A.Tsize,
+                       n, B, nrhs);
+  } else if (A.uniform && d == 3 && m <= 8) {
     const bool radial = A.kid != HTLR_K_POLY_TEST;
     const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
     const size_t fixed = (radial ? ((A.Tsize + 1) & ~1) : 0) * sizeof(T);

@@ -148,7 +148,8 @@ def test_w3d_fp64_sampled(torch):
 
 
 @pytest.mark.parametrize("d,n,leaf,p,kernel,nrhs", [(3, 32, 8, 6, "inv_r", 4), (2, 64, 8, 6, "neg_log", 16),
-                                                     (3, 32, 4, 8, "inv_r", 16)])
+                                                     (3, 32, 4, 8, "inv_r", 16), (3, 32, 8, 6, "inv_r", 16),
+                                                     (3, 32, 8, 4, "exp", 9), (3, 16, 8, 6, "gauss", 17)])
 def test_reduced_precision_vs_fp64(torch, d, n, leaf, p, kernel, nrhs):
     import paper_2508_05958_amd as H
     _say(f"[gpu] fp32/bf16 vs fp64 d={d} n={n} p={p} nrhs={nrhs}")
