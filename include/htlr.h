@@ -222,6 +222,80 @@ htlr_status htlr_plan_pairs(const double* points, int d, int n, int leaf, double
                             int admissibility, int level, int32_t* tau, int32_t* sigma,
                             int64_t cap, int64_t* count);
 
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of solve requests on one GPU.
+ * (Not in the paper; a serving layer over htlr_build / htlr_solve.)
+ *
+ * Requests (A u = f for possibly different grids, kernels and ranks) are
+ * queued by htlr_server_submit and advanced by htlr_server_step, one
+ * scheduling tick per call:
+ *  - admission: queued requests enter, first come first served, while the
+ *    device bytes of resident structures plus request state stay within
+ *    memory_budget; idle structures are evicted least recently used first;
+ *  - structures (the HTLR matrices) stay resident across requests, keyed by
+ *    (points, kernel, d, n, p, leaf, eta2, admissibility, a);
+ *  - every active request advances by one step of GMRES with FP64 iterative
+ *    refinement (the method of htlr_solve, with the refinement residual taken
+ *    after every GMRES cycle); the products of all requests on one structure
+ *    in one tick are fused into a single multi-right-hand-side product,
+ *    optionally replayed from a captured hipGraph;
+ *  - structures run on separate streams, so their work overlaps.
+ * A request's answer does not depend on which other requests share its
+ * ticks beyond rounding (each column of a fused product is computed by the
+ * same arithmetic as alone).
+ * A server is used from one host thread at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct htlr_server_s* htlr_server;
+
+typedef struct {
+  size_t memory_budget; /* device bytes for structures + request state; 0: 90% of free memory */
+  int max_active;       /* requests in flight; <= 0: 64 */
+  int max_batch;        /* requests of one structure fused per product (1..64); <= 0: 16 */
+  int restart;          /* GMRES cycle length; <= 0: 30 */
+  int inner_prec;       /* htlr_precision of the inner products */
+  int use_graphs;       /* 1: replay fused products from captured hipGraphs */
+  int autotune;         /* 1: time kernel variants per (structure, batch width, precision) */
+} htlr_server_opts;
+
+typedef struct {
+  const double* points; /* host, as in htlr_build (NULL: uniform grid) */
+  int kernel, d, n, p, leaf;
+  double eta2;          /* <= 0: 1 */
+  int admissibility;
+  const double* a;      /* host, N values, or NULL (a = 0); copied at submit */
+  const double* f;      /* host, N values; copied at submit */
+  double tol;           /* target ||f - A u|| / ||f|| (FP64 product); <= 0: 1e-8 */
+  int max_outer;        /* refinement cycles; <= 0: 50 */
+} htlr_request;
+
+typedef struct {
+  int state;            /* 0 queued, 1 active, 2 done, 3 failed */
+  int status;           /* htlr_status of a finished request */
+  int outer_iters, inner_iters;
+  double rel_residual;
+  double t_submit, t_admit, t_done; /* seconds on the server clock */
+} htlr_request_info;
+
+typedef struct {
+  int64_t ticks, fused_products, graph_launches, structures_built, evictions;
+  int resident_structures, active, queued;
+  size_t resident_bytes;
+} htlr_server_stats_t;
+
+htlr_status htlr_server_create(const htlr_server_opts* opts, htlr_server* out);
+/* Copies the request; *id identifies it in htlr_server_result. */
+htlr_status htlr_server_submit(htlr_server S, const htlr_request* req, int64_t* id);
+/* One scheduling tick (admission, one fused step per structure, retirement).
+ * Returns the number of active and queued requests after the tick. */
+htlr_status htlr_server_step(htlr_server S, int* active, int* queued);
+/* For a finished request: copies u (host, N doubles, may be NULL) and its
+ * info, then forgets the request.  For an unfinished one: fills info only
+ * and returns HTLR_ERR_INVALID with state 0 or 1. */
+htlr_status htlr_server_result(htlr_server S, int64_t id, double* u, htlr_request_info* info);
+htlr_status htlr_server_stats(htlr_server S, htlr_server_stats_t* out);
+double htlr_server_clock(htlr_server S);
+void htlr_server_destroy(htlr_server S);
+
 #ifdef __cplusplus
 }
 #endif

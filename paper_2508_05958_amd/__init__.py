@@ -229,6 +229,127 @@ class HTLRMatrix:
             pass
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_size_t), ("max_active", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("restart", ctypes.c_int), ("inner_prec", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("points", _c_dp), ("kernel", ctypes.c_int), ("d", ctypes.c_int), ("n", ctypes.c_int),
+                ("p", ctypes.c_int), ("leaf", ctypes.c_int), ("eta2", ctypes.c_double),
+                ("admissibility", ctypes.c_int), ("a", _c_dp), ("f", _c_dp), ("tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("inner_iters", ctypes.c_int), ("rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("fused_products", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+                ("structures_built", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("resident_structures", ctypes.c_int), ("active", ctypes.c_int), ("queued", ctypes.c_int),
+                ("resident_bytes", ctypes.c_size_t)]
+
+
+def _declare_server(L):
+    if getattr(L, "_server_declared", False):
+        return
+    L.htlr_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(_vp)]
+    L.htlr_server_submit.argtypes = [_vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_int64)]
+    L.htlr_server_step.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.htlr_server_result.argtypes = [_vp, ctypes.c_int64, _c_dp, ctypes.POINTER(_RequestInfo)]
+    L.htlr_server_stats.argtypes = [_vp, ctypes.POINTER(_ServerStats)]
+    L.htlr_server_clock.argtypes = [_vp]
+    L.htlr_server_clock.restype = ctypes.c_double
+    L.htlr_server_destroy.argtypes = [_vp]
+    L.htlr_server_destroy.restype = None
+    for name in ("htlr_server_create", "htlr_server_submit", "htlr_server_step", "htlr_server_result",
+                 "htlr_server_stats"):
+        getattr(L, name).restype = ctypes.c_int
+    L._server_declared = True
+
+
+class Server:
+    """Continuous-batching request server (wraps htlr_server)."""
+
+    def __init__(self, memory_budget=0, max_active=64, max_batch=16, restart=30, inner_prec="fp32",
+                 use_graphs=True, autotune=False):
+        L = lib()
+        _declare_server(L)
+        o = _ServerOpts(int(memory_budget), max_active, max_batch, restart,
+                        PRECISIONS[inner_prec] if isinstance(inner_prec, str) else int(inner_prec),
+                        1 if use_graphs else 0, 1 if autotune else 0)
+        h = _vp()
+        _check(L.htlr_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, f, kernel, d, n, p, leaf, points=None, a=None, tol=1e-8, eta2=1.0, admissibility="strong",
+               max_outer=0) -> int:
+        N = n ** d
+        fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(N))
+        keep = [fa]
+        r = _Request()
+        r.f = fa.ctypes.data_as(_c_dp)
+        if points is not None:
+            pa = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(d * n))
+            keep.append(pa)
+            r.points = pa.ctypes.data_as(_c_dp)
+        if a is not None:
+            aa = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(N))
+            keep.append(aa)
+            r.a = aa.ctypes.data_as(_c_dp)
+        r.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        r.d, r.n, r.p, r.leaf = d, n, p, leaf
+        r.eta2 = float(eta2)
+        r.admissibility = ADM[admissibility] if isinstance(admissibility, str) else int(admissibility)
+        r.tol = float(tol)
+        r.max_outer = int(max_outer)
+        rid = ctypes.c_int64()
+        _check(lib().htlr_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._sizes = getattr(self, "_sizes", {})
+        self._sizes[rid.value] = N
+        return rid.value
+
+    def step(self):
+        a, q = ctypes.c_int(), ctypes.c_int()
+        _check(lib().htlr_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def result(self, rid):
+        """(u, info) for a finished request, else (None, info)."""
+        i = _RequestInfo()
+        u = np.empty(self._sizes[rid])
+        st = lib().htlr_server_result(self._h, rid, u.ctypes.data_as(_c_dp), ctypes.byref(i))
+        info = {"state": i.state, "status": i.status, "outer_iters": i.outer_iters, "inner_iters": i.inner_iters,
+                "rel_residual": i.rel_residual, "t_submit": i.t_submit, "t_admit": i.t_admit, "t_done": i.t_done}
+        if st != HTLR_OK:
+            return None, info
+        return u, info
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib().htlr_server_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def clock(self) -> float:
+        return lib().htlr_server_clock(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().htlr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def htlr_build(points, kernel, d, n, p, leaf, **kw) -> HTLRMatrix:
     return HTLRMatrix(points, kernel, d, n, p, leaf, **kw)
 

@@ -364,6 +364,7 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
   // work items ordered (class, row block, split, tile)
   if (T.items_ks != ks) {
+    if (A.ws.frozen) fail(HTLR_ERR_INVALID, "matrix-core work list not reserved");
     std::vector<int32_t> items;
     for (size_t c = 0; c + 1 < T.class_start.size(); ++c)
       for (int mb = 0; mb < nmb; ++mb)
@@ -380,7 +381,10 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   void* Hout = H;
   if (ks > 1) {
     const size_t need = (size_t)helems * ks * esz;
-    if (parts.bytes < need) parts.alloc(need);
+    if (parts.bytes < need) {
+      if (A.ws.frozen) fail(HTLR_ERR_INVALID, "K-split buffer exceeds the reserved size");
+      parts.alloc(need);
+    }
     Hout = parts.ptr;
   }
   const unsigned nwg = (unsigned)(((T.nitems + 7) / 8) * 8);
@@ -411,6 +415,41 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
                          helems, ks, helems);
     HTLR_HIP(hipGetLastError());
   }
+}
+
+void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
+  A.ws.frozen = false;
+  ensure_workspace(A, nrhs, HTLR_FP64);
+  if (!A.uniform || !core_mfma_ok(A, HTLR_FP64)) {
+    A.ws.frozen = true;
+    return;
+  }
+  size_t parts_need = 0;
+  const int nmb = (A.P + kBM - 1) / kBM;
+  for (int c = 1; c <= nrhs; ++c) {
+    const int nb = core_mfma_nb(c);
+    for (LevelData& lv : A.levels) {
+      if (lv.npairs == 0) continue;
+      LevelData::Tiles& T = tiles_for(A, lv, nb);
+      if (T.ntile == 0) continue;
+      const int ks = pick_ksplit(T.ntile * nmb, T.maxlist);
+      if (T.items_ks != ks) {
+        std::vector<int32_t> items;
+        for (size_t cl = 0; cl + 1 < T.class_start.size(); ++cl)
+          for (int mb = 0; mb < nmb; ++mb)
+            for (int s = 0; s < ks; ++s)
+              for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
+                items.push_back((int32_t)((t << 12) | (mb << 6) | s));
+        T.items.alloc(items.size() * sizeof(int32_t));
+        HTLR_HIP(hipMemcpy(T.items.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        T.nitems = (int)items.size();
+        T.items_ks = ks;
+      }
+      if (ks > 1) parts_need = std::max(parts_need, (size_t)lv.nbox * c * A.P * ks * sizeof(double));
+    }
+  }
+  if (A.ws.parts.bytes < parts_need) A.ws.parts.alloc(parts_need);
+  A.ws.frozen = true;
 }
 
 }  // namespace htlr

@@ -74,7 +74,7 @@ struct LevelData {
 
 struct Workspace {
   int nrhs = 0;
-  int prec = -1;
+  bool frozen = false;               // reserved: products must not reallocate
   std::vector<DevBuf> W, H, W16;     // per level
   DevBuf zero;                       // a zero source tensor (matrix-core kernel)
   DevBuf parts;                      // K-split partial sums (matrix-core kernel)
@@ -127,6 +127,11 @@ struct htlr_matrix_impl {
 };
 
 bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
+void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec);
+// Allocates every buffer products with up to nrhs right-hand sides can need
+// (work buffers, matrix-core work lists, K-split partial sums), then freezes
+// them, so that later products never allocate (graph capture, serving).
+void reserve_workspace(htlr_matrix_impl& A, int nrhs);
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st, DevBuf& parts);
 

@@ -702,22 +702,25 @@ static int pick_rc(int nrhs, size_t fixed_bytes, size_t per_rc_bytes) {
 // ---------------------------------------------------------------------------
 // Work buffers
 
-static size_t elem_w(int prec) { return prec == HTLR_FP64 ? 8 : (prec == HTLR_FP32 ? 4 : 2); }
-static size_t elem_a(int prec) { return prec == HTLR_FP64 ? 8 : 4; }
 
 static size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
+  (void)prec;
   size_t tot = 0;
   for (const LevelData& lv : A.levels) {
     if (lv.npairs == 0) continue;
     size_t cnt = (size_t)lv.nbox * nrhs * A.P;
-    tot += ((cnt * elem_w(prec) + 255) & ~size_t(255)) + ((cnt * elem_a(prec) + 255) & ~size_t(255));
+    tot += 2 * ((cnt * sizeof(double) + 255) & ~size_t(255));
   }
   return tot;
 }
 
-static void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
+// Work buffers are sized for 8-byte elements so that products of every
+// precision share them; they are reallocated only when nrhs grows.
+void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
+  (void)prec;
   Workspace& ws = A.ws;
-  if (ws.nrhs >= nrhs && ws.prec == prec) return;
+  if (ws.nrhs >= nrhs) return;
+  if (ws.frozen) fail(HTLR_ERR_INVALID, "nrhs exceeds the reserved work buffers");
   ws.W.clear();
   ws.H.clear();
   ws.W.resize(A.L + 1);
@@ -726,15 +729,14 @@ static void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
   for (const LevelData& lv : A.levels) {
     if (lv.npairs == 0) continue;
     size_t cnt = (size_t)lv.nbox * nrhs * A.P;
-    ws.W[lv.level].alloc(cnt * elem_w(prec));
-    ws.H[lv.level].alloc(cnt * elem_a(prec));
+    ws.W[lv.level].alloc(cnt * sizeof(double));
+    ws.H[lv.level].alloc(cnt * sizeof(double));
     ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes;
   }
   ws.zero.alloc((size_t)A.P * sizeof(double));
   HTLR_HIP(hipMemset(ws.zero.ptr, 0, ws.zero.bytes));
   ws.bytes += ws.zero.bytes;
   ws.nrhs = nrhs;
-  ws.prec = prec;
 }
 
 // ---------------------------------------------------------------------------

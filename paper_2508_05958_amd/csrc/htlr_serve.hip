@@ -1,0 +1,642 @@
+// Request server: continuous batching of solve requests (see include/htlr.h).
+//
+// Every tick:
+//   1. admission: queued requests enter first come first served while the
+//      device bytes of resident structures plus request state fit the budget
+//      (idle structures are evicted least recently used first);
+//   2. for each resident structure with active requests, on the structure's
+//      own stream: one fused FP64 product for the requests that need their
+//      refinement residual, and one fused inner-precision product for the
+//      requests in a GMRES cycle, followed by their per-request Arnoldi
+//      updates (classical Gram-Schmidt twice, on the device);
+//   3. one synchronisation per structure, then the host-side Givens updates
+//      and state transitions;
+//   4. finished requests are retired and their memory returned.
+// Fused products gather the requests' vectors into a column-major batch and
+// call the HTLR product with nrhs = batch width; with use_graphs the gather
+// and the product are replayed from a hipGraph captured per (precision,
+// width).
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <set>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "htlr_handle.h"
+#include "htlr_vec.h"
+
+namespace htlr {
+
+extern thread_local std::string g_last_error;
+htlr_status record(const Error& e);
+
+namespace {
+
+#define HTLR_CHECK_ST(call)                                \
+  do {                                                     \
+    htlr_status s_ = (call);                               \
+    if (s_ != HTLR_OK) ::htlr::fail(s_, g_last_error);     \
+  } while (0)
+
+struct PinnedBuf {
+  double* p = nullptr;
+  size_t n = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  void alloc(size_t count) {
+    release();
+    HTLR_HIP(hipHostMalloc((void**)&p, count * sizeof(double), hipHostMallocDefault));
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~PinnedBuf() { release(); }
+};
+
+struct Structure;
+
+struct Req {
+  int64_t id = 0;
+  std::string key;
+  Structure* S = nullptr;
+  // copied request parameters
+  std::vector<double> f, a, points;
+  int kernel = 0, d = 0, n = 0, p = 0, leaf = 0, adm = 0;
+  double eta2 = 1.0, tol = 1e-8;
+  int max_outer = 50;
+  int64_t N = 0;
+  // lifecycle
+  int state = 0, status = HTLR_OK;
+  double t_submit = 0, t_admit = -1, t_done = -1;
+  std::vector<double> result;
+  // device state: f | x | r | d | V[0..m]
+  DevBuf dev;
+  size_t dev_bytes = 0;
+  double *df = nullptr, *dx = nullptr, *dr = nullptr, *dd = nullptr, *V = nullptr;
+  DevBuf hdev;             // device scalars: h pass 1 [m+1], h pass 2 [m+1], norm, y [m]
+  PinnedBuf host;          // pinned mirror of hdev
+  // GMRES-IR state
+  double fn = 0, rn = 0, beta = 0, rtol = 0;
+  int outer = 0, inner = 0, k = 0;
+  bool arnoldi = false;
+  std::vector<double> H, cs, sn, g, y;
+};
+
+struct Structure {
+  std::string key;
+  htlr_matrix A = nullptr;
+  int64_t N = 0;
+  size_t bytes = 0;
+  int active = 0;
+  double last_use = 0;
+  hipStream_t stream = nullptr;
+  int cap = 0;
+  DevBuf U64, F64, U32, F32, ptrs, partial;
+  PinnedBuf hptrs;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  std::map<std::pair<int, int>, int> uses;
+  size_t ptr_slot = 0;     // next free slot of hptrs in this tick (uploads are asynchronous)
+  ~Structure() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (A) htlr_free(A);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+constexpr int kRedB = 512;
+
+}  // namespace
+
+struct ServerImpl {
+  htlr_server_opts o{};
+  size_t budget = 0, used = 0;
+  double inner_tol = 1e-6;
+  int64_t next_id = 1;
+  std::deque<int64_t> queue;
+  std::map<int64_t, std::unique_ptr<Req>> reqs;
+  std::map<std::string, std::unique_ptr<Structure>> structs;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  htlr_server_stats_t st{};
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  static std::string make_key(const Req& q) {
+    std::ostringstream os;
+    os << q.kernel << '|' << q.d << '|' << q.n << '|' << q.p << '|' << q.leaf << '|' << q.eta2 << '|' << q.adm << '|';
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const std::vector<double>& v) {
+      for (double x : v) {
+        uint64_t b;
+        std::memcpy(&b, &x, 8);
+        h = (h ^ b) * 1099511628211ull;
+      }
+      h = (h ^ v.size()) * 1099511628211ull;
+    };
+    mix(q.points);
+    mix(q.a);
+    os << h;
+    return os.str();
+  }
+
+  size_t state_bytes(int64_t N) const { return ((size_t)(o.restart + 5) * N * sizeof(double) + 4095) & ~size_t(4095); }
+
+  // device bytes a new structure will hold: the matrix plus product work
+  // buffers and the fused batch buffers for cap columns
+  size_t structure_bytes(const Req& q) const {
+    htlr_build_opts bo{};
+    bo.eta2 = q.eta2;
+    bo.admissibility = q.adm;
+    size_t fp = 0;
+    HTLR_CHECK_ST(htlr_footprint(q.points.empty() ? nullptr : q.points.data(), (htlr_kernel)q.kernel, q.d, q.n, q.p,
+                                 q.leaf, &bo, &fp));
+    int L = 0;
+    std::vector<int> m;
+    tree_shape(q.d, q.n, q.leaf, &L, &m);
+    size_t P = 1, ws = 0;
+    for (int l = 0; l < q.d; ++l) P *= q.p;
+    for (int l = 0; l <= L; ++l) {
+      size_t nb = 1;
+      for (int k = 0; k < q.d; ++k) nb *= (size_t)(q.n / m[l]);
+      if (l >= 2) ws += nb * (size_t)o.max_batch * P * 16;
+    }
+    return fp + ws + (size_t)q.N * o.max_batch * 24 + (size_t)kRedB * (o.restart + 2) * 8;
+  }
+
+  void evict_idle(size_t need) {
+    while (used + need > budget) {
+      Structure* victim = nullptr;
+      for (auto& kv : structs)
+        if (kv.second->active == 0 && (!victim || kv.second->last_use < victim->last_use)) victim = kv.second.get();
+      if (!victim) return;
+      used -= victim->bytes;
+      structs.erase(victim->key);
+      ++st.evictions;
+    }
+  }
+
+  Structure* build(Req& q) {
+    auto S = std::make_unique<Structure>();
+    S->key = q.key;
+    S->N = q.N;
+    htlr_build_opts bo{};
+    bo.eta2 = q.eta2;
+    bo.admissibility = q.adm;
+    bo.a = q.a.empty() ? nullptr : q.a.data();
+    bo.precisions = (1 << HTLR_FP64) | (1 << o.inner_prec);
+    HTLR_CHECK_ST(htlr_build(q.points.empty() ? nullptr : q.points.data(), (htlr_kernel)q.kernel, q.d, q.n, q.p,
+                             q.leaf, &bo, &S->A));
+    HTLR_HIP(hipStreamCreate(&S->stream));
+    S->cap = o.max_batch;
+    S->U64.alloc((size_t)S->N * S->cap * sizeof(double));
+    S->F64.alloc((size_t)S->N * S->cap * sizeof(double));
+    if (o.inner_prec != HTLR_FP64) {
+      S->U32.alloc((size_t)S->N * S->cap * sizeof(float));
+      S->F32.alloc((size_t)S->N * S->cap * sizeof(float));
+    }
+    S->ptrs.alloc((size_t)S->cap * sizeof(double*));
+    // one slot of cap pointers per fused product of a tick
+    S->hptrs.alloc((size_t)S->cap * (2 * ((o.max_active + S->cap - 1) / S->cap) + 2));
+    S->partial.alloc((size_t)kRedB * (o.restart + 2) * sizeof(double));
+    {
+      std::lock_guard<std::mutex> lk(S->A->ws_mu);
+      reserve_workspace(*S->A, S->cap);
+    }
+    htlr_info_t inf{};
+    HTLR_CHECK_ST(htlr_info(S->A, &inf));
+    size_t wsb = 0;
+    HTLR_CHECK_ST(htlr_workspace_bytes(S->A, S->cap, HTLR_FP64, &wsb));
+    S->bytes = inf.device_bytes + wsb + S->A->ws.parts.bytes + S->U64.bytes + S->F64.bytes + S->U32.bytes + S->F32.bytes + S->partial.bytes;
+    Structure* raw = S.get();
+    structs[q.key] = std::move(S);
+    ++st.structures_built;
+    return raw;
+  }
+
+  void admit() {
+    int active = 0;
+    for (auto& kv : reqs)
+      if (kv.second->state == 1) ++active;
+    while (!queue.empty() && active < o.max_active) {
+      Req& q = *reqs.at(queue.front());
+      auto it = structs.find(q.key);
+      Structure* S = it == structs.end() ? nullptr : it->second.get();
+      const size_t sb = state_bytes(q.N);
+      size_t need = sb + (S ? 0 : structure_bytes(q));
+      if (used + need > budget) evict_idle(need);
+      if (used + need > budget) {
+        if (active == 0 && structs.empty()) {   // can never fit
+          q.state = 3;
+          q.status = HTLR_ERR_OOM;
+          q.t_done = now();
+          queue.pop_front();
+          continue;
+        }
+        break;
+      }
+      if (!S) {
+        S = build(q);
+        used += S->bytes;
+      }
+      q.S = S;
+      q.dev.alloc(sb);
+      q.dev_bytes = sb;
+      used += sb;
+      double* base = q.dev.as<double>();
+      q.df = base;
+      q.dx = base + q.N;
+      q.dr = base + 2 * q.N;
+      q.dd = base + 3 * q.N;
+      q.V = base + 4 * q.N;
+      const int m = o.restart;
+      q.hdev.alloc((size_t)(3 * m + 4) * sizeof(double));
+      q.host.alloc((size_t)(3 * m + 4));
+      HTLR_HIP(hipMemcpyAsync(q.df, q.f.data(), q.N * sizeof(double), hipMemcpyHostToDevice, S->stream));
+      hipLaunchKernelGGL(k_zero, dim3(vblocks(q.N)), dim3(256), 0, S->stream, q.dx, q.N);
+      q.H.assign((size_t)(m + 1) * m, 0.0);
+      q.cs.assign(m, 0.0);
+      q.sn.assign(m, 0.0);
+      q.g.assign(m + 1, 0.0);
+      q.y.assign(m, 0.0);
+      q.fn = -1.0;   // ||f|| computed with the first residual
+      q.arnoldi = false;
+      q.state = 1;
+      q.t_admit = now();
+      ++S->active;
+      S->last_use = q.t_admit;
+      ++active;
+      queue.pop_front();
+    }
+  }
+
+  // fused product of columns src[0..c) into out (F64 or F32) on S's stream
+  void fused_product(Structure* S, int prec, const std::vector<const double*>& src) {
+    const int c = (int)src.size();
+    static_assert(sizeof(const double*) == sizeof(double), "pointer table packs pointers into 8-byte slots");
+    if (S->ptr_slot + S->cap > S->hptrs.n) fail(HTLR_ERR_INVALID, "too many fused products in one tick");
+    const double** hp = reinterpret_cast<const double**>(S->hptrs.p + S->ptr_slot);
+    S->ptr_slot += S->cap;
+    for (int j = 0; j < c; ++j) hp[j] = src[j];
+    HTLR_HIP(hipMemcpyAsync(S->ptrs.ptr, hp, c * sizeof(double*), hipMemcpyHostToDevice, S->stream));
+    auto launch = [&]() {
+      const int nb = vblocks(S->N);
+      if (prec == HTLR_FP64) {
+        hipLaunchKernelGGL(k_gather_f64, dim3(nb), dim3(256), 0, S->stream, S->ptrs.as<const double*>(),
+                           S->U64.as<double>(), S->N, c);
+        HTLR_CHECK_ST(htlr_matvec(S->A, S->U64.ptr, S->F64.ptr, c, HTLR_FP64, HTLR_VEC_F64, S->stream));
+      } else {
+        hipLaunchKernelGGL(k_gather_f32, dim3(nb), dim3(256), 0, S->stream, S->ptrs.as<const double*>(),
+                           S->U32.as<float>(), S->N, c);
+        HTLR_CHECK_ST(htlr_matvec(S->A, S->U32.ptr, S->F32.ptr, c, (htlr_precision)prec, HTLR_VEC_F32, S->stream));
+      }
+    };
+    const auto key = std::make_pair(prec, c);
+    ++st.fused_products;
+    if (!o.use_graphs) {
+      launch();
+      return;
+    }
+    auto g = S->graphs.find(key);
+    if (g != S->graphs.end()) {
+      HTLR_HIP(hipGraphLaunch(g->second, S->stream));
+      ++st.graph_launches;
+      return;
+    }
+    if (S->uses[key]++ == 0) {   // first use runs eagerly: work buffers and work lists get allocated
+      launch();
+      return;
+    }
+    hipGraph_t graph = nullptr;
+    HTLR_HIP(hipStreamBeginCapture(S->stream, hipStreamCaptureModeRelaxed));
+    try {
+      launch();
+    } catch (...) {
+      (void)hipStreamEndCapture(S->stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    HTLR_HIP(hipStreamEndCapture(S->stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    HTLR_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    S->graphs[key] = exec;
+    HTLR_HIP(hipGraphLaunch(exec, S->stream));
+    ++st.graph_launches;
+  }
+
+  // device: out[c] = <Vb[:, c], x> into dst (device), c < ncols
+  void dots(Structure* S, const double* Vb, int ncols, const double* x, double* dst) {
+    hipLaunchKernelGGL(k_dots_partial, dim3(kRedB), dim3(kRB), 0, S->stream, Vb, S->N, ncols, x, S->N,
+                       S->partial.as<double>());
+    hipLaunchKernelGGL(k_dots_final, dim3((ncols + 63) / 64), dim3(64), 0, S->stream, S->partial.as<double>(), kRedB,
+                       ncols, dst);
+  }
+
+  void issue(Structure* S, std::vector<Req*>& members) {
+    const int m = o.restart;
+    const int64_t N = S->N;
+    std::vector<Req*> R, K;
+    for (Req* q : members) (q->arnoldi ? K : R).push_back(q);
+    // refinement residuals: r = f - A x (FP64)
+    for (size_t s = 0; s < R.size(); s += o.max_batch) {
+      const size_t e = std::min(R.size(), s + (size_t)o.max_batch);
+      std::vector<const double*> src;
+      for (size_t i = s; i < e; ++i) src.push_back(R[i]->dx);
+      fused_product(S, HTLR_FP64, src);
+      for (size_t i = s; i < e; ++i) {
+        Req* q = R[i];
+        const double* col = S->F64.as<double>() + (int64_t)(i - s) * N;
+        hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, S->stream, q->df, col, q->dr, N);
+        double* hd = q->hdev.as<double>();
+        dots(S, q->dr, 1, q->dr, hd + 2 * (m + 1));
+        if (q->fn < 0) dots(S, q->df, 1, q->df, hd + 2 * (m + 1) + 1);
+        HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+      }
+    }
+    // Arnoldi steps: w = A V_k (inner precision), CGS2, norm
+    const int ip = o.inner_prec;
+    for (size_t s = 0; s < K.size(); s += o.max_batch) {
+      const size_t e = std::min(K.size(), s + (size_t)o.max_batch);
+      std::vector<const double*> src;
+      for (size_t i = s; i < e; ++i) src.push_back(K[i]->V + (int64_t)K[i]->k * N);
+      fused_product(S, ip, src);
+      for (size_t i = s; i < e; ++i) {
+        Req* q = K[i];
+        double* w = q->V + (int64_t)(q->k + 1) * N;
+        if (ip == HTLR_FP64)
+          HTLR_HIP(hipMemcpyAsync(w, S->F64.as<double>() + (int64_t)(i - s) * N, N * sizeof(double),
+                                  hipMemcpyDeviceToDevice, S->stream));
+        else
+          hipLaunchKernelGGL(k_f2d, dim3(vblocks(N)), dim3(256), 0, S->stream, S->F32.as<float>() + (int64_t)(i - s) * N,
+                             w, N);
+        double* hd = q->hdev.as<double>();
+        for (int pass = 0; pass < 2; ++pass) {
+          double* hp = hd + pass * (m + 1);
+          dots(S, q->V, q->k + 1, w, hp);
+          hipLaunchKernelGGL(k_sub_vh, dim3(vblocks(N)), dim3(256), 0, S->stream, q->V, N, q->k + 1, hp, w, N);
+        }
+        dots(S, w, 1, w, hd + 2 * (m + 1));
+        HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+      }
+    }
+    HTLR_HIP(hipGetLastError());
+  }
+
+  void finish_one(Req& q) {
+    Structure* S = q.S;
+    const int m = o.restart;
+    const int64_t N = S->N;
+    const double* hh = q.host.p;
+    if (!q.arnoldi) {
+      if (q.fn < 0) q.fn = std::sqrt(hh[2 * (m + 1) + 1]);
+      q.rn = std::sqrt(hh[2 * (m + 1)]);
+      if (!std::isfinite(q.rn) || !std::isfinite(q.fn)) {
+        q.state = 3;
+        q.status = HTLR_ERR_NUMERIC;
+        return;
+      }
+      if (q.fn == 0.0 || q.rn <= q.tol * q.fn) {
+        q.state = 2;
+        q.status = HTLR_OK;
+        return;
+      }
+      if (q.outer >= q.max_outer) {
+        q.state = 3;
+        q.status = HTLR_ERR_NOT_CONVERGED;
+        return;
+      }
+      // start a GMRES cycle on A d = r
+      ++q.outer;
+      q.beta = q.rn;
+      q.rtol = std::max(inner_tol, q.tol * q.fn / q.rn);
+      hipLaunchKernelGGL(k_scale_to, dim3(vblocks(N)), dim3(256), 0, S->stream, q.dr, 1.0 / q.beta, q.V, N);
+      std::fill(q.g.begin(), q.g.end(), 0.0);
+      q.g[0] = q.beta;
+      q.k = 0;
+      q.arnoldi = true;
+      return;
+    }
+    const int k = q.k;
+    std::vector<double> h(k + 2);
+    for (int j = 0; j <= k; ++j) h[j] = hh[j] + hh[(m + 1) + j];
+    const double hn = std::sqrt(hh[2 * (m + 1)]);
+    if (!std::isfinite(hn)) {
+      q.state = 3;
+      q.status = HTLR_ERR_NUMERIC;
+      return;
+    }
+    h[k + 1] = hn;
+    double* w = q.V + (int64_t)(k + 1) * N;
+    if (hn > 0) hipLaunchKernelGGL(k_scale_to, dim3(vblocks(N)), dim3(256), 0, S->stream, w, 1.0 / hn, w, N);
+    for (int j = 0; j < k; ++j) {
+      const double t = q.cs[j] * h[j] + q.sn[j] * h[j + 1];
+      h[j + 1] = -q.sn[j] * h[j] + q.cs[j] * h[j + 1];
+      h[j] = t;
+    }
+    const double den = std::hypot(h[k], h[k + 1]);
+    q.cs[k] = den > 0 ? h[k] / den : 1.0;
+    q.sn[k] = den > 0 ? h[k + 1] / den : 0.0;
+    h[k] = den;
+    q.g[k + 1] = -q.sn[k] * q.g[k];
+    q.g[k] = q.cs[k] * q.g[k];
+    for (int j = 0; j <= k; ++j) q.H[(size_t)j * m + k] = h[j];
+    ++q.inner;
+    q.k = k + 1;
+    const bool conv = std::fabs(q.g[k + 1]) <= q.rtol * q.beta || hn == 0.0;
+    if (conv || q.k == m) {
+      // x += V y with y = R^{-1} g; the next tick recomputes the FP64 residual
+      const int kk = q.k;
+      for (int i = kk - 1; i >= 0; --i) {
+        double s = q.g[i];
+        for (int j = i + 1; j < kk; ++j) s -= q.H[(size_t)i * m + j] * q.y[j];
+        q.y[i] = s / q.H[(size_t)i * m + i];
+      }
+      double* yd = q.hdev.as<double>() + 2 * (m + 1) + 2;
+      std::memcpy(q.host.p + 2 * (m + 1) + 2, q.y.data(), kk * sizeof(double));
+      HTLR_HIP(hipMemcpyAsync(yd, q.host.p + 2 * (m + 1) + 2, kk * sizeof(double), hipMemcpyHostToDevice, S->stream));
+      hipLaunchKernelGGL(k_add_vy, dim3(vblocks(N)), dim3(256), 0, S->stream, q.V, N, kk, yd, q.dx, N);
+      q.arnoldi = false;
+    }
+  }
+
+  void retire(Req& q) {
+    Structure* S = q.S;
+    q.result.resize(q.N);
+    HTLR_HIP(hipStreamSynchronize(S->stream));
+    HTLR_HIP(hipMemcpy(q.result.data(), q.dx, q.N * sizeof(double), hipMemcpyDeviceToHost));
+    q.t_done = now();
+    q.dev.release();
+    q.hdev.release();
+    q.host.release();
+    used -= q.dev_bytes;
+    --S->active;
+    S->last_use = q.t_done;
+    q.S = nullptr;
+  }
+
+  void step(int* active, int* queued) {
+    ++st.ticks;
+    admit();
+    std::map<Structure*, std::vector<Req*>> groups;
+    for (auto& kv : reqs)
+      if (kv.second->state == 1) groups[kv.second->S].push_back(kv.second.get());
+    for (auto& g : groups) {
+      g.first->ptr_slot = 0;   // the previous tick ended with a synchronisation
+      issue(g.first, g.second);
+    }
+    for (auto& g : groups) HTLR_HIP(hipStreamSynchronize(g.first->stream));
+    for (auto& g : groups)
+      for (Req* q : g.second) {
+        finish_one(*q);
+        if (q->state >= 2) retire(*q);
+      }
+    int a = 0;
+    for (auto& kv : reqs)
+      if (kv.second->state == 1) ++a;
+    if (active) *active = a;
+    if (queued) *queued = (int)queue.size();
+  }
+};
+
+}  // namespace htlr
+
+struct htlr_server_s : htlr::ServerImpl {};
+
+using namespace htlr;
+
+extern "C" {
+
+htlr_status htlr_server_create(const htlr_server_opts* opts, htlr_server* out) {
+  if (!out) { g_last_error = "out is NULL"; return HTLR_ERR_INVALID; }
+  *out = nullptr;
+  try {
+    auto S = std::make_unique<htlr_server_s>();
+    if (opts) S->o = *opts;
+    if (S->o.max_active <= 0) S->o.max_active = 64;
+    if (S->o.max_batch <= 0) S->o.max_batch = 16;
+    if (S->o.max_batch > 64) fail(HTLR_ERR_INVALID, "max_batch must be <= 64");
+    if (S->o.restart <= 0) S->o.restart = 30;
+    if (S->o.restart > 200) fail(HTLR_ERR_INVALID, "restart too large");
+    const int ip = S->o.inner_prec;
+    if (ip != HTLR_FP64 && ip != HTLR_FP32 && ip != HTLR_BF16_CORE) fail(HTLR_ERR_INVALID, "unknown inner precision");
+    S->inner_tol = ip == HTLR_FP32 ? 1e-6 : (ip == HTLR_BF16_CORE ? 1e-2 : 1e-12);
+    S->budget = S->o.memory_budget;
+    if (!S->budget) {
+      size_t fr = 0, tot = 0;
+      HTLR_HIP(hipMemGetInfo(&fr, &tot));
+      S->budget = (size_t)(0.9 * (double)fr);
+    }
+    *out = S.release();
+    return HTLR_OK;
+  } catch (const Error& e) {
+    return record(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HTLR_ERR_INVALID;
+  }
+}
+
+htlr_status htlr_server_submit(htlr_server S, const htlr_request* r, int64_t* id) {
+  if (!S || !r || !id || !r->f) { g_last_error = "null argument"; return HTLR_ERR_INVALID; }
+  try {
+    auto q = std::make_unique<Req>();
+    q->kernel = r->kernel;
+    q->d = r->d;
+    q->n = r->n;
+    q->p = r->p;
+    q->leaf = r->leaf;
+    q->adm = r->admissibility;
+    q->eta2 = r->eta2 > 0 ? r->eta2 : 1.0;
+    q->tol = r->tol > 0 ? r->tol : 1e-8;
+    q->max_outer = r->max_outer > 0 ? r->max_outer : 50;
+    if (q->d != 2 && q->d != 3) fail(HTLR_ERR_UNSUPPORTED, "d must be 2 or 3");
+    if (q->n < 1) fail(HTLR_ERR_INVALID, "n must be positive");
+    q->N = 1;
+    for (int l = 0; l < q->d; ++l) q->N *= q->n;
+    q->f.assign(r->f, r->f + q->N);
+    if (r->a) q->a.assign(r->a, r->a + q->N);
+    if (r->points) q->points.assign(r->points, r->points + (size_t)q->d * q->n);
+    q->key = ServerImpl::make_key(*q);
+    q->id = S->next_id++;
+    q->t_submit = S->now();
+    *id = q->id;
+    S->queue.push_back(q->id);
+    S->reqs[q->id] = std::move(q);
+    return HTLR_OK;
+  } catch (const Error& e) {
+    return record(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HTLR_ERR_INVALID;
+  }
+}
+
+htlr_status htlr_server_step(htlr_server S, int* active, int* queued) {
+  if (!S) { g_last_error = "null server"; return HTLR_ERR_INVALID; }
+  try {
+    S->step(active, queued);
+    return HTLR_OK;
+  } catch (const Error& e) {
+    return record(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HTLR_ERR_INVALID;
+  }
+}
+
+htlr_status htlr_server_result(htlr_server S, int64_t id, double* u, htlr_request_info* info) {
+  if (!S) { g_last_error = "null server"; return HTLR_ERR_INVALID; }
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) { g_last_error = "unknown request id"; return HTLR_ERR_INVALID; }
+  Req& q = *it->second;
+  if (info) {
+    info->state = q.state;
+    info->status = q.status;
+    info->outer_iters = q.outer;
+    info->inner_iters = q.inner;
+    info->rel_residual = q.fn > 0 ? q.rn / q.fn : 0.0;
+    info->t_submit = q.t_submit;
+    info->t_admit = q.t_admit;
+    info->t_done = q.t_done;
+  }
+  if (q.state < 2) { g_last_error = "request not finished"; return HTLR_ERR_INVALID; }
+  if (u && !q.result.empty()) std::memcpy(u, q.result.data(), q.N * sizeof(double));
+  S->reqs.erase(it);
+  return HTLR_OK;
+}
+
+htlr_status htlr_server_stats(htlr_server S, htlr_server_stats_t* out) {
+  if (!S || !out) { g_last_error = "null argument"; return HTLR_ERR_INVALID; }
+  *out = S->st;
+  out->resident_structures = (int)S->structs.size();
+  out->resident_bytes = S->used;
+  int a = 0;
+  for (auto& kv : S->reqs)
+    if (kv.second->state == 1) ++a;
+  out->active = a;
+  out->queued = (int)S->queue.size();
+  return HTLR_OK;
+}
+
+double htlr_server_clock(htlr_server S) { return S ? S->now() : 0.0; }
+
+void htlr_server_destroy(htlr_server S) {
+  if (!S) return;
+  (void)hipDeviceSynchronize();
+  delete S;
+}
+
+}  // extern "C"
