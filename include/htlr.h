@@ -201,6 +201,24 @@ typedef struct {
 htlr_status htlr_profile_enable(htlr_matrix A, int enable);
 htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, int* count);
 
+/* Autotuner: times variants of the product's kernels for products with
+ * nrhs right-hand sides in precision prec on this matrix (the split of the
+ * core apply's reduction over workgroups, the near-field kernel variant and
+ * its waves per leaf), and keeps the fastest for later products of that
+ * shape.  With the environment variable HTLR_TUNE_CACHE naming a file, results
+ * are read from and appended to it, keyed by (d, n, p, leaf, kernel, grid,
+ * nrhs, prec).  Allocates scratch vectors; synchronises the device. */
+typedef struct {
+  int ks_target;        /* workgroups the core apply aims for when splitting its reduction */
+  int near_kind;        /* 0: VALU row kernel, 1: matrix-core kernel */
+  int near_waves;       /* waves per leaf of the VALU row kernel */
+  int candidates;       /* variants timed (0: taken from the cache) */
+  double ms_default;    /* product time with the built-in choice */
+  double ms_best;       /* product time with the chosen variant */
+} htlr_tune_result;
+
+htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tune_result* out);
+
 /* Releases the handle and all its device memory (synchronises the device). */
 void htlr_free(htlr_matrix A);
 

@@ -56,6 +56,11 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double)]
 
 
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("ks_target", ctypes.c_int), ("near_kind", ctypes.c_int), ("near_waves", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("ms_default", ctypes.c_double), ("ms_best", ctypes.c_double)]
+
+
 class _ProfEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double)]
 
@@ -90,11 +95,12 @@ def lib() -> ctypes.CDLL:
         L.htlr_plan_pairs.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.htlr_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_TuneResult)]
         L.htlr_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.htlr_profile_read.argtypes = [_vp, ctypes.POINTER(_ProfEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("htlr_build", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec", "htlr_solve",
                      "htlr_info", "htlr_plan_counts", "htlr_plan_pairs", "htlr_profile_enable",
-                     "htlr_profile_read"):
+                     "htlr_profile_read", "htlr_autotune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -204,6 +210,13 @@ class HTLRMatrix:
         b = ctypes.c_size_t()
         _check(lib().htlr_workspace_bytes(self._h, nrhs, PRECISIONS[prec], ctypes.byref(b)))
         return b.value
+
+    def autotune(self, nrhs=1, prec="fp64") -> dict:
+        """Time kernel variants for products of this shape; keep the fastest."""
+        r = _TuneResult()
+        _check(lib().htlr_autotune(self._h, nrhs, PRECISIONS[prec] if isinstance(prec, str) else int(prec),
+                                   ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in _TuneResult._fields_}
 
     def profile(self, enable: bool = True):
         """Start (or stop) per-launch hipEvent timing of products; clears the record."""

@@ -347,10 +347,28 @@ __global__ void k_reduce_parts(const TA* __restrict__ parts, TA* __restrict__ H,
 }
 
 // Number of K splits that gives the level enough workgroups to fill the GPU.
-static int pick_ksplit(int64_t base_wgs, int64_t max_list) {
+static int pick_ksplit(int64_t base_wgs, int64_t max_list, int target) {
   int ks = 1;
-  while (ks < 64 && base_wgs * ks < 2048 && max_list / (ks * 2) >= 4) ks *= 2;
+  while (ks < 64 && base_wgs * ks < target && max_list / (ks * 2) >= 4) ks *= 2;
   return ks;
+}
+
+static LevelData::Tiles::Items& items_for(LevelData::Tiles& T, int ks, int nmb, bool frozen) {
+  auto it = T.items.find(ks);
+  if (it != T.items.end()) return it->second;
+  if (frozen) fail(HTLR_ERR_INVALID, "matrix-core work list not reserved");
+  // work items ordered (class, row block, split, tile)
+  std::vector<int32_t> items;
+  for (size_t cl = 0; cl + 1 < T.class_start.size(); ++cl)
+    for (int mb = 0; mb < nmb; ++mb)
+      for (int s = 0; s < ks; ++s)
+        for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
+          items.push_back((int32_t)((t << 12) | (mb << 6) | s));
+  LevelData::Tiles::Items& I = T.items[ks];
+  I.buf.alloc(items.size() * sizeof(int32_t));
+  HTLR_HIP(hipMemcpy(I.buf.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  I.n = (int)items.size();
+  return I;
 }
 
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
@@ -360,22 +378,9 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   LevelData::Tiles& T = tiles_for(A, lv, nb);
   if (T.ntile == 0) return;
   const int nmb = (A.P + kBM - 1) / kBM;
-  const int ks = pick_ksplit(T.ntile * nmb, T.maxlist);
+  const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
   if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
-  // work items ordered (class, row block, split, tile)
-  if (T.items_ks != ks) {
-    if (A.ws.frozen) fail(HTLR_ERR_INVALID, "matrix-core work list not reserved");
-    std::vector<int32_t> items;
-    for (size_t c = 0; c + 1 < T.class_start.size(); ++c)
-      for (int mb = 0; mb < nmb; ++mb)
-        for (int s = 0; s < ks; ++s)
-          for (int64_t t = T.class_start[c]; t < T.class_start[c + 1]; ++t)
-            items.push_back((int32_t)((t << 12) | (mb << 6) | s));
-    T.items.alloc(items.size() * sizeof(int32_t));
-    HTLR_HIP(hipMemcpy(T.items.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    T.nitems = (int)items.size();
-    T.items_ks = ks;
-  }
+  LevelData::Tiles::Items& I = items_for(T, ks, nmb, A.ws.frozen);
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
   const int64_t helems = lv.nbox * (int64_t)nrhs * A.P;
   void* Hout = H;
@@ -387,22 +392,22 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     }
     Hout = parts.ptr;
   }
-  const unsigned nwg = (unsigned)(((T.nitems + 7) / 8) * 8);
+  const unsigned nwg = (unsigned)(((I.n + 7) / 8) * 8);
   const int32_t* tau = T.tau.as<int32_t>();
   const int64_t* ptr = T.ptr.as<int64_t>();
   const int4* off = T.off.as<int4>();
-  const int32_t* items = T.items.as<int32_t>();
+  const int32_t* items = I.buf.as<int32_t>();
   if (prec == HTLR_BF16_CORE)
     hipLaunchKernelGGL(k_core_mfma<uint16_t>, dim3(nwg), dim3(256), 0, st, lv.Gm16.as<uint16_t>(), (const uint16_t*)W,
-                       (const uint16_t*)zero, (float*)Hout, tau, ptr, off, items, T.nitems, ks, helems, A.P, nrhs, nb,
+                       (const uint16_t*)zero, (float*)Hout, tau, ptr, off, items, I.n, ks, helems, A.P, nrhs, nb,
                        lv.B);
   else if (prec == HTLR_FP32)
     hipLaunchKernelGGL(k_core_mfma<float>, dim3(nwg), dim3(256), 0, st, lv.Gm32.as<float>(), (const float*)W,
-                       (const float*)zero, (float*)Hout, tau, ptr, off, items, T.nitems, ks, helems, A.P, nrhs, nb,
+                       (const float*)zero, (float*)Hout, tau, ptr, off, items, I.n, ks, helems, A.P, nrhs, nb,
                        lv.B);
   else
     hipLaunchKernelGGL(k_core_mfma<double>, dim3(nwg), dim3(256), 0, st, lv.Gm64.as<double>(), (const double*)W,
-                       (const double*)zero, (double*)Hout, tau, ptr, off, items, T.nitems, ks, helems, A.P, nrhs, nb,
+                       (const double*)zero, (double*)Hout, tau, ptr, off, items, I.n, ks, helems, A.P, nrhs, nb,
                        lv.B);
   HTLR_HIP(hipGetLastError());
   if (ks > 1) {
@@ -428,24 +433,17 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
   const int nmb = (A.P + kBM - 1) / kBM;
   for (int c = 1; c <= nrhs; ++c) {
     const int nb = core_mfma_nb(c);
-    for (LevelData& lv : A.levels) {
-      if (lv.npairs == 0) continue;
-      LevelData::Tiles& T = tiles_for(A, lv, nb);
-      if (T.ntile == 0) continue;
-      const int ks = pick_ksplit(T.ntile * nmb, T.maxlist);
-      if (T.items_ks != ks) {
-        std::vector<int32_t> items;
-        for (size_t cl = 0; cl + 1 < T.class_start.size(); ++cl)
-          for (int mb = 0; mb < nmb; ++mb)
-            for (int s = 0; s < ks; ++s)
-              for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
-                items.push_back((int32_t)((t << 12) | (mb << 6) | s));
-        T.items.alloc(items.size() * sizeof(int32_t));
-        HTLR_HIP(hipMemcpy(T.items.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        T.nitems = (int)items.size();
-        T.items_ks = ks;
+    for (int prec = 0; prec < 3; ++prec) {
+      const int target = find_tune(A, c, prec).ks_target;
+      const size_t esz = prec == HTLR_FP64 ? 8 : 4;
+      for (LevelData& lv : A.levels) {
+        if (lv.npairs == 0) continue;
+        LevelData::Tiles& T = tiles_for(A, lv, nb);
+        if (T.ntile == 0) continue;
+        const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, target);
+        items_for(T, ks, nmb, false);
+        if (ks > 1) parts_need = std::max(parts_need, (size_t)lv.nbox * c * A.P * ks * esz);
       }
-      if (ks > 1) parts_need = std::max(parts_need, (size_t)lv.nbox * c * A.P * ks * sizeof(double));
     }
   }
   if (A.ws.parts.bytes < parts_need) A.ws.parts.alloc(parts_need);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -66,8 +67,11 @@ struct LevelData {
     DevBuf off;                      // int4 (core id, offset x, y, z) per entry
     std::vector<int64_t> class_start;  // first tile of each parity class
     int64_t maxlist = 0;             // longest offset list of a tile
-    DevBuf items;                    // work items (tile << 12 | row block << 6 | split)
-    int nitems = 0, items_ks = 0;
+    struct Items {
+      DevBuf buf;                    // work items (tile << 12 | row block << 6 | split)
+      int n = 0;
+    };
+    std::map<int, Items> items;      // per number of K splits
   };
   std::vector<Tiles> tiles;
 };
@@ -103,6 +107,13 @@ struct Profiler {
   }
 };
 
+// Kernel variant choices for products of one shape (nrhs, precision).
+struct TuneParams {
+  int ks_target = 2048;              // matrix-core core apply: workgroups aimed for when splitting K
+  int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel
+  int near_nw = 0;                   // VALU row kernel: waves per leaf (0 automatic)
+};
+
 struct htlr_matrix_impl {
   int d = 0, n = 0, p = 0, leaf = 0, L = 0, P = 0, kid = 0;
   int64_t N = 0;
@@ -124,6 +135,8 @@ struct htlr_matrix_impl {
   std::mutex ws_mu;
   Workspace ws;
   Profiler prof;
+  std::map<std::pair<int, int>, TuneParams> tune;   // (nrhs, precision) -> choices
+  TuneParams cur;                    // choices of the product being issued
 };
 
 bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
@@ -132,6 +145,9 @@ void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec);
 // (work buffers, matrix-core work lists, K-split partial sums), then freezes
 // them, so that later products never allocate (graph capture, serving).
 void reserve_workspace(htlr_matrix_impl& A, int nrhs);
+// Choices for a product of this shape: exact match, else the nearest tuned
+// smaller width of the same precision, else the defaults.
+TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec);
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st, DevBuf& parts);
 

@@ -17,6 +17,8 @@
 // launches on a stream are ordered, so the product is deterministic.
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "htlr_device.h"
@@ -762,9 +764,23 @@ struct ProfScope {
   }
 };
 
+TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
+  auto it = A.tune.find({nrhs, prec});
+  if (it != A.tune.end()) return it->second;
+  TuneParams best;
+  int bw = 0;
+  for (auto& kv : A.tune)
+    if (kv.first.second == prec && kv.first.first < nrhs && kv.first.first > bw) {
+      bw = kv.first.first;
+      best = kv.second;
+    }
+  return best;
+}
+
 template <typename T>
 static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st) {
   const int d = A.d, p = A.p, P = A.P, n = A.n, pm1 = p - 1;
+  A.cur = find_tune(A, nrhs, prec);
   const bool f64 = std::is_same<T, double>::value;
   const Plan& pl = A.plan;
   const int m = pl.m[A.L], B = pl.B[A.L];
@@ -777,7 +793,8 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   // near field + diagonal (overwrites f)
   {
   ProfScope ps(A, "near", -1, st);
-  const bool near_mfma = !f64 && A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST && nrhs >= 8;
+  const bool mfma_ok = !f64 && A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST;
+  const bool near_mfma = mfma_ok && (A.cur.near_kind == 1 || (A.cur.near_kind < 0 && nrhs >= 8));
   if (near_mfma) {
     const size_t sh = (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(float) + (size_t)512 * 16 * sizeof(float);
     if (sh > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "near-field working set exceeds LDS");
@@ -794,7 +811,11 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     const int nchunk = (nrhs + rc - 1) / rc;
     // waves per leaf: enough waves to fill the GPU, within the LDS budget
     int nw = 1;
-    while (nw < 4 && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+    if (A.cur.near_nw > 0) {
+      while (nw < A.cur.near_nw && nw < 4 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+    } else {
+      while (nw < 4 && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+    }
     const size_t sh = fixed + per_wave * rc * nw;
     if (sh > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "near-field working set exceeds LDS");
 #define HTLR_NEAR_ROWS(RCV, NWV)                                                                                  \
@@ -949,6 +970,136 @@ htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_pr
     hipStream_t st = (hipStream_t)stream;
     if (prec == HTLR_FP64) run_matvec<double>(*A, (const double*)u, (double*)f, nrhs, prec, st);
     else run_matvec<float>(*A, (const float*)u, (float*)f, nrhs, prec, st);
+    return HTLR_OK;
+  } catch (const Error& e) {
+    return record(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HTLR_ERR_INVALID;
+  }
+}
+
+htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tune_result* out) {
+  try {
+    g_last_error.clear();
+    if (!A) fail(HTLR_ERR_INVALID, "null handle");
+    if (nrhs < 1 || nrhs > 64) fail(HTLR_ERR_INVALID, "nrhs out of range (1..64)");
+    if (prec != HTLR_FP64 && prec != HTLR_FP32 && prec != HTLR_BF16_CORE) fail(HTLR_ERR_INVALID, "unknown precision");
+    if (!(A->precisions & (1 << prec))) fail(HTLR_ERR_UNSUPPORTED, "matrix built without this precision");
+    if (A->ws.frozen) fail(HTLR_ERR_INVALID, "tune before reserving work buffers");
+    htlr_tune_result res{};
+    // cache lookup
+    char key[256];
+    std::snprintf(key, sizeof(key), "d%d_n%d_p%d_leaf%d_k%d_%s_eta%.6g_adm%d_nrhs%d_prec%d", A->d, A->n, A->p, A->leaf,
+                  A->kid, A->uniform ? "uniform" : "tensor", A->eta2, A->adm_kind, nrhs, (int)prec);
+    const char* cache = std::getenv("HTLR_TUNE_CACHE");
+    if (cache && *cache) {
+      FILE* fp = std::fopen(cache, "r");
+      if (fp) {
+        char k2[256];
+        TuneParams t;
+        double md = 0, mb = 0;
+        bool found = false;
+        while (std::fscanf(fp, "%255s %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw, &md, &mb) == 6)
+          if (std::strcmp(k2, key) == 0) {
+            A->tune[{nrhs, (int)prec}] = t;
+            res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
+            found = true;
+          }
+        std::fclose(fp);
+        if (found) {
+          if (out) *out = res;
+          return HTLR_OK;
+        }
+      }
+    }
+    const size_t esz = prec == HTLR_FP64 ? 8 : 4;
+    const size_t bytes = (size_t)A->N * nrhs * esz;
+    DevBuf u, f;
+    u.alloc(bytes);
+    f.alloc(bytes);
+    {
+      // deterministic pseudo-random input (values do not affect timing)
+      std::vector<unsigned char> host(bytes);
+      uint64_t x = 88172645463325252ull;
+      if (esz == 8) {
+        double* hp = reinterpret_cast<double*>(host.data());
+        for (size_t i = 0; i < bytes / 8; ++i) { x ^= x << 13; x ^= x >> 7; x ^= x << 17; hp[i] = (double)(x >> 11) * 0x1.0p-53 - 0.5; }
+      } else {
+        float* hp = reinterpret_cast<float*>(host.data());
+        for (size_t i = 0; i < bytes / 4; ++i) { x ^= x << 13; x ^= x >> 7; x ^= x << 17; hp[i] = (float)((double)(x >> 11) * 0x1.0p-53 - 0.5); }
+      }
+      HTLR_HIP(hipMemcpy(u.ptr, host.data(), bytes, hipMemcpyHostToDevice));
+    }
+    hipStream_t st = nullptr;
+    hipEvent_t e0, e1;
+    HTLR_HIP(hipEventCreate(&e0));
+    HTLR_HIP(hipEventCreate(&e1));
+    auto time_with = [&](const TuneParams& t) -> double {
+      A->tune[{nrhs, (int)prec}] = t;
+      std::lock_guard<std::mutex> lk(A->ws_mu);
+      ensure_workspace(*A, nrhs, prec);
+      auto once = [&]() {
+        if (prec == HTLR_FP64) run_matvec<double>(*A, u.as<double>(), f.as<double>(), nrhs, prec, st);
+        else run_matvec<float>(*A, u.as<float>(), f.as<float>(), nrhs, prec, st);
+      };
+      once();   // warm-up (work lists, buffers)
+      float best = 1e30f;
+      for (int r = 0; r < 3; ++r) {
+        HTLR_HIP(hipEventRecord(e0, st));
+        once();
+        HTLR_HIP(hipEventRecord(e1, st));
+        HTLR_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HTLR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      ++res.candidates;
+      return best;
+    };
+    TuneParams best;                    // defaults
+    res.ms_default = time_with(best);
+    double best_ms = res.ms_default;
+    if (core_mfma_ok(*A, prec))
+      for (int target : {512, 1024, 4096, 8192}) {
+        TuneParams t = best;
+        t.ks_target = target;
+        const double ms = time_with(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+      }
+    const bool near_rows = A->uniform && A->d == 3 && A->plan.m[A->L] <= 8;
+    const bool near_mfma = prec != HTLR_FP64 && A->uniform && A->d == 3 && A->plan.m[A->L] == 8 &&
+                           A->kid != HTLR_K_POLY_TEST;
+    if (near_mfma) {
+      TuneParams t = best;
+      t.near_kind = (nrhs >= 8) ? 0 : 1;   // the variant the defaults did not use
+      const double ms = time_with(t);
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    if (near_rows && (best.near_kind == 0 || (best.near_kind < 0 && !(near_mfma && nrhs >= 8))))
+      for (int nw : {1, 2, 4}) {
+        TuneParams t = best;
+        t.near_kind = near_mfma ? 0 : -1;
+        t.near_nw = nw;
+        const double ms = time_with(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+      }
+    A->tune[{nrhs, (int)prec}] = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    res.ks_target = best.ks_target;
+    res.near_kind = best.near_kind;
+    res.near_waves = best.near_nw;
+    res.ms_best = best_ms;
+    if (cache && *cache) {
+      FILE* fp = std::fopen(cache, "a");
+      if (fp) {
+        std::fprintf(fp, "%s %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw, res.ms_default,
+                     best_ms);
+        std::fclose(fp);
+      }
+    }
+    if (out) *out = res;
     return HTLR_OK;
   } catch (const Error& e) {
     return record(e);

@@ -211,6 +211,13 @@ struct ServerImpl {
     // one slot of cap pointers per fused product of a tick
     S->hptrs.alloc((size_t)S->cap * (2 * ((o.max_active + S->cap - 1) / S->cap) + 2));
     S->partial.alloc((size_t)kRedB * (o.restart + 2) * sizeof(double));
+    if (o.autotune) {
+      // tune the fused product shapes this structure will see
+      for (int w = 1; w <= S->cap; w *= 2) {
+        HTLR_CHECK_ST(htlr_autotune(S->A, w, HTLR_FP64, nullptr));
+        if (o.inner_prec != HTLR_FP64) HTLR_CHECK_ST(htlr_autotune(S->A, w, (htlr_precision)o.inner_prec, nullptr));
+      }
+    }
     {
       std::lock_guard<std::mutex> lk(S->A->ws_mu);
       reserve_workspace(*S->A, S->cap);
