@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 128^3 mixed-precision block")
     ap.add_argument("--cpu-leaves", type=int, default=96)
+    ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
+    ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -191,6 +194,112 @@ def cpu_baseline(w, count, f_gpu):
                       f"processes: {wall:.1f} s wall, {busy:.1f} s CPU"}, err
 
 
+def solve_block(H, torch, np, W):
+    """Warped-grid solve A u = f, f = A u*: GMRES with FP32 inner products and
+    FP64 refinement against plain FP64 GMRES, both to the same FP64 residual."""
+    w = W.WORKLOADS["w3d_exp_warp_n96"]
+    x = W.warped_nodes(w.n)
+    pts = W.grid_points([x] * 3)
+    a = 2.0 + pts[:, 0]
+    t0 = time.time()
+    M = H.htlr_build(np.concatenate([x] * 3), w.kernel, 3, w.n, w.p, w.leaf, a=a, precisions=["fp64", "fp32"])
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    us = torch.tensor(W.solve_target(pts), device="cuda")
+    f = M.matvec(us, prec="fp64")
+    out = {"workload": w.name, "N": w.N, "tol": 1e-10, "build_s": round(build_s, 3)}
+    for inner in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info, st = M.solve(f, tol=1e-10, restart=30, inner_prec=inner, max_inner=600)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"inner_{inner}"] = {
+            "seconds": round(dt, 3), "solves_per_s": round(1.0 / dt, 4), "points_per_s": round(w.N / dt, 1),
+            "rel_residual_fp64": info.rel_residual, "outer_iters": info.outer_iters,
+            "inner_iters": info.inner_iters, "matvecs_fp64": info.matvecs_fp64, "matvecs_inner": info.matvecs_inner,
+            "rel_err_vs_ustar": float(torch.linalg.norm(u - us) / torch.linalg.norm(us)), "status": st}
+    M.free()
+    return out
+
+
+def serve_block(H, np, W, count):
+    """Serving: Poisson arrivals of mixed solve requests (d, n, kernel, p drawn
+    per request, f ~ N(0,1), a = 1 + x_1/2, relative residual 1e-8)."""
+    A = {}
+
+    def a_of(d, n):
+        if (d, n) not in A:
+            A[(d, n)] = 1.0 + 0.5 * W.grid_points([W.uniform_nodes(n)] * d)[:, 0]
+        return A[(d, n)]
+
+    def drain(S, pending):
+        done = {}
+        while pending:
+            S.step()
+            for rid in list(pending):
+                u, info = S.result(rid)
+                if u is not None or info["state"] >= 2:
+                    done[rid] = info
+                    pending.discard(rid)
+        return done
+
+    def run(S, reqs, fs, times):
+        """Submit request i at server time t0 + times[i]; step until done."""
+        t0 = S.clock()
+        pending, done, order = set(), {}, list(range(len(reqs)))
+        arrival = {}
+        i = 0
+        while i < len(order) or pending:
+            now = S.clock() - t0
+            while i < len(order) and times[order[i]] <= now:
+                r = reqs[order[i]]
+                rid = S.submit(fs[order[i]], r.kernel, r.d, r.n, r.p, 8, a=a_of(r.d, r.n), tol=1e-8)
+                arrival[rid] = t0 + times[order[i]]
+                pending.add(rid)
+                i += 1
+            if not pending:
+                time.sleep(max(0.0, min(0.01, times[order[i]] - now)))
+                continue
+            S.step()
+            for rid in list(pending):
+                u, info = S.result(rid)
+                if u is not None or info["state"] >= 2:
+                    info["latency"] = info["t_done"] - arrival[rid]
+                    done[rid] = info
+                    pending.discard(rid)
+        span = S.clock() - t0
+        lat = sorted(v["latency"] for v in done.values())
+        return {"requests": len(done), "makespan_s": round(span, 3), "solves_per_s": round(len(done) / span, 3),
+                "p50_latency_s": round(lat[len(lat) // 2], 4), "p99_latency_s": round(lat[int(0.99 * (len(lat) - 1))], 4),
+                "max_rel_residual": max(v["rel_residual"] for v in done.values()),
+                "all_converged": all(v["status"] == 0 for v in done.values())}
+
+    reqs = W.request_stream(count, rate=1.0)
+    fs = [r.rhs() for r in reqs]
+    out = {"requests": count, "tol": 1e-8, "max_active": 256, "max_batch": 16}
+    for inner in ("fp32", "fp64"):
+        S = H.Server(max_active=256, max_batch=16, inner_prec=inner, use_graphs=True)
+        seen = {}
+        for r in reqs:
+            seen.setdefault((r.d, r.n, r.kernel, r.p), r)
+        t0 = time.time()
+        drain(S, {S.submit(r.rhs(), r.kernel, r.d, r.n, r.p, 8, a=a_of(r.d, r.n), tol=1e-8) for r in seen.values()})
+        warm = time.time() - t0
+        cap = run(S, reqs, fs, [0.0] * count)
+        res = {"structures": len(seen), "warm_build_s": round(warm, 2), "capacity": cap}
+        if inner == "fp32":
+            rate = 0.5 * cap["solves_per_s"]
+            times = [r.arrival / rate for r in reqs]       # request_stream uses unit rate
+            res["poisson_half_capacity"] = dict(run(S, reqs, fs, times), rate_per_s=round(rate, 3))
+        st = S.stats()
+        res["server"] = {k: st[k] for k in ("ticks", "fused_products", "graph_launches", "resident_structures",
+                                            "resident_bytes")}
+        S.close()
+        out[f"inner_{inner}"] = res
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -254,6 +363,14 @@ def main():
             del f3
             torch.cuda.empty_cache()
         out["w3d_invr_n128_r16"] = block
+    if not args.no_solve:
+        print("[bench] warped-grid solve (FP32-IR and FP64 GMRES)", file=sys.stderr, flush=True)
+        out["w3d_exp_warp_n96_solve"] = solve_block(H, torch, np, W)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        print(f"[bench] serving: {args.serve_requests} mixed requests", file=sys.stderr, flush=True)
+        out["serving"] = serve_block(H, np, W, args.serve_requests)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         print(f"[bench] cpu_baseline: oracle on {args.cpu_leaves} leaves", file=sys.stderr, flush=True)
         cb, err = cpu_baseline(w, args.cpu_leaves, f_host)
