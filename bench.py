@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
     ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--summarize-profile", default=None, metavar="DIR",
+                    help="print a markdown summary of a rocprofv3 run directory (stats/, fetch/, write/) and exit")
+    ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -300,8 +303,52 @@ def serve_block(H, np, W, count):
     return out
 
 
+def summarize_profile(d, command, workload, prec):
+    """Markdown summary of rocprofv3 CSV output: kernel statistics plus HBM
+    traffic from FETCH_SIZE / WRITE_SIZE, each calibrated by the counter value
+    of the run's 1 GiB device copy (largest copy dispatch)."""
+    import csv
+    import glob
+
+    def rows(sub, name):
+        f = glob.glob(os.path.join(d, sub, "**", name), recursive=True)
+        return list(csv.DictReader(open(f[0]))) if f else []
+
+    def short(k):
+        k = k.replace("(anonymous namespace)::", "")
+        return k.split("(")[0].replace("void ", "")[:70]
+
+    lines = [f"# rocprofv3 summary: {workload}, {prec}", "", "Command:", "", "```", command, "```", ""]
+    st = rows("stats", "*kernel_stats.csv")
+    lines += ["| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in st[:14]:
+        lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                     f"{float(r['TotalDurationNs'])/1e6:.2f} | {float(r['Percentage']):.1f} |")
+    traffic = {}
+    for sub, name in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        cc = rows(sub, "*counter_collection.csv")
+        if not cc:
+            continue
+        copies = [float(r["Counter_Value"]) for r in cc if "copy" in r["Kernel_Name"].lower()
+                  or "elementwise" in r["Kernel_Name"]]
+        cal = (1 << 20) / max(copies) if copies else 1.0          # KiB expected for 1 GiB / KiB counted
+        agg = {}
+        for r in cc:
+            agg.setdefault(short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        lines += ["", f"{name} per dispatch (KiB as counted; calibration factor {cal:.3f} from the 1 GiB copy):", "",
+                  "| kernel | dispatches | mean KiB | max KiB | calibrated max GB |", "|---|---|---|---|---|"]
+        for k, v in sorted(agg.items(), key=lambda kv: -max(kv[1]))[:10]:
+            lines.append(f"| {k} | {len(v)} | {sum(v)/len(v):.0f} | {max(v):.0f} | {max(v)*cal*1024/1e9:.3f} |")
+            traffic.setdefault(k, {})[name] = max(v) * cal * 1024
+    return "\n".join(lines) + "\n", traffic
+
+
 def main():
     args = parse()
+    if args.summarize_profile:
+        md, _ = summarize_profile(args.summarize_profile, args.profile_command, args.workload, args.prec or "")
+        print(md)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
               file=sys.stderr)
