@@ -35,8 +35,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 128;   // output rows per workgroup
-constexpr int kBN = 128;   // output columns per workgroup
+constexpr int kBNmax = 128;  // widest output tile (columns)
 constexpr int kCB = 64;    // bytes of K per row per stage
 
 template <typename TE> struct AccT { using type = float; };
@@ -53,18 +52,23 @@ __device__ __forceinline__ const TE* col_src(const TE* W, const TE* zero, int ct
   return ok ? W + (sg * nrhs + cr) * P : zero;
 }
 
-template <typename TE>
-__global__ __launch_bounds__(256, 2) void k_core_mfma(
+// BMT x BNT output tile per workgroup; 2 BMT threads; waves arranged
+// (BMT / 64) x 2, each owning 64 rows x BNT/2 columns.
+template <typename TE, int BMT, int BNT>
+__global__ __launch_bounds__(2 * BMT) void k_core_mfma(
     const TE* __restrict__ G, const TE* __restrict__ W, const TE* __restrict__ zero,
     typename AccT<TE>::type* __restrict__ H, const int32_t* __restrict__ tile_tau,
     const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
     int nitems, int ksplit, int64_t part_stride, int P, int nrhs, int NB, int B) {
   using TA = typename AccT<TE>::type;
+  constexpr int NT = 2 * BMT;             // threads
   constexpr int E = 16 / sizeof(TE);      // elements per 16-byte chunk
   constexpr int KBE = kCB / sizeof(TE);   // K elements per stage
   constexpr int LDW = KBE + E;            // padded LDS row (80 bytes)
-  __shared__ __align__(16) TE As[2][kBM * LDW];
-  __shared__ __align__(16) TE Bs[2][kBN * LDW];
+  constexpr int NBH = 2 * BNT / BMT;      // B chunks staged per thread (A: 2)
+  constexpr int WNC = BNT / 2;            // columns per wave
+  __shared__ __align__(16) TE As[2][BMT * LDW];
+  __shared__ __align__(16) TE Bs[2][BNT * LDW];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // Work item of this workgroup.  Workgroups are dealt to the 8 XCDs round
@@ -75,20 +79,25 @@ __global__ __launch_bounds__(256, 2) void k_core_mfma(
   if (q >= nitems) return;
   const int item = items[q];
   const int tile = item >> 12;
-  const int m0 = ((item >> 6) & 63) * kBM;
+  const int m0 = ((item >> 6) & 63) * BMT;
   const int split = item & 63;
   const int part = tid & 3;               // 16-byte chunk within a 64-byte row slice
-  const int sr0 = tid >> 2, sr1 = (tid >> 2) + 64;
-  const int arow0 = m0 + sr0, arow1 = m0 + sr1;
+  const int srow = tid >> 2;              // staged row / column, plus multiples of NT/4
+  const int arow0 = m0 + srow, arow1 = m0 + srow + NT / 4;
 
-  // the two columns staged by this thread: target box, rhs, box coordinates
-  const int b0 = sr0 / nrhs, b1 = sr1 / nrhs;
-  const int cr0 = sr0 % nrhs, cr1 = sr1 % nrhs;
-  const int ct0 = (b0 < NB) ? tile_tau[(int64_t)tile * NB + b0] : -1;
-  const int ct1 = (b1 < NB) ? tile_tau[(int64_t)tile * NB + b1] : -1;
-  const int t0c = ct0 < 0 ? 0 : ct0, t1c = ct1 < 0 ? 0 : ct1;
-  const int cx0 = t0c % B, cy0 = (t0c / B) % B, cz0 = t0c / (B * B);
-  const int cx1 = t1c % B, cy1 = (t1c / B) % B, cz1 = t1c / (B * B);
+  // columns staged by this thread: target box, rhs, box coordinates
+  int ct[NBH], cr[NBH], cx[NBH], cy[NBH], cz[NBH];
+#pragma unroll
+  for (int h = 0; h < NBH; ++h) {
+    const int col = srow + h * (NT / 4);
+    const int b = col / nrhs;
+    cr[h] = col % nrhs;
+    ct[h] = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
+    const int t = ct[h] < 0 ? 0 : ct[h];
+    cx[h] = t % B;
+    cy[h] = (t / B) % B;
+    cz[h] = t / (B * B);
+  }
 
   int64_t e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
   {
@@ -103,27 +112,31 @@ __global__ __launch_bounds__(256, 2) void k_core_mfma(
   const int64_t PP = (int64_t)P * P;
   const uint4 z4 = make_uint4(0, 0, 0, 0);
 
+  static_assert(NBH == 1 || NBH == 2, "one or two staged B columns per thread");
   const TE* gA = G;
   const TE* gB0 = zero;
   const TE* gB1 = zero;
   uint4 ra0 = z4, ra1 = z4, rb0 = z4, rb1 = z4;
+  const int ct0 = ct[0], cr0 = cr[0], cx0 = cx[0], cy0 = cy[0], cz0 = cz[0];
+  const int ct1 = ct[NBH - 1], cr1 = cr[NBH - 1], cx1 = cx[NBH - 1], cy1 = cy[NBH - 1], cz1 = cz[NBH - 1];
 
   const int wm = wv >> 1, wn = wv & 1;
   constexpr bool k16 = std::is_same<TE, double>::value;   // 16x16 tiles for f64
-  constexpr int TI = k16 ? 4 : 2;                          // sub-tiles per wave per dim
+  constexpr int TM = k16 ? 16 : 32;                        // MFMA tile side
+  constexpr int TI = 64 / TM, TJ = WNC / TM;               // MFMA tiles per wave
   using AccV = typename std::conditional<k16, f64x4, f32x16>::type;
-  AccV acc[TI][TI];
+  AccV acc[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < TI; ++j) acc[i][j] = AccV{};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = AccV{};
 
-#define HTLR_SET_DELTA(EIDX)                                             \
-  {                                                                      \
-    const int4 o_ = tile_off[EIDX];                                      \
-    gA = G + (int64_t)o_.x * PP;                                         \
-    gB0 = col_src(W, zero, ct0, cx0, cy0, cz0, cr0, o_, B, nrhs, P);     \
-    gB1 = col_src(W, zero, ct1, cx1, cy1, cz1, cr1, o_, B, nrhs, P);     \
+#define HTLR_SET_DELTA(EIDX)                                                       \
+  {                                                                                \
+    const int4 o_ = tile_off[EIDX];                                                \
+    gA = G + (int64_t)o_.x * PP;                                                   \
+    gB0 = col_src(W, zero, ct0, cx0, cy0, cz0, cr0, o_, B, nrhs, P);               \
+    if constexpr (NBH == 2) gB1 = col_src(W, zero, ct1, cx1, cy1, cz1, cr1, o_, B, nrhs, P); \
   }
 #define HTLR_GLOAD(K0)                                                                                       \
   {                                                                                                          \
@@ -132,14 +145,14 @@ __global__ __launch_bounds__(256, 2) void k_core_mfma(
     ra0 = (kin_ && arow0 < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)arow0 * P + k_) : z4;         \
     ra1 = (kin_ && arow1 < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)arow1 * P + k_) : z4;         \
     rb0 = kin_ ? *reinterpret_cast<const uint4*>(gB0 + k_) : z4;                                             \
-    rb1 = kin_ ? *reinterpret_cast<const uint4*>(gB1 + k_) : z4;                                             \
+    if constexpr (NBH == 2) rb1 = kin_ ? *reinterpret_cast<const uint4*>(gB1 + k_) : z4;                     \
   }
-#define HTLR_SSTORE(BUF)                                                       \
-  {                                                                            \
-    *reinterpret_cast<uint4*>(&As[BUF][sr0 * LDW + part * E]) = ra0;           \
-    *reinterpret_cast<uint4*>(&As[BUF][sr1 * LDW + part * E]) = ra1;           \
-    *reinterpret_cast<uint4*>(&Bs[BUF][sr0 * LDW + part * E]) = rb0;           \
-    *reinterpret_cast<uint4*>(&Bs[BUF][sr1 * LDW + part * E]) = rb1;           \
+#define HTLR_SSTORE(BUF)                                                                        \
+  {                                                                                             \
+    *reinterpret_cast<uint4*>(&As[BUF][srow * LDW + part * E]) = ra0;                           \
+    *reinterpret_cast<uint4*>(&As[BUF][(srow + NT / 4) * LDW + part * E]) = ra1;                \
+    *reinterpret_cast<uint4*>(&Bs[BUF][srow * LDW + part * E]) = rb0;                           \
+    if constexpr (NBH == 2) *reinterpret_cast<uint4*>(&Bs[BUF][(srow + NT / 4) * LDW + part * E]) = rb1; \
   }
 
   if (nstage > 0) {
@@ -159,44 +172,49 @@ __global__ __launch_bounds__(256, 2) void k_core_mfma(
         if (ksn == 0) HTLR_SET_DELTA(en);
         HTLR_GLOAD(ksn * KBE);
       }
-      const TE* Asb = As[cur];
-      const TE* Bsb = Bs[cur];
+      const TE* Asb = As[cur] + (wm * 64) * LDW;
+      const TE* Bsb = Bs[cur] + (wn * WNC) * LDW;
       if constexpr (std::is_same<TE, uint16_t>::value) {
 #pragma unroll
         for (int kk = 0; kk < KBE; kk += 16) {
-          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Asb[(wm * 64 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&Asb[(wm * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-          const bf16x8 bb0 = *reinterpret_cast<const bf16x8*>(&Bsb[(wn * 64 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-          const bf16x8 bb1 = *reinterpret_cast<const bf16x8*>(&Bsb[(wn * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bb0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bb1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bb0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bb1, acc[1][1], 0, 0, 0);
+          bf16x8 a[TI], b[TJ];
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(&Asb[(i * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(&Bsb[(j * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
       } else if constexpr (std::is_same<TE, float>::value) {
 #pragma unroll
         for (int kk = 0; kk < KBE; kk += 2) {
-          const float a0 = Asb[(wm * 64 + (lane & 31)) * LDW + kk + (lane >> 5)];
-          const float a1 = Asb[(wm * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
-          const float bb0 = Bsb[(wn * 64 + (lane & 31)) * LDW + kk + (lane >> 5)];
-          const float bb1 = Bsb[(wn * 64 + 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
-          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bb0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bb1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bb0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bb1, acc[1][1], 0, 0, 0);
+          float a[TI], b[TJ];
+#pragma unroll
+          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
       } else {
 #pragma unroll
         for (int kk = 0; kk < KBE; kk += 4) {
-          double a[4], b[4];
+          double a[TI], b[TJ];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = Asb[(wm * 64 + i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
+          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = Bsb[(wn * 64 + j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
+          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < TI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
       }
       if (more) HTLR_SSTORE(cur ^ 1);
@@ -213,13 +231,13 @@ __global__ __launch_bounds__(256, 2) void k_core_mfma(
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < TI; ++j) {
+    for (int j = 0; j < TJ; ++j) {
+      const int col = wn * WNC + j * TM + (lane & (TM - 1));
+      const int b = col / nrhs, r = col % nrhs;
+      const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
+      if (t < 0) continue;
+      TA* Ho = H + ((int64_t)t * nrhs + r) * P;
       if constexpr (k16) {
-        const int col = wn * 64 + j * 16 + (lane & 15);
-        const int b = col / nrhs, r = col % nrhs;
-        const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
-        if (t < 0) continue;
-        TA* Ho = H + ((int64_t)t * nrhs + r) * P;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           // f64 16x16x4 accumulator: register v holds row lane/16 + 4 v
@@ -227,11 +245,6 @@ __global__ __launch_bounds__(256, 2) void k_core_mfma(
           if (row < P) Ho[row] = acc[i][j][v];
         }
       } else {
-        const int col = wn * 64 + j * 32 + (lane & 31);
-        const int b = col / nrhs, r = col % nrhs;
-        const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
-        if (t < 0) continue;
-        TA* Ho = H + ((int64_t)t * nrhs + r) * P;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int row = m0 + wm * 64 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
@@ -329,10 +342,24 @@ static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
   return T;
 }
 
-int core_mfma_nb(int nrhs) {
+static int core_mfma_nb(int nrhs, int bnt) {
   int nb = 1;
-  while (nb * 2 * nrhs <= kBN) nb *= 2;
+  while (nb * 2 * nrhs <= bnt) nb *= 2;
   return nb;
+}
+
+// Tile shape for one level: 1 = 128x128, 2 = 128x64 (few columns), 3 = 256x128.
+static int pick_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
+  if (A.cur.tile >= 1 && A.cur.tile <= 3) return A.cur.tile;
+  const int64_t class_boxes = lv.nbox >> A.d;
+  if (class_boxes * nrhs <= 64) return 2;
+  if (prec == HTLR_BF16_CORE && A.P >= 256) return 3;
+  return 1;
+}
+
+static void variant_shape(int v, int* bmt, int* bnt) {
+  *bmt = v == 3 ? 256 : 128;
+  *bnt = v == 2 ? 64 : 128;
 }
 
 // Sums the K-split partial results in a fixed order: H = sum_s part_s.
@@ -354,7 +381,8 @@ static int pick_ksplit(int64_t base_wgs, int64_t max_list, int target) {
 }
 
 static LevelData::Tiles::Items& items_for(LevelData::Tiles& T, int ks, int nmb, bool frozen) {
-  auto it = T.items.find(ks);
+  const int key = ks + 64 * nmb;
+  auto it = T.items.find(key);
   if (it != T.items.end()) return it->second;
   if (frozen) fail(HTLR_ERR_INVALID, "matrix-core work list not reserved");
   // work items ordered (class, row block, split, tile)
@@ -364,20 +392,33 @@ static LevelData::Tiles::Items& items_for(LevelData::Tiles& T, int ks, int nmb, 
       for (int s = 0; s < ks; ++s)
         for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
           items.push_back((int32_t)((t << 12) | (mb << 6) | s));
-  LevelData::Tiles::Items& I = T.items[ks];
+  LevelData::Tiles::Items& I = T.items[key];
   I.buf.alloc(items.size() * sizeof(int32_t));
   HTLR_HIP(hipMemcpy(I.buf.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   I.n = (int)items.size();
   return I;
 }
 
+template <typename TE, int BMT, int BNT>
+static void launch_variant(const TE* G, const TE* W, const TE* zero, void* H, const int32_t* tau, const int64_t* ptr,
+                           const int4* off, const LevelData::Tiles::Items& I, int ks, int64_t helems, int P, int nrhs,
+                           int nb, int B, hipStream_t st) {
+  using TA = typename AccT<TE>::type;
+  const unsigned nwg = (unsigned)(((I.n + 7) / 8) * 8);
+  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(2 * BMT), 0, st, G, W, zero, (TA*)H, tau, ptr, off,
+                     I.buf.as<int32_t>(), I.n, ks, helems, P, nrhs, nb, B);
+}
+
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st, DevBuf& parts) {
-  if (nrhs > kBN) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
-  const int nb = core_mfma_nb(nrhs);
+  if (nrhs > kBNmax) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
+  const int var = pick_variant(A, lv, nrhs, prec);
+  int bmt, bnt;
+  variant_shape(var, &bmt, &bnt);
+  const int nb = core_mfma_nb(nrhs, bnt);
   LevelData::Tiles& T = tiles_for(A, lv, nb);
   if (T.ntile == 0) return;
-  const int nmb = (A.P + kBM - 1) / kBM;
+  const int nmb = (A.P + bmt - 1) / bmt;
   const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
   if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
   LevelData::Tiles::Items& I = items_for(T, ks, nmb, A.ws.frozen);
@@ -392,23 +433,26 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     }
     Hout = parts.ptr;
   }
-  const unsigned nwg = (unsigned)(((I.n + 7) / 8) * 8);
   const int32_t* tau = T.tau.as<int32_t>();
   const int64_t* ptr = T.ptr.as<int64_t>();
   const int4* off = T.off.as<int4>();
-  const int32_t* items = I.buf.as<int32_t>();
-  if (prec == HTLR_BF16_CORE)
-    hipLaunchKernelGGL(k_core_mfma<uint16_t>, dim3(nwg), dim3(256), 0, st, lv.Gm16.as<uint16_t>(), (const uint16_t*)W,
-                       (const uint16_t*)zero, (float*)Hout, tau, ptr, off, items, I.n, ks, helems, A.P, nrhs, nb,
-                       lv.B);
-  else if (prec == HTLR_FP32)
-    hipLaunchKernelGGL(k_core_mfma<float>, dim3(nwg), dim3(256), 0, st, lv.Gm32.as<float>(), (const float*)W,
-                       (const float*)zero, (float*)Hout, tau, ptr, off, items, I.n, ks, helems, A.P, nrhs, nb,
-                       lv.B);
-  else
-    hipLaunchKernelGGL(k_core_mfma<double>, dim3(nwg), dim3(256), 0, st, lv.Gm64.as<double>(), (const double*)W,
-                       (const double*)zero, (double*)Hout, tau, ptr, off, items, I.n, ks, helems, A.P, nrhs, nb,
-                       lv.B);
+#define HTLR_LV(TE, GPTR)                                                                                          \
+  switch (var) {                                                                                                 \
+    case 2: launch_variant<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
+                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+    case 3: launch_variant<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems, \
+                                         A.P, nrhs, nb, lv.B, st); break;                                        \
+    default: launch_variant<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks,       \
+                                          helems, A.P, nrhs, nb, lv.B, st); break;                               \
+  }
+  if (prec == HTLR_BF16_CORE) {
+    HTLR_LV(uint16_t, lv.Gm16.as<uint16_t>());
+  } else if (prec == HTLR_FP32) {
+    HTLR_LV(float, lv.Gm32.as<float>());
+  } else {
+    HTLR_LV(double, lv.Gm64.as<double>());
+  }
+#undef HTLR_LV
   HTLR_HIP(hipGetLastError());
   if (ks > 1) {
     const int blocks = (int)std::min<int64_t>((helems + 255) / 256, 4096);
@@ -430,22 +474,25 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
     return;
   }
   size_t parts_need = 0;
-  const int nmb = (A.P + kBM - 1) / kBM;
+  const TuneParams saved = A.cur;
   for (int c = 1; c <= nrhs; ++c) {
-    const int nb = core_mfma_nb(c);
     for (int prec = 0; prec < 3; ++prec) {
-      const int target = find_tune(A, c, prec).ks_target;
+      A.cur = find_tune(A, c, prec);
       const size_t esz = prec == HTLR_FP64 ? 8 : 4;
       for (LevelData& lv : A.levels) {
         if (lv.npairs == 0) continue;
-        LevelData::Tiles& T = tiles_for(A, lv, nb);
+        int bmt, bnt;
+        variant_shape(pick_variant(A, lv, c, prec), &bmt, &bnt);
+        LevelData::Tiles& T = tiles_for(A, lv, core_mfma_nb(c, bnt));
         if (T.ntile == 0) continue;
-        const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, target);
+        const int nmb = (A.P + bmt - 1) / bmt;
+        const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
         items_for(T, ks, nmb, false);
         if (ks > 1) parts_need = std::max(parts_need, (size_t)lv.nbox * c * A.P * ks * esz);
       }
     }
   }
+  A.cur = saved;
   if (A.ws.parts.bytes < parts_need) A.ws.parts.alloc(parts_need);
   A.ws.frozen = true;
 }

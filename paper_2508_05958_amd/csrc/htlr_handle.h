@@ -112,6 +112,7 @@ struct TuneParams {
   int ks_target = 2048;              // matrix-core core apply: workgroups aimed for when splitting K
   int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel
   int near_nw = 0;                   // VALU row kernel: waves per leaf (0 automatic)
+  int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128
 };
 
 struct htlr_matrix_impl {

@@ -1000,7 +1000,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         TuneParams t;
         double md = 0, mb = 0;
         bool found = false;
-        while (std::fscanf(fp, "%255s %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw, &md, &mb) == 6)
+        while (std::fscanf(fp, "%255s %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw, &t.tile, &md,
+                           &mb) == 7)
           if (std::strcmp(k2, key) == 0) {
             A->tune[{nrhs, (int)prec}] = t;
             res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
@@ -1060,13 +1061,20 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     TuneParams best;                    // defaults
     res.ms_default = time_with(best);
     double best_ms = res.ms_default;
-    if (core_mfma_ok(*A, prec))
+    if (core_mfma_ok(*A, prec)) {
+      for (int tile : {1, 2, 3}) {
+        TuneParams t = best;
+        t.tile = tile;
+        const double ms = time_with(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+      }
       for (int target : {512, 1024, 4096, 8192}) {
         TuneParams t = best;
         t.ks_target = target;
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
+    }
     const bool near_rows = A->uniform && A->d == 3 && A->plan.m[A->L] <= 8;
     const bool near_mfma = prec != HTLR_FP64 && A->uniform && A->d == 3 && A->plan.m[A->L] == 8 &&
                            A->kid != HTLR_K_POLY_TEST;
@@ -1094,8 +1102,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "a");
       if (fp) {
-        std::fprintf(fp, "%s %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw, res.ms_default,
-                     best_ms);
+        std::fprintf(fp, "%s %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw, best.tile,
+                     res.ms_default, best_ms);
         std::fclose(fp);
       }
     }

@@ -63,3 +63,39 @@ def test_server_with_autotune(torch):
         S.close()
     for a, b in zip(*outs):
         assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 10 * TS.TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile):
+    """Force each matrix-core tile shape (128x128, 128x64, 256x128) through
+    the tuner's cache file and compare with the oracle (FP64) or with the
+    GPU FP64 product (FP32, BF16)."""
+    import paper_2508_05958_amd as H
+    from oracle import geometry, htlr
+    _say(f"[gpu] forced tile {tile} {prec}")
+    n, p, leaf, nrhs = 32, 6, 8, 3
+    pid = {"fp64": 0, "fp32": 1, "bf16": 2}[prec]
+    cache = tmp_path / "tune.txt"
+    key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
+    cache.write_text(f"{key} 2048 -1 0 {tile} 1.0 1.0\n")
+    monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
+    g = geometry.uniform_grid(3, n)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    u = np.random.default_rng(tile).standard_normal((g.N, nrhs))
+    M = H.htlr_build(None, "inv_r", 3, n, p, leaf, a=a)
+    ref_t = torch.tensor(u.T.copy(), dtype=torch.float64, device="cuda").t()
+    f_ref = M.matvec(ref_t, prec="fp64").cpu().numpy()
+    r = M.autotune(nrhs, prec)
+    assert r["candidates"] == 0
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ut = torch.tensor(u.T.copy(), dtype=dt, device="cuda").t()
+    f = M.matvec(ut, prec=prec).double().cpu().numpy()
+    if prec == "fp64":
+        O = htlr.HTLR(g, "inv_r", p, leaf, a)
+        leaves = O.tree.leaves()
+        pick = [leaves[i] for i in (0, 21, 42, 63)]
+        fo = O.matvec(u, pick)
+        assert np.linalg.norm(f[O.leaf_rows(pick)] - fo) / np.linalg.norm(fo) <= 1e-12
+    tol = {"fp64": 1e-13, "fp32": 1e-5, "bf16": 5e-3}[prec]
+    assert np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref) <= tol
