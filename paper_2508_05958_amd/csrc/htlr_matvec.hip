@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_near_uniform(
 // for m*m*RC FMAs.
 // With NW waves per leaf, wave w takes every NW-th source box and the
 // partial sums are added in wave order through LDS.
-template <int KID, typename T, int RC, int NW>
+template <int KID, typename T, int RC, int NW, bool FULL>
 __global__ __launch_bounds__(64 * NW) void k_near_rows(
     const T* __restrict__ u, T* __restrict__ f, const T* __restrict__ a, const int64_t* __restrict__ nptr,
     const int32_t* __restrict__ nsrc, const T* __restrict__ table, int tsize, int n, int m, int B, int nrhs, T h,
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(64 * NW) void k_near_rows(
   for (int64_t e0 = ebeg; e0 < eend; e0 += NW) {
     const int64_t e = e0 + wv;
     const bool have = e < eend;
-    const int sg = have ? nsrc[e] : 0;
+    const int sg = __builtin_amdgcn_readfirstlane(have ? nsrc[e] : 0);   // one source box per wave
     const int sb0 = sg % B, sb1 = (sg / B) % B, sb2 = sg / (B * B);
     __syncthreads();
     for (int idx = lane; have && idx < M * RC; idx += 64) {
@@ -175,6 +175,9 @@ __global__ __launch_bounds__(64 * NW) void k_near_rows(
     __syncthreads();
     if (!active || !have) continue;
     const int D = (tb0 - sb0) * m;   // I0 - J0 = D + (i0 - j0)
+    int sq[2 * MM - 1];              // (D + dl)^2 for dl = -(MM-1)..MM-1, wave-uniform
+#pragma unroll
+    for (int k = 0; k < 2 * MM - 1; ++k) sq[k] = __builtin_amdgcn_readfirstlane((D + k - (MM - 1)) * (D + k - (MM - 1)));
     for (int j2 = 0; j2 < m; ++j2) {
       const int d2 = I2 - (sb2 * m + j2);
       for (int j1 = 0; j1 < m; ++j1) {
@@ -186,7 +189,8 @@ __global__ __launch_bounds__(64 * NW) void k_near_rows(
           for (int k = 0; k < 2 * MM - 1; ++k) {
             const int dl = k - (MM - 1);
             const int dd = D + dl;
-            tv[k] = (dl > -m && dl < m) ? tab[base + dd * dd] : T(0);
+            if constexpr (FULL) tv[k] = tab[base + sq[k]];
+            else tv[k] = (dl > -m && dl < m) ? tab[base + dd * dd] : T(0);
           }
         } else {
           const T f12 = w0 * ipow(T(1) + T(kPolyADev[1]) * (h * d1), pm1) * ipow(T(1) + T(kPolyADev[2]) * (h * d2), pm1);
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(64 * NW) void k_near_rows(
         const T* ur = us + (size_t)(m * j1 + m * m * j2) * RC;
 #pragma unroll
         for (int j0 = 0; j0 < MM; ++j0) {
-          if (j0 >= m) break;
+          if (!FULL && j0 >= m) break;
           T uv[RC];
 #pragma unroll
           for (int r = 0; r < RC; ++r) uv[r] = ur[j0 * RC + r];
@@ -252,16 +256,19 @@ __global__ __launch_bounds__(64 * NW) void k_near_rows(
 // K(i, j) = T[|I - J|^2] read from the LDS table, B = u_sigma staged in LDS.
 // Each of the 4 waves owns 128 target rows (8 MFMA tiles).
 typedef float htlr_f32x4 __attribute__((ext_vector_type(4)));
+typedef double htlr_f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_near_mfma(const float* __restrict__ u, float* __restrict__ f,
-                                                    const float* __restrict__ a, const int64_t* __restrict__ nptr,
-                                                    const int32_t* __restrict__ nsrc, const float* __restrict__ table,
+template <typename T>
+__global__ __launch_bounds__(256) void k_near_mfma(const T* __restrict__ u, T* __restrict__ f,
+                                                    const T* __restrict__ a, const int64_t* __restrict__ nptr,
+                                                    const int32_t* __restrict__ nsrc, const T* __restrict__ table,
                                                     int tsize, int n, int B, int nrhs) {
+  using V4 = typename std::conditional<std::is_same<T, double>::value, htlr_f64x4, htlr_f32x4>::type;
   constexpr int m = 8, M = 512;
   extern __shared__ unsigned char smem_raw[];
-  float* tab = reinterpret_cast<float*>(smem_raw);
+  T* tab = reinterpret_cast<T*>(smem_raw);
   const int tpad = (tsize + 3) & ~3;
-  float* us = tab + tpad;                 // [M][16]
+  T* us = tab + tpad;                     // [M/2][16]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tau = blockIdx.x;
   const int r0 = blockIdx.y * 16;
@@ -277,47 +284,57 @@ __global__ __launch_bounds__(256) void k_near_mfma(const float* __restrict__ u, 
   for (int t = 0; t < 4; ++t) Iy[t] = tb1 * m + ((2 * t + (l15 >> 3)) & 7);
 #pragma unroll
   for (int t = 0; t < 2; ++t) Iz[t] = tb2 * m + 2 * wv + t;
-  htlr_f32x4 acc[8];
+  V4 acc[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = htlr_f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 8; ++t) acc[t] = V4{T(0), T(0), T(0), T(0)};
   const int jl = lane >> 4, rl = lane & 15;
+  constexpr int JH = M / 2;               // source points staged at a time
   for (int64_t e = nptr[tau]; e < nptr[tau + 1]; ++e) {
     const int sg = nsrc[e];
     const int sb0 = sg % B, sb1 = (sg / B) % B, sb2 = sg / (B * B);
-    __syncthreads();
-    for (int idx = tid; idx < M * 16; idx += 256) {
-      const int j = idx % M, r = idx / M;
-      us[j * 16 + r] = (r0 + r < nrhs)
-                           ? u[(int64_t)(r0 + r) * N + lin3(sb0 * m + (j & 7), sb1 * m + ((j >> 3) & 7), sb2 * m + (j >> 6), n)]
-                           : 0.f;
-    }
-    __syncthreads();
-    for (int j0 = 0; j0 < M; j0 += 4) {
-      const int j = j0 + jl;
-      const int dx = Ix - (sb0 * m + (j & 7));
-      const int jy = sb1 * m + ((j >> 3) & 7), jz = sb2 * m + (j >> 6);
-      const float b = us[j * 16 + rl];
-      const int dx2 = dx * dx;
-      int dy2[4], dz2[2];
+    for (int half = 0; half < 2; ++half) {
+      const int jb = half * JH;
+      __syncthreads();
+      for (int idx = tid; idx < JH * 16; idx += 256) {
+        const int j = jb + idx % JH, r = idx / JH;
+        us[(j - jb) * 16 + r] =
+            (r0 + r < nrhs)
+                ? u[(int64_t)(r0 + r) * N + lin3(sb0 * m + (j & 7), sb1 * m + ((j >> 3) & 7), sb2 * m + (j >> 6), n)]
+                : T(0);
+      }
+      __syncthreads();
+      for (int j0 = jb; j0 < jb + JH; j0 += 4) {
+        const int j = j0 + jl;
+        const int dx = Ix - (sb0 * m + (j & 7));
+        const int jy = sb1 * m + ((j >> 3) & 7), jz = sb2 * m + (j >> 6);
+        const T b = us[(j - jb) * 16 + rl];
+        const int dx2 = dx * dx;
+        int dy2[4], dz2[2];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) { const int d = Iy[t] - jy; dy2[t] = d * d; }
+        for (int t = 0; t < 4; ++t) { const int d = Iy[t] - jy; dy2[t] = d * d; }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) { const int d = Iz[t] - jz; dz2[t] = d * d; }
+        for (int t = 0; t < 2; ++t) { const int d = Iz[t] - jz; dz2[t] = d * d; }
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float av = tab[dx2 + dy2[t & 3] + dz2[t >> 2]];
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[t], 0, 0, 0);
+        for (int t = 0; t < 8; ++t) {
+          const T av = tab[dx2 + dy2[t & 3] + dz2[t >> 2]];
+          if constexpr (std::is_same<T, double>::value)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[t], 0, 0, 0);
+          else
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[t], 0, 0, 0);
+        }
       }
     }
   }
-  // D layout of 16x16x4 f32: register v holds row 4 (lane / 16) + v, column lane % 16
   const int r = lane & 15;
   if (r0 + r >= nrhs) return;
 #pragma unroll
   for (int t = 0; t < 8; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = wv * 128 + t * 16 + 4 * (lane >> 4) + v;
+      // accumulator layouts of 16x16x4: f32 register v holds row 4 (lane/16) + v,
+      // f64 register v holds row lane/16 + 4 v; the column is lane % 16
+      const int row = std::is_same<T, double>::value ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+      const int i = wv * 128 + t * 16 + row;
       const int64_t g = lin3(tb0 * m + (i & 7), tb1 * m + ((i >> 3) & 7), tb2 * m + (i >> 6), n);
       const int64_t o = (int64_t)(r0 + r) * N + g;
       f[o] = acc[t][v] + a[g] * u[o];
@@ -793,14 +810,14 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   // near field + diagonal (overwrites f)
   {
   ProfScope ps(A, "near", -1, st);
-  const bool mfma_ok = !f64 && A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST;
+  const bool mfma_ok = A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST &&
+                       (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T) <= kLdsBudget;
   const bool near_mfma = mfma_ok && (A.cur.near_kind == 1 || (A.cur.near_kind < 0 && nrhs >= 8));
   if (near_mfma) {
-    const size_t sh = (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(float) + (size_t)512 * 16 * sizeof(float);
-    if (sh > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "near-field working set exceeds LDS");
-    hipLaunchKernelGGL(k_near_mfma, dim3(nleaf, (nrhs + 15) / 16), dim3(256), sh, st, (const float*)u, (float*)f,
-                       (const float*)a, A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), A.T32.as<float>(), A.Tsize,
-                       n, B, nrhs);
+    const size_t sh = (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T);
+    const T* tab = f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr;
+    hipLaunchKernelGGL((k_near_mfma<T>), dim3(nleaf, (nrhs + 15) / 16), dim3(256), sh, st, u, f, a,
+                       A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), tab, A.Tsize, n, B, nrhs);
   } else if (A.uniform && d == 3 && m <= 8) {
     const bool radial = A.kid != HTLR_K_POLY_TEST;
     const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
@@ -812,21 +829,25 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     // waves per leaf: enough waves to fill the GPU, within the LDS budget
     int nw = 1;
     if (A.cur.near_nw > 0) {
-      while (nw < A.cur.near_nw && nw < 4 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+      while (nw < A.cur.near_nw && nw < 8 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
     } else {
-      while (nw < 4 && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+      while (nw < 8 && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
     }
+    const bool full = m == 8;
     const size_t sh = fixed + per_wave * rc * nw;
     if (sh > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "near-field working set exceeds LDS");
-#define HTLR_NEAR_ROWS(RCV, NWV)                                                                                  \
-  HTLR_DISPATCH_KID(A.kid, hipLaunchKernelGGL((k_near_rows<KID, T, RCV, NWV>), dim3(nleaf, nchunk), dim3(64 * NWV), sh, \
-                                              st, u, f, a, A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), tab,   \
+#define HTLR_NEAR_ROWS3(RCV, NWV, FV)                                                                              \
+  HTLR_DISPATCH_KID(A.kid, hipLaunchKernelGGL((k_near_rows<KID, T, RCV, NWV, FV>), dim3(nleaf, nchunk), dim3(64 * NWV),  \
+                                              sh, st, u, f, a, A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), tab, \
                                               A.Tsize, n, m, B, nrhs, (T)A.h, (T)A.w0, (T)A.D0, pm1))
+#define HTLR_NEAR_ROWS(RCV, NWV)                                   \
+  if (full) { HTLR_NEAR_ROWS3(RCV, NWV, true); } else { HTLR_NEAR_ROWS3(RCV, NWV, false); }
 #define HTLR_NEAR_NW(RCV)                                  \
   switch (nw) {                                            \
     case 1: HTLR_NEAR_ROWS(RCV, 1); break;                 \
     case 2: HTLR_NEAR_ROWS(RCV, 2); break;                 \
-    default: HTLR_NEAR_ROWS(RCV, 4); break;                \
+    case 4: HTLR_NEAR_ROWS(RCV, 4); break;                 \
+    default: HTLR_NEAR_ROWS(RCV, 8); break;                \
   }
     switch (rc) {
       case 1: HTLR_NEAR_NW(1); break;
@@ -839,6 +860,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     }
 #undef HTLR_NEAR_NW
 #undef HTLR_NEAR_ROWS
+#undef HTLR_NEAR_ROWS3
   } else if (A.uniform) {
     const bool radial = A.kid != HTLR_K_POLY_TEST;
     const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
@@ -1076,8 +1098,9 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
       }
     }
     const bool near_rows = A->uniform && A->d == 3 && A->plan.m[A->L] <= 8;
-    const bool near_mfma = prec != HTLR_FP64 && A->uniform && A->d == 3 && A->plan.m[A->L] == 8 &&
-                           A->kid != HTLR_K_POLY_TEST;
+    const size_t tsz = (prec == HTLR_FP64 ? 8 : 4);
+    const bool near_mfma = A->uniform && A->d == 3 && A->plan.m[A->L] == 8 && A->kid != HTLR_K_POLY_TEST &&
+                           (((size_t)A->Tsize + 3) & ~size_t(3)) * tsz + (size_t)256 * 16 * tsz <= kLdsBudget;
     if (near_mfma) {
       TuneParams t = best;
       t.near_kind = (nrhs >= 8) ? 0 : 1;   // the variant the defaults did not use
@@ -1085,7 +1108,7 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
       if (ms < best_ms) { best_ms = ms; best = t; }
     }
     if (near_rows && (best.near_kind == 0 || (best.near_kind < 0 && !(near_mfma && nrhs >= 8))))
-      for (int nw : {1, 2, 4}) {
+      for (int nw : {1, 2, 4, 8}) {
         TuneParams t = best;
         t.near_kind = near_mfma ? 0 : -1;
         t.near_nw = nw;

@@ -68,6 +68,8 @@ CASES = [
     (3, 12, 3, 3, "inv_r", "warped", 2),
     (3, 16, 4, 4, "poly_test", "uniform", 1),
     (2, 24, 3, 4, "poly_test", "warped", 1),
+    (3, 32, 8, 4, "inv_r", "uniform", 9),         # matrix-core near field in FP64
+    (3, 32, 8, 4, "exp", "uniform", 1),           # full-leaf row kernel, one RHS
 ]
 
 
