@@ -20,6 +20,7 @@
 // 64 x 64 sub-tile with 32x32 (bf16, f32) or 16x16 (f64) MFMA instructions.
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <map>
 #include <set>
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
     const TE* __restrict__ G, const TE* __restrict__ W, const TE* __restrict__ zero,
     typename AccT<TE>::type* __restrict__ H, const int32_t* __restrict__ tile_tau,
     const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
-    int nitems, int ksplit, int64_t part_stride, int P, int nrhs, int NB, int B) {
+    int nitems, int ksplit, int64_t part_stride, int P, int nrhs, int NB, int B, const int32_t* __restrict__ tile_out) {
   using TA = typename AccT<TE>::type;
   constexpr int NT = 2 * BMT;             // threads
   constexpr int E = 16 / sizeof(TE);      // elements per 16-byte chunk
@@ -236,7 +237,9 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
       const int b = col / nrhs, r = col % nrhs;
       const int t = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
       if (t < 0) continue;
-      TA* Ho = H + ((int64_t)t * nrhs + r) * P;
+      // output slot: the target box, or (offset-major mode) the pair's partial buffer
+      const int slot = tile_out ? tile_out[(int64_t)tile * NB + b] : t;
+      TA* Ho = H + ((int64_t)slot * nrhs + r) * P;
       if constexpr (k16) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -406,12 +409,162 @@ static void launch_variant(const TE* G, const TE* W, const TE* zero, void* H, co
   using TA = typename AccT<TE>::type;
   const unsigned nwg = (unsigned)(((I.n + 7) / 8) * 8);
   hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(2 * BMT), 0, st, G, W, zero, (TA*)H, tau, ptr, off,
-                     I.buf.as<int32_t>(), I.n, ks, helems, P, nrhs, nb, B);
+                     I.buf.as<int32_t>(), I.n, ks, helems, P, nrhs, nb, B, (const int32_t*)nullptr);
+}
+
+template <typename TE, int BMT, int BNT>
+static void launch_variant_out(const TE* G, const TE* W, const TE* zero, void* H, const LevelData::OffsetTiles& T,
+                               int P, int nrhs, int B, hipStream_t st) {
+  using TA = typename AccT<TE>::type;
+  const unsigned nwg = (unsigned)(((T.nitems + 7) / 8) * 8);
+  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(2 * BMT), 0, st, G, W, zero, (TA*)H,
+                     T.tau.as<int32_t>(), T.ptr.as<int64_t>(), T.off.as<int4>(), T.items.as<int32_t>(), T.nitems, 1,
+                     (int64_t)0, P, nrhs, T.nb, B, T.out.as<int32_t>());
+}
+
+// H_tau = sum of the partial products of tau's pairs, in a fixed order.
+template <typename TA>
+__global__ void k_reduce_pairs(const TA* __restrict__ partial, TA* __restrict__ H, const int64_t* __restrict__ rptr,
+                               const int32_t* __restrict__ ridx, int64_t per_box) {
+  const int64_t tau = blockIdx.x;
+  const int64_t k0 = rptr[tau], k1 = rptr[tau + 1];
+  for (int64_t e = threadIdx.x; e < per_box; e += blockDim.x) {
+    TA v = TA(0);
+    for (int64_t k = k0; k < k1; ++k) v += partial[(int64_t)ridx[k] * per_box + e];
+    H[tau * per_box + e] = v;
+  }
+}
+
+// Offset-major work lists: one group of tiles per offset, each tile holding
+// boxes for which that offset is admissible, its columns' outputs going to
+// per-pair slots (pairs numbered offset by offset).
+static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb, int nmb, bool frozen) {
+  for (auto& t : lv.otiles)
+    if (t.nb == nb && t.nmb == nmb) return t;
+  if (frozen) fail(HTLR_ERR_INVALID, "offset-major work list not reserved");
+  const int B = lv.B;
+  const Csr& cs = A.plan.adm[lv.level];
+  std::map<std::array<int, 3>, int> cid;
+  for (int c = 0; c < lv.ncore; ++c)
+    cid[{lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]}] = c;
+  std::vector<std::vector<int32_t>> taus(lv.ncore);
+  for (int64_t t = 0; t < lv.nbox; ++t) {
+    const int tx = (int)(t % B), ty = (int)((t / B) % B), tz = (int)(t / ((int64_t)B * B));
+    for (int64_t e = cs.ptr[t]; e < cs.ptr[t + 1]; ++e) {
+      const int64_t sg = cs.src[e];
+      const int c = cid.at({(int)(sg % B) - tx, (int)((sg / B) % B) - ty, (int)(sg / ((int64_t)B * B)) - tz});
+      taus[c].push_back((int32_t)t);
+    }
+  }
+  std::vector<int32_t> tau, out, items;
+  std::vector<int64_t> ptr{0};
+  std::vector<int4> off;
+  std::vector<std::vector<int32_t>> pairs_of(lv.nbox);
+  int32_t pair = 0;
+  for (int c = 0; c < lv.ncore; ++c) {
+    const int4 o = make_int4(c, lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]);
+    for (size_t s = 0; s < taus[c].size(); s += nb) {
+      for (int q = 0; q < nb; ++q) {
+        if (s + q < taus[c].size()) {
+          const int32_t t = taus[c][s + q];
+          tau.push_back(t);
+          out.push_back(pair);
+          pairs_of[t].push_back(pair);
+          ++pair;
+        } else {
+          tau.push_back(-1);
+          out.push_back(-1);
+        }
+      }
+      off.push_back(o);
+      ptr.push_back((int64_t)off.size());
+    }
+  }
+  const int64_t ntile = (int64_t)ptr.size() - 1;
+  if (ntile >= (1 << 19)) fail(HTLR_ERR_UNSUPPORTED, "offset-major work list too large");
+  for (int64_t t = 0; t < ntile; ++t)
+    for (int mb = 0; mb < nmb; ++mb) items.push_back((int32_t)((t << 12) | (mb << 6)));
+  std::vector<int64_t> rptr{0};
+  std::vector<int32_t> ridx;
+  for (int64_t t = 0; t < lv.nbox; ++t) {
+    ridx.insert(ridx.end(), pairs_of[t].begin(), pairs_of[t].end());
+    rptr.push_back((int64_t)ridx.size());
+  }
+  lv.otiles.emplace_back();
+  LevelData::OffsetTiles& T = lv.otiles.back();
+  T.nb = nb;
+  T.nmb = nmb;
+  T.npairs = pair;
+  T.nitems = (int)items.size();
+  auto up = [](DevBuf& b, const void* src, size_t bytes) {
+    b.alloc(std::max<size_t>(bytes, 16));
+    if (bytes) HTLR_HIP(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+  };
+  up(T.tau, tau.data(), tau.size() * sizeof(int32_t));
+  up(T.out, out.data(), out.size() * sizeof(int32_t));
+  up(T.ptr, ptr.data(), ptr.size() * sizeof(int64_t));
+  up(T.off, off.data(), off.size() * sizeof(int4));
+  up(T.items, items.data(), items.size() * sizeof(int32_t));
+  up(T.rptr, rptr.data(), rptr.size() * sizeof(int64_t));
+  up(T.ridx, ridx.data(), ridx.size() * sizeof(int32_t));
+  A.device_bytes += T.tau.bytes + T.out.bytes + T.ptr.bytes + T.off.bytes + T.items.bytes + T.rptr.bytes + T.ridx.bytes;
+  return T;
+}
+
+// Offset-major mode for a level: automatic when class tiles cannot fill
+// their columns and the per-pair partial buffer stays modest.
+static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
+  const size_t esz = prec == HTLR_FP64 ? 8 : 4;
+  const size_t partial = (size_t)lv.npairs * nrhs * A.P * esz;
+  if (A.cur.core_mode == 1) return false;
+  if (A.cur.core_mode == 2) return partial <= ((size_t)1 << 31);
+  const int64_t class_boxes = lv.nbox >> A.d;
+  return class_boxes * nrhs < 128 && partial <= ((size_t)512 << 20);
 }
 
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st, DevBuf& parts) {
   if (nrhs > kBNmax) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
+  if (use_offset_major(A, lv, nrhs, prec)) {
+    const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
+    const int var = (A.cur.tile >= 1 && A.cur.tile <= 3) ? A.cur.tile : (avg * nrhs <= 64 ? 2 : 1);
+    int bmt, bnt;
+    variant_shape(var, &bmt, &bnt);
+    const int nb = core_mfma_nb(nrhs, bnt);
+    const int nmb = (A.P + bmt - 1) / bmt;
+    LevelData::OffsetTiles& T = offset_tiles_for(A, lv, nb, nmb, A.ws.frozen);
+    const size_t esz = prec == HTLR_FP64 ? 8 : 4;
+    const size_t need = (size_t)T.npairs * nrhs * A.P * esz;
+    if (A.ws.pairs.bytes < need) {
+      if (A.ws.frozen) fail(HTLR_ERR_INVALID, "pair buffer exceeds the reserved size");
+      A.ws.pairs.alloc(need);
+    }
+    void* Hp = A.ws.pairs.ptr;
+#define HTLR_LVO(TE, GPTR)                                                                                         \
+  switch (var) {                                                                                                 \
+    case 2: launch_variant_out<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
+    case 3: launch_variant_out<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;  \
+    default: launch_variant_out<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break; \
+  }
+    if (prec == HTLR_BF16_CORE) {
+      HTLR_LVO(uint16_t, lv.Gm16.as<uint16_t>());
+    } else if (prec == HTLR_FP32) {
+      HTLR_LVO(float, lv.Gm32.as<float>());
+    } else {
+      HTLR_LVO(double, lv.Gm64.as<double>());
+    }
+#undef HTLR_LVO
+    HTLR_HIP(hipGetLastError());
+    const int64_t per_box = (int64_t)nrhs * A.P;
+    if (prec == HTLR_FP64)
+      hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((unsigned)lv.nbox), dim3(256), 0, st, (const double*)Hp,
+                         (double*)H, T.rptr.as<int64_t>(), T.ridx.as<int32_t>(), per_box);
+    else
+      hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((unsigned)lv.nbox), dim3(256), 0, st, (const float*)Hp,
+                         (float*)H, T.rptr.as<int64_t>(), T.ridx.as<int32_t>(), per_box);
+    HTLR_HIP(hipGetLastError());
+    return;
+  }
   const int var = pick_variant(A, lv, nrhs, prec);
   int bmt, bnt;
   variant_shape(var, &bmt, &bnt);
@@ -473,7 +626,7 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
     A.ws.frozen = true;
     return;
   }
-  size_t parts_need = 0;
+  size_t parts_need = 0, pairs_need = 0;
   const TuneParams saved = A.cur;
   for (int c = 1; c <= nrhs; ++c) {
     for (int prec = 0; prec < 3; ++prec) {
@@ -481,6 +634,15 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
       const size_t esz = prec == HTLR_FP64 ? 8 : 4;
       for (LevelData& lv : A.levels) {
         if (lv.npairs == 0) continue;
+        if (use_offset_major(A, lv, c, prec)) {
+          const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
+          const int var = (A.cur.tile >= 1 && A.cur.tile <= 3) ? A.cur.tile : (avg * c <= 64 ? 2 : 1);
+          int bmt, bnt;
+          variant_shape(var, &bmt, &bnt);
+          offset_tiles_for(A, lv, core_mfma_nb(c, bnt), (A.P + bmt - 1) / bmt, false);
+          pairs_need = std::max(pairs_need, (size_t)lv.npairs * c * A.P * esz);
+          continue;
+        }
         int bmt, bnt;
         variant_shape(pick_variant(A, lv, c, prec), &bmt, &bnt);
         LevelData::Tiles& T = tiles_for(A, lv, core_mfma_nb(c, bnt));
@@ -494,6 +656,7 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
   }
   A.cur = saved;
   if (A.ws.parts.bytes < parts_need) A.ws.parts.alloc(parts_need);
+  if (A.ws.pairs.bytes < pairs_need) A.ws.pairs.alloc(pairs_need);
   A.ws.frozen = true;
 }
 

@@ -74,6 +74,15 @@ struct LevelData {
     std::map<int, Items> items;      // per number of K splits
   };
   std::vector<Tiles> tiles;
+  // offset-major work lists (one GEMM per offset; outputs per pair, then reduced)
+  struct OffsetTiles {
+    int nb = 0, nmb = 0;
+    int64_t npairs = 0;
+    int nitems = 0;
+    DevBuf tau, out, ptr, off, items;  // tiles as in Tiles, plus output slots
+    DevBuf rptr, ridx;                 // per box: its pairs, in a fixed order
+  };
+  std::vector<OffsetTiles> otiles;
 };
 
 struct Workspace {
@@ -82,6 +91,7 @@ struct Workspace {
   std::vector<DevBuf> W, H, W16;     // per level
   DevBuf zero;                       // a zero source tensor (matrix-core kernel)
   DevBuf parts;                      // K-split partial sums (matrix-core kernel)
+  DevBuf pairs;                      // per-pair products (offset-major mode)
   size_t bytes = 0;
 };
 
@@ -113,6 +123,7 @@ struct TuneParams {
   int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel
   int near_nw = 0;                   // VALU row kernel: waves per leaf (0 automatic)
   int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128
+  int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
 };
 
 struct htlr_matrix_impl {

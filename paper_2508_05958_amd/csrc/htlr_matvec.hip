@@ -1022,8 +1022,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         TuneParams t;
         double md = 0, mb = 0;
         bool found = false;
-        while (std::fscanf(fp, "%255s %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw, &t.tile, &md,
-                           &mb) == 7)
+        while (std::fscanf(fp, "%255s %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw, &t.tile,
+                           &t.core_mode, &md, &mb) == 8)
           if (std::strcmp(k2, key) == 0) {
             A->tune[{nrhs, (int)prec}] = t;
             res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
@@ -1084,6 +1084,12 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     res.ms_default = time_with(best);
     double best_ms = res.ms_default;
     if (core_mfma_ok(*A, prec)) {
+      for (int mode : {1, 2}) {
+        TuneParams t = best;
+        t.core_mode = mode;
+        const double ms = time_with(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+      }
       for (int tile : {1, 2, 3}) {
         TuneParams t = best;
         t.tile = tile;
@@ -1125,8 +1131,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "a");
       if (fp) {
-        std::fprintf(fp, "%s %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw, best.tile,
-                     res.ms_default, best_ms);
+        std::fprintf(fp, "%s %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw, best.tile,
+                     best.core_mode, res.ms_default, best_ms);
         std::fclose(fp);
       }
     }

@@ -226,7 +226,7 @@ struct ServerImpl {
     HTLR_CHECK_ST(htlr_info(S->A, &inf));
     size_t wsb = 0;
     HTLR_CHECK_ST(htlr_workspace_bytes(S->A, S->cap, HTLR_FP64, &wsb));
-    S->bytes = inf.device_bytes + wsb + S->A->ws.parts.bytes + S->U64.bytes + S->F64.bytes + S->U32.bytes + S->F32.bytes + S->partial.bytes;
+    S->bytes = inf.device_bytes + wsb + S->A->ws.parts.bytes + S->A->ws.pairs.bytes + S->U64.bytes + S->F64.bytes + S->U32.bytes + S->F32.bytes + S->partial.bytes;
     Structure* raw = S.get();
     structs[q.key] = std::move(S);
     ++st.structures_built;
@@ -245,16 +245,22 @@ struct ServerImpl {
       size_t need = sb + (S ? 0 : structure_bytes(q));
       if (used + need > budget) evict_idle(need);
       if (used + need > budget) {
-        if (active == 0 && structs.empty()) {   // can never fit
-          q.state = 3;
-          q.status = HTLR_ERR_OOM;
-          q.t_done = now();
-          queue.pop_front();
-          continue;
+        if (active == 0 && structs.empty() && !S) {
+          // the estimate is an upper bound; decide on the built size
+          S = build(q);
+          if (S->bytes + sb > budget) {
+            structs.erase(q.key);
+            q.state = 3;
+            q.status = HTLR_ERR_OOM;
+            q.t_done = now();
+            queue.pop_front();
+            continue;
+          }
+          used += S->bytes;
+        } else {
+          break;
         }
-        break;
-      }
-      if (!S) {
+      } else if (!S) {
         S = build(q);
         used += S->bytes;
       }
