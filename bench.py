@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
     ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--write-traffic", action="store_true",
+                    help="with --summarize-profile: store per-launch HBM bytes for the roofline's traffic field")
     ap.add_argument("--summarize-profile", default=None, metavar="DIR",
                     help="print a markdown summary of a rocprofv3 run directory (stats/, fetch/, write/) and exit")
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
@@ -84,9 +86,12 @@ def traffic_for(workload, prec, step, launches):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_digest") != source_digest() or step not in t.get("kernels", {}):
+    # counters are kept per kernel family: the near-field kernel, and the core
+    # apply's largest dispatch (the deepest level, which dominates)
+    key = "near" if step == "near" else ("core" if step.startswith("core") else step)
+    if t.get("source_digest") != source_digest() or key not in t.get("kernels", {}):
         return None
-    return t["kernels"][step]["hbm_bytes_per_launch"]
+    return t["kernels"][key]["hbm_bytes_per_launch"]
 
 
 def run_workload(H, torch, w, prec, steps, warmup, profile=True):
@@ -329,8 +334,8 @@ def summarize_profile(d, command, workload, prec):
         cc = rows(sub, "*counter_collection.csv")
         if not cc:
             continue
-        copies = [float(r["Counter_Value"]) for r in cc if "copy" in r["Kernel_Name"].lower()
-                  or "elementwise" in r["Kernel_Name"]]
+        # the largest runtime copy dispatch is the 1 GiB calibration copy
+        copies = [float(r["Counter_Value"]) for r in cc if "copybuffer" in r["Kernel_Name"].lower()]
         cal = (1 << 20) / max(copies) if copies else 1.0          # KiB expected for 1 GiB / KiB counted
         agg = {}
         for r in cc:
@@ -340,14 +345,26 @@ def summarize_profile(d, command, workload, prec):
         for k, v in sorted(agg.items(), key=lambda kv: -max(kv[1]))[:10]:
             lines.append(f"| {k} | {len(v)} | {sum(v)/len(v):.0f} | {max(v):.0f} | {max(v)*cal*1024/1e9:.3f} |")
             traffic.setdefault(k, {})[name] = max(v) * cal * 1024
-    return "\n".join(lines) + "\n", traffic
+    fam = {}
+    for k, v in traffic.items():
+        key = "near" if "near" in k else ("core" if "core" in k else None)
+        if key and "FETCH_SIZE" in v and "WRITE_SIZE" in v:
+            b = v["FETCH_SIZE"] + v["WRITE_SIZE"]
+            if b > fam.get(key, {}).get("hbm_bytes_per_launch", -1):
+                fam[key] = {"kernel": k, "hbm_bytes_per_launch": b, "fetch_bytes": v["FETCH_SIZE"],
+                            "write_bytes": v["WRITE_SIZE"]}
+    return "\n".join(lines) + "\n", fam
 
 
 def main():
     args = parse()
     if args.summarize_profile:
-        md, _ = summarize_profile(args.summarize_profile, args.profile_command, args.workload, args.prec or "")
+        md, fam = summarize_profile(args.summarize_profile, args.profile_command, args.workload, args.prec or "")
         print(md)
+        if args.write_traffic:
+            with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.prec}.json"), "w") as fh:
+                json.dump({"source_digest": source_digest(), "workload": args.workload, "prec": args.prec,
+                           "kernels": fam}, fh, indent=1)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -385,11 +402,18 @@ def main():
     del f
     torch.cuda.empty_cache()
     if args.copy_probe_mib:
-        x = torch.empty(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        # a plain device-to-device copy of known size (the HIP runtime's copy
+        # kernel), used to calibrate the FETCH_SIZE / WRITE_SIZE counters
+        import ctypes
+        nbytes = args.copy_probe_mib * (1 << 20)
+        x = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
-        y.copy_(x)
         torch.cuda.synchronize()
-        out["copy_probe_bytes"] = 2 * x.numel() * 4
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        assert hip.hipMemcpy(y.data_ptr(), x.data_ptr(), nbytes, 3) == 0      # hipMemcpyDeviceToDevice
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
         del x, y
     if not args.no_extra:
         x3 = W.WORKLOADS["w3d_invr_n128_r16"]
