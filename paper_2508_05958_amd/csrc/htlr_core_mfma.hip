@@ -16,7 +16,7 @@
 // falls outside the domain reads a zero tensor.  Each workgroup owns a
 // 128 x 128 output tile and accumulates it over the tile's whole K range
 // (owner computes, no atomics, deterministic).  Operands are staged through
-// LDS in 64-byte K slices with double buffering; 4 waves each compute a
+// LDS in 64- or 128-byte K slices with double buffering; 4 waves each compute a
 // 64 x 64 sub-tile with 32x32 (bf16, f32) or 16x16 (f64) MFMA instructions.
 
 #include <algorithm>
@@ -35,22 +35,36 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // one 16-byte staged chunk
 
 constexpr int kBNmax = 128;  // widest output tile (columns)
-constexpr int kCB = 64;    // bytes of K per row per stage
 
 template <typename TE> struct AccT { using type = float; };
 template <> struct AccT<double> { using type = double; };
 
+// Operand pointers are kept in the global address space from the kernel
+// entry on: pointers selected and carried across loop iterations otherwise
+// become generic, and generic loads are also counted by the LDS wait counter,
+// which would make every LDS wait of the MFMA loop wait for the prefetch.
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+
 // Source tensor of one staged column for offset o, or the zero tensor when
 // the column is empty or its source box lies outside the domain.
 template <typename TE>
-__device__ __forceinline__ const TE* col_src(const TE* W, const TE* zero, int ct, int cx, int cy, int cz, int cr,
-                                             int4 o, int B, int nrhs, int P) {
+__device__ __forceinline__ gptr<TE> col_src(gptr<TE> W, gptr<TE> zero, int ct, int cx, int cy, int cz, int cr,
+                                            int4 o, int B, int nrhs, int P) {
   const int sx = cx + o.y, sy = cy + o.z, sz = cz + o.w;
   const bool ok = ct >= 0 && sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B;
   const int64_t sg = (int64_t)sx + (int64_t)B * (sy + (int64_t)B * sz);
   return ok ? W + (sg * nrhs + cr) * P : zero;
+}
+
+// Bytes of K staged per row and stage: 128 for the 32-bit and 64-bit tiles
+// (more bytes in flight per stage while the next one is fetched), 64 for
+// bfloat16 and the 256-row tile (LDS and registers).
+template <typename TE, int BMT, int BNT>
+constexpr int stage_bytes() {
+  return (sizeof(TE) >= 4 && BMT == 128) ? 128 : 64;
 }
 
 // BMT x BNT output tile per workgroup; 2 BMT threads; waves arranged
@@ -62,12 +76,18 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
     const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
     int nitems, int ksplit, int64_t part_stride, int P, int nrhs, int NB, int B, const int32_t* __restrict__ tile_out) {
   using TA = typename AccT<TE>::type;
+  const gptr<TE> Gg = (gptr<TE>)G, Wg = (gptr<TE>)W, zg = (gptr<TE>)zero;
   constexpr int NT = 2 * BMT;             // threads
   constexpr int E = 16 / sizeof(TE);      // elements per 16-byte chunk
-  constexpr int KBE = kCB / sizeof(TE);   // K elements per stage
-  constexpr int LDW = KBE + E;            // padded LDS row (80 bytes)
-  constexpr int NBH = 2 * BNT / BMT;      // B chunks staged per thread (A: 2)
+  constexpr int CB = stage_bytes<TE, BMT, BNT>();
+  constexpr int KBE = CB / sizeof(TE);    // K elements per stage
+  constexpr int LDW = KBE + E;            // padded LDS row
+  constexpr int CPR = CB / 16;            // 16-byte chunks per staged row
+  constexpr int RPP = NT / CPR;           // rows staged per pass of all threads
+  constexpr int NA = BMT / RPP;           // A rows staged per thread
+  constexpr int NBH = BNT / RPP;          // B columns staged per thread
   constexpr int WNC = BNT / 2;            // columns per wave
+  static_assert(NA >= 1 && NBH >= 1 && NA * RPP == BMT && NBH * RPP == BNT, "staging shape");
   __shared__ __align__(16) TE As[2][BMT * LDW];
   __shared__ __align__(16) TE Bs[2][BNT * LDW];
 
@@ -82,15 +102,14 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
   const int tile = item >> 12;
   const int m0 = ((item >> 6) & 63) * BMT;
   const int split = item & 63;
-  const int part = tid & 3;               // 16-byte chunk within a 64-byte row slice
-  const int srow = tid >> 2;              // staged row / column, plus multiples of NT/4
-  const int arow0 = m0 + srow, arow1 = m0 + srow + NT / 4;
+  const int part = tid % CPR;             // 16-byte chunk within a staged row slice
+  const int srow = tid / CPR;             // staged row / column, plus multiples of RPP
 
-  // columns staged by this thread: target box, rhs, box coordinates
+  // columns staged by this thread: target box (or -1), rhs, box coordinates
   int ct[NBH], cr[NBH], cx[NBH], cy[NBH], cz[NBH];
 #pragma unroll
   for (int h = 0; h < NBH; ++h) {
-    const int col = srow + h * (NT / 4);
+    const int col = srow + h * RPP;
     const int b = col / nrhs;
     cr[h] = col % nrhs;
     ct[h] = (b < NB) ? tile_tau[(int64_t)tile * NB + b] : -1;
@@ -111,15 +130,15 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
   const int ksteps = (P + KBE - 1) / KBE;
   const int64_t nstage = (e1 - e0) * ksteps;
   const int64_t PP = (int64_t)P * P;
-  const uint4 z4 = make_uint4(0, 0, 0, 0);
+  const u32x4 z4 = u32x4{0u, 0u, 0u, 0u};
 
-  static_assert(NBH == 1 || NBH == 2, "one or two staged B columns per thread");
-  const TE* gA = G;
-  const TE* gB0 = zero;
-  const TE* gB1 = zero;
-  uint4 ra0 = z4, ra1 = z4, rb0 = z4, rb1 = z4;
-  const int ct0 = ct[0], cr0 = cr[0], cx0 = cx[0], cy0 = cy[0], cz0 = cz[0];
-  const int ct1 = ct[NBH - 1], cr1 = cr[NBH - 1], cx1 = cx[NBH - 1], cy1 = cy[NBH - 1], cz1 = cz[NBH - 1];
+  gptr<TE> gA = Gg;
+  gptr<TE> gB[NBH];
+  u32x4 ra[NA], rb[NBH];
+#pragma unroll
+  for (int h = 0; h < NBH; ++h) { gB[h] = zg; rb[h] = z4; }
+#pragma unroll
+  for (int i = 0; i < NA; ++i) ra[i] = z4;
 
   const int wm = wv >> 1, wn = wv & 1;
   constexpr bool k16 = std::is_same<TE, double>::value;   // 16x16 tiles for f64
@@ -132,28 +151,35 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = AccV{};
 
-#define HTLR_SET_DELTA(EIDX)                                                       \
-  {                                                                                \
-    const int4 o_ = tile_off[EIDX];                                                \
-    gA = G + (int64_t)o_.x * PP;                                                   \
-    gB0 = col_src(W, zero, ct0, cx0, cy0, cz0, cr0, o_, B, nrhs, P);               \
-    if constexpr (NBH == 2) gB1 = col_src(W, zero, ct1, cx1, cy1, cz1, cr1, o_, B, nrhs, P); \
+#define HTLR_SET_DELTA(EIDX)                                                                  \
+  {                                                                                           \
+    const int4 o_ = tile_off[EIDX];                                                           \
+    gA = Gg + (int64_t)o_.x * PP;                                                             \
+    _Pragma("unroll") for (int h = 0; h < NBH; ++h)                                           \
+      gB[h] = col_src<TE>(Wg, zg, ct[h], cx[h], cy[h], cz[h], cr[h], o_, B, nrhs, P);        \
   }
-#define HTLR_GLOAD(K0)                                                                                       \
-  {                                                                                                          \
-    const int k_ = (K0) + part * E;                                                                          \
-    const bool kin_ = k_ < P;                                                                                \
-    ra0 = (kin_ && arow0 < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)arow0 * P + k_) : z4;         \
-    ra1 = (kin_ && arow1 < P) ? *reinterpret_cast<const uint4*>(gA + (int64_t)arow1 * P + k_) : z4;         \
-    rb0 = kin_ ? *reinterpret_cast<const uint4*>(gB0 + k_) : z4;                                             \
-    if constexpr (NBH == 2) rb1 = kin_ ? *reinterpret_cast<const uint4*>(gB1 + k_) : z4;                     \
+// Out-of-range chunks read the zero tensor (a select between two pointers,
+// not between a loaded value and a zero held in memory).
+#define HTLR_GLOAD(K0)                                                                                   \
+  {                                                                                                      \
+    const int k_ = (K0) + part * E;                                                                      \
+    const bool kin_ = k_ < P;                                                                            \
+    _Pragma("unroll") for (int i = 0; i < NA; ++i) {                                                     \
+      const int ar_ = m0 + srow + i * RPP;                                                               \
+      const gptr<TE> pa_ = (kin_ && ar_ < P) ? gA + (int64_t)ar_ * P + k_ : zg;                          \
+      ra[i] = *(gptr<u32x4>)pa_;                                                                         \
+    }                                                                                                    \
+    _Pragma("unroll") for (int h = 0; h < NBH; ++h) {                                                    \
+      const gptr<TE> pb_ = kin_ ? gB[h] + k_ : zg;                                                       \
+      rb[h] = *(gptr<u32x4>)pb_;                                                                         \
+    }                                                                                                    \
   }
-#define HTLR_SSTORE(BUF)                                                                        \
-  {                                                                                             \
-    *reinterpret_cast<uint4*>(&As[BUF][srow * LDW + part * E]) = ra0;                           \
-    *reinterpret_cast<uint4*>(&As[BUF][(srow + NT / 4) * LDW + part * E]) = ra1;                \
-    *reinterpret_cast<uint4*>(&Bs[BUF][srow * LDW + part * E]) = rb0;                           \
-    if constexpr (NBH == 2) *reinterpret_cast<uint4*>(&Bs[BUF][(srow + NT / 4) * LDW + part * E]) = rb1; \
+#define HTLR_SSTORE(BUF)                                                                              \
+  {                                                                                                   \
+    _Pragma("unroll") for (int i = 0; i < NA; ++i)                                                    \
+      *reinterpret_cast<u32x4*>(&As[BUF][(srow + i * RPP) * LDW + part * E]) = ra[i];                 \
+    _Pragma("unroll") for (int h = 0; h < NBH; ++h)                                                   \
+      *reinterpret_cast<u32x4*>(&Bs[BUF][(srow + h * RPP) * LDW + part * E]) = rb[h];                 \
   }
 
   if (nstage > 0) {
@@ -422,22 +448,34 @@ static void launch_variant_out(const TE* G, const TE* W, const TE* zero, void* H
                      (int64_t)0, P, nrhs, T.nb, B, T.out.as<int32_t>());
 }
 
-// H_tau = sum of the partial products of tau's pairs, in a fixed order.
+// H_tau = sum of the partial products of tau's pairs, in a fixed order (the
+// box's pairs occupy the consecutive slots rptr[tau] .. rptr[tau + 1] - 1).
 template <typename TA>
 __global__ void k_reduce_pairs(const TA* __restrict__ partial, TA* __restrict__ H, const int64_t* __restrict__ rptr,
-                               const int32_t* __restrict__ ridx, int64_t per_box) {
+                               int64_t per_box) {
   const int64_t tau = blockIdx.x;
   const int64_t k0 = rptr[tau], k1 = rptr[tau + 1];
   for (int64_t e = threadIdx.x; e < per_box; e += blockDim.x) {
+    const TA* src = partial + k0 * per_box + e;
+    const int64_t n = k1 - k0;
     TA v = TA(0);
-    for (int64_t k = k0; k < k1; ++k) v += partial[(int64_t)ridx[k] * per_box + e];
+    int64_t k = 0;
+    for (; k + 4 <= n; k += 4) {
+      const TA a0 = src[k * per_box], a1 = src[(k + 1) * per_box];
+      const TA a2 = src[(k + 2) * per_box], a3 = src[(k + 3) * per_box];
+      v += a0;
+      v += a1;
+      v += a2;
+      v += a3;
+    }
+    for (; k < n; ++k) v += src[k * per_box];
     H[tau * per_box + e] = v;
   }
 }
 
 // Offset-major work lists: one group of tiles per offset, each tile holding
 // boxes for which that offset is admissible, its columns' outputs going to
-// per-pair slots (pairs numbered offset by offset).
+// per-pair slots.  A box's pairs take consecutive slots, in offset order.
 static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb, int nmb, bool frozen) {
   for (auto& t : lv.otiles)
     if (t.nb == nb && t.nmb == nmb) return t;
@@ -459,8 +497,12 @@ static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& 
   std::vector<int32_t> tau, out, items;
   std::vector<int64_t> ptr{0};
   std::vector<int4> off;
-  std::vector<std::vector<int32_t>> pairs_of(lv.nbox);
-  int32_t pair = 0;
+  std::vector<int64_t> rptr(lv.nbox + 1, 0);
+  for (int c = 0; c < lv.ncore; ++c)
+    for (int32_t t : taus[c]) ++rptr[t + 1];
+  for (int64_t t = 0; t < lv.nbox; ++t) rptr[t + 1] += rptr[t];
+  std::vector<int64_t> cursor(rptr.begin(), rptr.end() - 1);
+  int64_t pair = 0;
   for (int c = 0; c < lv.ncore; ++c) {
     const int4 o = make_int4(c, lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]);
     for (size_t s = 0; s < taus[c].size(); s += nb) {
@@ -468,8 +510,7 @@ static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& 
         if (s + q < taus[c].size()) {
           const int32_t t = taus[c][s + q];
           tau.push_back(t);
-          out.push_back(pair);
-          pairs_of[t].push_back(pair);
+          out.push_back((int32_t)cursor[t]++);
           ++pair;
         } else {
           tau.push_back(-1);
@@ -482,14 +523,9 @@ static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& 
   }
   const int64_t ntile = (int64_t)ptr.size() - 1;
   if (ntile >= (1 << 19)) fail(HTLR_ERR_UNSUPPORTED, "offset-major work list too large");
+  if (pair >= ((int64_t)1 << 31)) fail(HTLR_ERR_UNSUPPORTED, "too many pairs for the offset-major mode");
   for (int64_t t = 0; t < ntile; ++t)
     for (int mb = 0; mb < nmb; ++mb) items.push_back((int32_t)((t << 12) | (mb << 6)));
-  std::vector<int64_t> rptr{0};
-  std::vector<int32_t> ridx;
-  for (int64_t t = 0; t < lv.nbox; ++t) {
-    ridx.insert(ridx.end(), pairs_of[t].begin(), pairs_of[t].end());
-    rptr.push_back((int64_t)ridx.size());
-  }
   lv.otiles.emplace_back();
   LevelData::OffsetTiles& T = lv.otiles.back();
   T.nb = nb;
@@ -506,8 +542,7 @@ static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& 
   up(T.off, off.data(), off.size() * sizeof(int4));
   up(T.items, items.data(), items.size() * sizeof(int32_t));
   up(T.rptr, rptr.data(), rptr.size() * sizeof(int64_t));
-  up(T.ridx, ridx.data(), ridx.size() * sizeof(int32_t));
-  A.device_bytes += T.tau.bytes + T.out.bytes + T.ptr.bytes + T.off.bytes + T.items.bytes + T.rptr.bytes + T.ridx.bytes;
+  A.device_bytes += T.tau.bytes + T.out.bytes + T.ptr.bytes + T.off.bytes + T.items.bytes + T.rptr.bytes;
   return T;
 }
 
@@ -522,12 +557,19 @@ static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int
   return class_boxes * nrhs < 128 && partial <= ((size_t)512 << 20);
 }
 
+// Tile shape of the offset-major mode: 128x64 unless an offset's boxes
+// times right-hand sides fill well over 128 columns on average.
+static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs) {
+  if (A.cur.tile >= 1 && A.cur.tile <= 3) return A.cur.tile;
+  const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
+  return avg * nrhs <= 128 ? 2 : 1;
+}
+
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st, DevBuf& parts) {
   if (nrhs > kBNmax) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
   if (use_offset_major(A, lv, nrhs, prec)) {
-    const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
-    const int var = (A.cur.tile >= 1 && A.cur.tile <= 3) ? A.cur.tile : (avg * nrhs <= 64 ? 2 : 1);
+    const int var = offset_major_variant(A, lv, nrhs);
     int bmt, bnt;
     variant_shape(var, &bmt, &bnt);
     const int nb = core_mfma_nb(nrhs, bnt);
@@ -558,10 +600,10 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     const int64_t per_box = (int64_t)nrhs * A.P;
     if (prec == HTLR_FP64)
       hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((unsigned)lv.nbox), dim3(256), 0, st, (const double*)Hp,
-                         (double*)H, T.rptr.as<int64_t>(), T.ridx.as<int32_t>(), per_box);
+                         (double*)H, T.rptr.as<int64_t>(), per_box);
     else
       hipLaunchKernelGGL(k_reduce_pairs<float>, dim3((unsigned)lv.nbox), dim3(256), 0, st, (const float*)Hp,
-                         (float*)H, T.rptr.as<int64_t>(), T.ridx.as<int32_t>(), per_box);
+                         (float*)H, T.rptr.as<int64_t>(), per_box);
     HTLR_HIP(hipGetLastError());
     return;
   }
@@ -622,21 +664,19 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
 void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
   A.ws.frozen = false;
   ensure_workspace(A, nrhs, HTLR_FP64);
-  if (!A.uniform || !core_mfma_ok(A, HTLR_FP64)) {
-    A.ws.frozen = true;
-    return;
-  }
-  size_t parts_need = 0, pairs_need = 0;
+  size_t parts_need = 0, pairs_need = 0, nparts_need = 0;
   const TuneParams saved = A.cur;
   for (int c = 1; c <= nrhs; ++c) {
     for (int prec = 0; prec < 3; ++prec) {
       A.cur = find_tune(A, c, prec);
+      if (use_near_leaves(A, c, prec, false))
+        nparts_need = std::max(nparts_need, near_leaves_shape(A, c, prec, false).parts_bytes);
+      if (!A.uniform || !core_mfma_ok(A, HTLR_FP64)) continue;
       const size_t esz = prec == HTLR_FP64 ? 8 : 4;
       for (LevelData& lv : A.levels) {
         if (lv.npairs == 0) continue;
         if (use_offset_major(A, lv, c, prec)) {
-          const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
-          const int var = (A.cur.tile >= 1 && A.cur.tile <= 3) ? A.cur.tile : (avg * c <= 64 ? 2 : 1);
+          const int var = offset_major_variant(A, lv, c);
           int bmt, bnt;
           variant_shape(var, &bmt, &bnt);
           offset_tiles_for(A, lv, core_mfma_nb(c, bnt), (A.P + bmt - 1) / bmt, false);
@@ -657,6 +697,7 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
   A.cur = saved;
   if (A.ws.parts.bytes < parts_need) A.ws.parts.alloc(parts_need);
   if (A.ws.pairs.bytes < pairs_need) A.ws.pairs.alloc(pairs_need);
+  if (A.ws.nparts.bytes < nparts_need) A.ws.nparts.alloc(nparts_need);
   A.ws.frozen = true;
 }
 

@@ -80,7 +80,7 @@ struct LevelData {
     int64_t npairs = 0;
     int nitems = 0;
     DevBuf tau, out, ptr, off, items;  // tiles as in Tiles, plus output slots
-    DevBuf rptr, ridx;                 // per box: its pairs, in a fixed order
+    DevBuf rptr;                       // per box: first slot of its pairs (consecutive, offset order)
   };
   std::vector<OffsetTiles> otiles;
 };
@@ -92,6 +92,7 @@ struct Workspace {
   DevBuf zero;                       // a zero source tensor (matrix-core kernel)
   DevBuf parts;                      // K-split partial sums (matrix-core kernel)
   DevBuf pairs;                      // per-pair products (offset-major mode)
+  DevBuf nparts;                     // K-split partial sums (leaf-column near field)
   size_t bytes = 0;
 };
 
@@ -120,10 +121,30 @@ struct Profiler {
 // Kernel variant choices for products of one shape (nrhs, precision).
 struct TuneParams {
   int ks_target = 2048;              // matrix-core core apply: workgroups aimed for when splitting K
-  int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel
+  int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel with
+                                     // right-hand sides as columns, 2 with target leaves as columns
   int near_nw = 0;                   // VALU row kernel: waves per leaf (0 automatic)
+  int near_ks = 0;                   // leaf-column near kernel: K splits (0 automatic)
+  int near_tpw = 0;                  // leaf-column near kernel: 16-row tiles per wave, 4 or 8 (0 = 8)
   int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128
   int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
+};
+
+// Groups of target leaves for the leaf-column near kernel: lpc leaves per
+// group (Morton order) and the union of their near offsets.
+struct NearGroups {
+  int lpc = 0;
+  bool ok = false;                   // every member's near list = group list inside the domain
+  int64_t ngroups = 0, maxlist = 0;
+  DevBuf mem;                        // [ngroups][lpc] leaves (-1 = empty slot)
+  DevBuf ptr;                        // [ngroups + 1] into off
+  DevBuf off;                        // int4 (dx, dy, dz, 0) per entry
+};
+
+struct NearLeavesShape {
+  bool ok = false;
+  int lpc = 0, tpw = 8, ks = 1;
+  size_t parts_bytes = 0;
 };
 
 struct htlr_matrix_impl {
@@ -143,6 +164,7 @@ struct htlr_matrix_impl {
   DevBuf T64, T32;                   // uniform radial kernels: near-field table by squared distance
   int Tsize = 0;
   std::vector<LevelData> levels;     // index = level
+  std::vector<NearGroups> ngroups;   // leaf-column near kernel work lists, per leaves per group
   size_t device_bytes = 0;
   std::mutex ws_mu;
   Workspace ws;
@@ -160,6 +182,13 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs);
 // Choices for a product of this shape: exact match, else the nearest tuned
 // smaller width of the same precision, else the defaults.
 TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec);
+// Leaf-column near field (uniform 3D grids, 8^3-point leaves, radial kernels, nrhs <= 8).
+bool near_leaves_ok(const htlr_matrix_impl& A, int nrhs, int prec);
+NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool frozen);
+// Whether the product of this shape, with the choices in A.cur, takes the leaf-column near kernel.
+bool use_near_leaves(htlr_matrix_impl& A, int nrhs, int prec, bool frozen);
+template <typename T>
+void launch_near_leaves(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st);
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st, DevBuf& parts);
 

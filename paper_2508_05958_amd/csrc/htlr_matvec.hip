@@ -812,8 +812,12 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   ProfScope ps(A, "near", -1, st);
   const bool mfma_ok = A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST &&
                        (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T) <= kLdsBudget;
-  const bool near_mfma = mfma_ok && (A.cur.near_kind == 1 || (A.cur.near_kind < 0 && nrhs >= 8));
-  if (near_mfma) {
+  const bool near_leaves = use_near_leaves(A, nrhs, prec, A.ws.frozen);
+  const bool near_mfma = !near_leaves && mfma_ok &&
+                         (A.cur.near_kind == 1 || A.cur.near_kind == 2 || (A.cur.near_kind < 0 && nrhs >= 8));
+  if (near_leaves) {
+    launch_near_leaves<T>(A, u, f, nrhs, prec, st);
+  } else if (near_mfma) {
     const size_t sh = (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T);
     const T* tab = f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr;
     hipLaunchKernelGGL((k_near_mfma<T>), dim3(nleaf, (nrhs + 15) / 16), dim3(256), sh, st, u, f, a,
@@ -827,11 +831,13 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     while (rc > 1 && fixed + per_wave * rc > kLdsBudget) rc /= 2;
     const int nchunk = (nrhs + rc - 1) / rc;
     // waves per leaf: enough waves to fill the GPU, within the LDS budget
+    // (8 waves per leaf cap registers at 128 per lane: only for the narrow chunks)
+    const int nwmax = (f64 ? rc >= 2 : rc >= 4) ? 4 : 8;
     int nw = 1;
     if (A.cur.near_nw > 0) {
-      while (nw < A.cur.near_nw && nw < 8 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+      while (nw < A.cur.near_nw && nw < nwmax && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
     } else {
-      while (nw < 8 && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
+      while (nw < nwmax && (int64_t)nleaf * nchunk * nw < 8192 && fixed + per_wave * rc * nw * 2 <= kLdsBudget) nw *= 2;
     }
     const bool full = m == 8;
     const size_t sh = fixed + per_wave * rc * nw;
@@ -849,15 +855,25 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     case 4: HTLR_NEAR_ROWS(RCV, 4); break;                 \
     default: HTLR_NEAR_ROWS(RCV, 8); break;                \
   }
+#define HTLR_NEAR_NW4(RCV)                                 \
+  switch (nw) {                                            \
+    case 1: HTLR_NEAR_ROWS(RCV, 1); break;                 \
+    case 2: HTLR_NEAR_ROWS(RCV, 2); break;                 \
+    default: HTLR_NEAR_ROWS(RCV, 4); break;                \
+  }
     switch (rc) {
       case 1: HTLR_NEAR_NW(1); break;
-      case 2: HTLR_NEAR_NW(2); break;
-      case 4: HTLR_NEAR_NW(4); break;
+      case 2:
+        if constexpr (std::is_same<T, double>::value) { HTLR_NEAR_NW4(2); }
+        else { HTLR_NEAR_NW(2); }
+        break;
+      case 4: HTLR_NEAR_NW4(4); break;
       default:
-        if constexpr (!std::is_same<T, double>::value) { HTLR_NEAR_NW(8); }
+        if constexpr (!std::is_same<T, double>::value) { HTLR_NEAR_NW4(8); }
         else fail(HTLR_ERR_INVALID, "near-field chunk size");
         break;
     }
+#undef HTLR_NEAR_NW4
 #undef HTLR_NEAR_NW
 #undef HTLR_NEAR_ROWS
 #undef HTLR_NEAR_ROWS3
@@ -1018,13 +1034,15 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "r");
       if (fp) {
-        char k2[256];
+        char k2[256], line[512];
         TuneParams t;
         double md = 0, mb = 0;
         bool found = false;
-        while (std::fscanf(fp, "%255s %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw, &t.tile,
-                           &t.core_mode, &md, &mb) == 8)
-          if (std::strcmp(k2, key) == 0) {
+        // key ks_target near_kind near_nw tile core_mode near_ks near_tpw ms_default ms_best
+        while (std::fgets(line, sizeof(line), fp))
+          if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw,
+                          &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw, &md, &mb) == 10 &&
+              std::strcmp(k2, key) == 0) {
             A->tune[{nrhs, (int)prec}] = t;
             res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
             found = true;
@@ -1107,16 +1125,35 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     const size_t tsz = (prec == HTLR_FP64 ? 8 : 4);
     const bool near_mfma = A->uniform && A->d == 3 && A->plan.m[A->L] == 8 && A->kid != HTLR_K_POLY_TEST &&
                            (((size_t)A->Tsize + 3) & ~size_t(3)) * tsz + (size_t)256 * 16 * tsz <= kLdsBudget;
+    const bool near_lv = near_leaves_ok(*A, nrhs, prec);
     if (near_mfma) {
       TuneParams t = best;
-      t.near_kind = (nrhs >= 8) ? 0 : 1;   // the variant the defaults did not use
+      t.near_kind = 1;
       const double ms = time_with(t);
       if (ms < best_ms) { best_ms = ms; best = t; }
     }
-    if (near_rows && (best.near_kind == 0 || (best.near_kind < 0 && !(near_mfma && nrhs >= 8))))
+    if (near_lv) {
+      for (int tpw : {4, 8})
+        for (int ks : {1, 2, 4, 8, 16, 32}) {
+          TuneParams t = best;
+          t.near_kind = 2;
+          t.near_tpw = tpw;
+          t.near_ks = ks;
+          const double ms = time_with(t);
+          if (ms < best_ms) { best_ms = ms; best = t; }
+        }
+    }
+    if (near_mfma || near_lv) {
+      TuneParams t = best;
+      t.near_kind = 0;
+      t.near_nw = 0;
+      const double ms = time_with(t);
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    if (near_rows && best.near_kind == 0)
       for (int nw : {1, 2, 4, 8}) {
         TuneParams t = best;
-        t.near_kind = near_mfma ? 0 : -1;
+        t.near_kind = 0;
         t.near_nw = nw;
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
@@ -1131,8 +1168,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "a");
       if (fp) {
-        std::fprintf(fp, "%s %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw, best.tile,
-                     best.core_mode, res.ms_default, best_ms);
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw,
+                     best.tile, best.core_mode, best.near_ks, best.near_tpw, res.ms_default, best_ms);
         std::fclose(fp);
       }
     }

@@ -79,7 +79,7 @@ def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mo
     pid = {"fp64": 0, "fp32": 1, "bf16": 2}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 1.0 1.0\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]
@@ -102,28 +102,37 @@ def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mo
     assert np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref) <= tol
 
 
+_NEAR_REF = {}
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("near_kind,nw", [(1, 0), (0, 1), (0, 8)])
-def test_every_near_variant_matches(torch, tmp_path, monkeypatch, prec, near_kind, nw):
-    """Force the near-field variant (matrix-core, VALU rows with 1 or 8 waves
-    per leaf) through the tuner's cache file; compare with the oracle."""
+@pytest.mark.parametrize("nrhs", [1, 5])
+@pytest.mark.parametrize("near_kind,nw,ks,tpw", [(1, 0, 0, 0), (0, 1, 0, 0), (0, 8, 0, 0), (2, 0, 1, 8), (2, 0, 4, 4),
+                                                 (2, 0, 32, 8)])
+def test_every_near_variant_matches(torch, tmp_path, monkeypatch, prec, nrhs, near_kind, nw, ks, tpw):
+    """Force the near-field variant through the tuner's cache file and compare
+    with the oracle: matrix cores with right-hand sides as columns (1), VALU
+    rows with 1 or 8 waves per leaf (0), matrix cores with target leaves as
+    columns (2) at several K splits and tiles per wave."""
     import paper_2508_05958_amd as H
     from oracle import geometry, htlr
-    _say(f"[gpu] forced near {near_kind}/{nw} {prec}")
-    n, p, leaf, nrhs = 32, 4, 8, 5
+    _say(f"[gpu] forced near kind={near_kind} nw={nw} ks={ks} tpw={tpw} {prec} nrhs={nrhs}")
+    n, p, leaf = 32, 4, 8
     pid = {"fp64": 0, "fp32": 1}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k1_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 {near_kind} {nw} 0 0 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 {near_kind} {nw} 0 0 {ks} {tpw} 1.0 1.0\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]
-    u = np.random.default_rng(near_kind * 10 + nw).standard_normal((g.N, nrhs))
+    u = np.random.default_rng(nrhs).standard_normal((g.N, nrhs))
+    if nrhs not in _NEAR_REF:
+        _NEAR_REF[nrhs] = htlr.HTLR(g, "neg_log", p, leaf, a).matvec(u)
+    fo = _NEAR_REF[nrhs]
     M = H.htlr_build(None, "neg_log", 3, n, p, leaf, a=a)
     assert M.autotune(nrhs, prec)["candidates"] == 0
     dt = torch.float64 if prec == "fp64" else torch.float32
     ut = torch.tensor(u.T.copy(), dtype=dt, device="cuda").t()
     f = M.matvec(ut, prec=prec).double().cpu().numpy()
-    fo = htlr.HTLR(g, "neg_log", p, leaf, a).matvec(u)
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert np.linalg.norm(f - fo) / np.linalg.norm(fo) <= tol
