@@ -566,7 +566,11 @@ static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, 
 }
 
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
-                      int nrhs, hipStream_t st, DevBuf& parts) {
+                      int nrhs, hipStream_t st) {
+  if ((int)A.ws.parts.size() <= lv.level) A.ws.parts.resize(lv.level + 1);
+  if ((int)A.ws.pairs.size() <= lv.level) A.ws.pairs.resize(lv.level + 1);
+  DevBuf& parts = A.ws.parts[lv.level];
+  DevBuf& pairs = A.ws.pairs[lv.level];
   if (nrhs > kBNmax) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
   if (use_offset_major(A, lv, nrhs, prec)) {
     const int var = offset_major_variant(A, lv, nrhs);
@@ -577,11 +581,11 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     LevelData::OffsetTiles& T = offset_tiles_for(A, lv, nb, nmb, A.ws.frozen);
     const size_t esz = prec == HTLR_FP64 ? 8 : 4;
     const size_t need = (size_t)T.npairs * nrhs * A.P * esz;
-    if (A.ws.pairs.bytes < need) {
+    if (pairs.bytes < need) {
       if (A.ws.frozen) fail(HTLR_ERR_INVALID, "pair buffer exceeds the reserved size");
-      A.ws.pairs.alloc(need);
+      pairs.alloc(need);
     }
-    void* Hp = A.ws.pairs.ptr;
+    void* Hp = pairs.ptr;
 #define HTLR_LVO(TE, GPTR)                                                                                         \
   switch (var) {                                                                                                 \
     case 2: launch_variant_out<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
@@ -664,7 +668,9 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
 void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
   A.ws.frozen = false;
   ensure_workspace(A, nrhs, HTLR_FP64);
-  size_t parts_need = 0, pairs_need = 0, nparts_need = 0;
+  const int nl = A.L + 1;
+  std::vector<size_t> parts_need(nl, 0), pairs_need(nl, 0);
+  size_t nparts_need = 0;
   const TuneParams saved = A.cur;
   for (int c = 1; c <= nrhs; ++c) {
     for (int prec = 0; prec < 3; ++prec) {
@@ -675,12 +681,12 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
       const size_t esz = prec == HTLR_FP64 ? 8 : 4;
       for (LevelData& lv : A.levels) {
         if (lv.npairs == 0) continue;
+        const int l = lv.level;
         if (use_offset_major(A, lv, c, prec)) {
-          const int var = offset_major_variant(A, lv, c);
           int bmt, bnt;
-          variant_shape(var, &bmt, &bnt);
+          variant_shape(offset_major_variant(A, lv, c), &bmt, &bnt);
           offset_tiles_for(A, lv, core_mfma_nb(c, bnt), (A.P + bmt - 1) / bmt, false);
-          pairs_need = std::max(pairs_need, (size_t)lv.npairs * c * A.P * esz);
+          pairs_need[l] = std::max(pairs_need[l], (size_t)lv.npairs * c * A.P * esz);
           continue;
         }
         int bmt, bnt;
@@ -690,14 +696,19 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
         const int nmb = (A.P + bmt - 1) / bmt;
         const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
         items_for(T, ks, nmb, false);
-        if (ks > 1) parts_need = std::max(parts_need, (size_t)lv.nbox * c * A.P * ks * esz);
+        if (ks > 1) parts_need[l] = std::max(parts_need[l], (size_t)lv.nbox * c * A.P * ks * esz);
       }
     }
   }
   A.cur = saved;
-  if (A.ws.parts.bytes < parts_need) A.ws.parts.alloc(parts_need);
-  if (A.ws.pairs.bytes < pairs_need) A.ws.pairs.alloc(pairs_need);
+  if ((int)A.ws.parts.size() < nl) A.ws.parts.resize(nl);
+  if ((int)A.ws.pairs.size() < nl) A.ws.pairs.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    if (A.ws.parts[l].bytes < parts_need[l]) A.ws.parts[l].alloc(parts_need[l]);
+    if (A.ws.pairs[l].bytes < pairs_need[l]) A.ws.pairs[l].alloc(pairs_need[l]);
+  }
   if (A.ws.nparts.bytes < nparts_need) A.ws.nparts.alloc(nparts_need);
+  side_streams(A);
   A.ws.frozen = true;
 }
 

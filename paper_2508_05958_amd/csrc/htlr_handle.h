@@ -90,10 +90,17 @@ struct Workspace {
   bool frozen = false;               // reserved: products must not reallocate
   std::vector<DevBuf> W, H, W16;     // per level
   DevBuf zero;                       // a zero source tensor (matrix-core kernel)
-  DevBuf parts;                      // K-split partial sums (matrix-core kernel)
-  DevBuf pairs;                      // per-pair products (offset-major mode)
+  // per level (levels run concurrently): K-split partial sums of the
+  // matrix-core kernel, per-pair products of the offset-major mode
+  std::vector<DevBuf> parts, pairs;
   DevBuf nparts;                     // K-split partial sums (leaf-column near field)
-  size_t bytes = 0;
+  size_t bytes = 0;                  // W, H and zero
+  size_t extra_bytes() const {
+    size_t b = nparts.bytes;
+    for (const DevBuf& x : parts) b += x.bytes;
+    for (const DevBuf& x : pairs) b += x.bytes;
+    return b;
+  }
 };
 
 // hipEvent pairs around product launches, for measurement.
@@ -128,6 +135,7 @@ struct TuneParams {
   int near_tpw = 0;                  // leaf-column near kernel: 16-row tiles per wave, 4 or 8 (0 = 8)
   int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128
   int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
+  int serial = 0;                    // 1: every launch on the caller's stream (no level concurrency)
 };
 
 // Groups of target leaves for the leaf-column near kernel: lpc leaves per
@@ -171,9 +179,23 @@ struct htlr_matrix_impl {
   Profiler prof;
   std::map<std::pair<int, int>, TuneParams> tune;   // (nrhs, precision) -> choices
   TuneParams cur;                    // choices of the product being issued
+  hipEvent_t ev_fork = nullptr;      // level concurrency: fork from and join into the caller's stream
+  hipEvent_t ev_level[kMaxLevels] = {};
+  htlr_matrix_impl() = default;
+  htlr_matrix_impl(const htlr_matrix_impl&) = delete;
+  htlr_matrix_impl& operator=(const htlr_matrix_impl&) = delete;
+  ~htlr_matrix_impl() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (hipEvent_t e : ev_level)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
+// Side streams for the concurrent level chains of a product (a few per
+// device, shared by every handle, default priority, kept until the process
+// ends); also creates the handle's fork and level events.
+const std::vector<hipStream_t>& side_streams(htlr_matrix_impl& A);
 void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec);
 // Allocates every buffer products with up to nrhs right-hand sides can need
 // (work buffers, matrix-core work lists, K-split partial sums), then freezes
@@ -190,7 +212,7 @@ bool use_near_leaves(htlr_matrix_impl& A, int nrhs, int prec, bool frozen);
 template <typename T>
 void launch_near_leaves(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st);
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
-                      int nrhs, hipStream_t st, DevBuf& parts);
+                      int nrhs, hipStream_t st);
 
 }  // namespace htlr
 

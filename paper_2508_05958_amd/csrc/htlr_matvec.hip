@@ -781,6 +781,26 @@ struct ProfScope {
   }
 };
 
+const std::vector<hipStream_t>& side_streams(htlr_matrix_impl& A) {
+  constexpr int kSideStreams = 4;
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<hipStream_t>& v = pool[A.device];
+  if (v.empty()) {
+    for (int i = 0; i < kSideStreams; ++i) {
+      hipStream_t s = nullptr;
+      HTLR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      v.push_back(s);
+    }
+  }
+  if (!A.ev_fork) {
+    HTLR_HIP(hipEventCreateWithFlags(&A.ev_fork, hipEventDisableTiming));
+    for (hipEvent_t& e : A.ev_level) HTLR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  return v;
+}
+
 TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
   auto it = A.tune.find({nrhs, prec});
   if (it != A.tune.end()) return it->second;
@@ -806,6 +826,84 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   if (P > 8 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "p^d larger than 2048");
   const T* a = f64 ? (const T*)A.a64.ptr : (const T*)A.a32.ptr;
   const int64_t nleaf = A.levels[A.L].nbox;
+
+  // far field.  Each level's up and core launches run on a side stream,
+  // concurrently with the near field and with the other levels; the down
+  // expansions then add into f on the caller's stream in level order, so the
+  // summation order is fixed.
+  std::vector<LevelData*> act;
+  for (LevelData& lv : A.levels)
+    if (lv.npairs > 0) act.push_back(&lv);
+  const bool fork = A.cur.serial == 0 && !act.empty();
+  const std::vector<hipStream_t>* side = fork ? &side_streams(A) : nullptr;
+  if (fork) {
+    HTLR_HIP(hipEventRecord(A.ev_fork, st));
+    for (size_t i = 0; i < act.size() && i < side->size(); ++i)
+      HTLR_HIP(hipStreamWaitEvent((*side)[i], A.ev_fork, 0));
+  }
+  for (size_t li = 0; li < act.size(); ++li) {
+    LevelData& lv = *act[li];
+    const hipStream_t ls = fork ? (*side)[li % side->size()] : st;
+    const int l = lv.level, lm = lv.m, lB = lv.B;
+    const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
+    const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
+    T* H = A.ws.H[l].as<T>();
+    size_t sh_up = ((size_t)(d == 3 ? lm * lm : lm) + (size_t)p * lm + (size_t)p * p) * sizeof(T);
+    if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
+    if (prec == HTLR_BF16_CORE) {
+      if constexpr (!std::is_same<T, double>::value) {
+        if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
+        if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
+        uint16_t* W16 = A.ws.W[l].as<uint16_t>();
+        { ProfScope ps(A, "up", l, ls);
+        hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, ls, u, W16, V,
+                           1, d, n, lm, lB, p, nrhs);
+        HTLR_HIP(hipGetLastError()); }
+        ProfScope ps(A, "core", l, ls);
+        if (core_mfma_ok(A, prec)) {
+          launch_core_mfma(A, lv, prec, W16, H, A.ws.zero.ptr, nrhs, ls);
+        } else {
+        const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
+        const int nchunk = (nrhs + rc - 1) / rc;
+        size_t sh = (size_t)rc * P * sizeof(float);
+        HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<uint16_t, uint16_t, float, RC, false>),
+                                                dim3(lv.nbox, nchunk), dim3(kThreads), sh, ls, W16, H,
+                                                lv.Gm16.as<uint16_t>(), lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
+                                                lv.cid.as<int32_t>(), P, nrhs));
+        HTLR_HIP(hipGetLastError());
+        }
+      }
+    } else {
+    T* W = A.ws.W[l].as<T>();
+    { ProfScope ps(A, "up", l, ls);
+    hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, ls, u, W, V, A.uniform ? 1 : 0, d,
+                       n, lm, lB, p, nrhs);
+    HTLR_HIP(hipGetLastError()); }
+    ProfScope ps(A, "core", l, ls);
+    if (A.uniform && core_mfma_ok(A, prec)) {
+      launch_core_mfma(A, lv, prec, W, H, A.ws.zero.ptr, nrhs, ls);
+    } else if (A.uniform) {
+      const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
+      if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
+      const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(T));
+      const int nchunk = (nrhs + rc - 1) / rc;
+      size_t sh = (size_t)rc * P * sizeof(T);
+      HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, false>), dim3(lv.nbox, nchunk), dim3(kThreads),
+                                              sh, ls, W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
+                                              lv.cid.as<int32_t>(), P, nrhs));
+    } else {
+      const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T), (size_t)P * sizeof(T));
+      const int nchunk = (nrhs + rc - 1) / rc;
+      size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T);
+      HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_tensor<KID, T, RC>), dim3(lv.nbox, nchunk),
+                                                                     dim3(kThreads), sh, ls, W, H, lv.cheb64.as<double>(),
+                                                                     lv.ptr.as<int64_t>(), lv.src.as<int32_t>(), d, p, lB,
+                                                                     nrhs, pm1)));
+    }
+    HTLR_HIP(hipGetLastError());
+    }
+    if (fork) HTLR_HIP(hipEventRecord(A.ev_level[li], ls));
+  }
 
   // near field + diagonal (overwrites f)
   {
@@ -903,67 +1001,13 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   HTLR_HIP(hipGetLastError());
   }
 
-  // far field, level by level
-  for (LevelData& lv : A.levels) {
-    if (lv.npairs == 0) continue;
+
+  for (size_t li = 0; li < act.size(); ++li) {
+    LevelData& lv = *act[li];
     const int l = lv.level, lm = lv.m, lB = lv.B;
-    const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
     const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
     T* H = A.ws.H[l].as<T>();
-    size_t sh_up = ((size_t)(d == 3 ? lm * lm : lm) + (size_t)p * lm + (size_t)p * p) * sizeof(T);
-    if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
-    if (prec == HTLR_BF16_CORE) {
-      if constexpr (!std::is_same<T, double>::value) {
-        if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
-        if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
-        uint16_t* W16 = A.ws.W[l].as<uint16_t>();
-        { ProfScope ps(A, "up", l, st);
-        hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, st, u, W16, V,
-                           1, d, n, lm, lB, p, nrhs);
-        HTLR_HIP(hipGetLastError()); }
-        ProfScope ps(A, "core", l, st);
-        if (core_mfma_ok(A, prec)) {
-          launch_core_mfma(A, lv, prec, W16, H, A.ws.zero.ptr, nrhs, st, A.ws.parts);
-        } else {
-        const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
-        const int nchunk = (nrhs + rc - 1) / rc;
-        size_t sh = (size_t)rc * P * sizeof(float);
-        HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<uint16_t, uint16_t, float, RC, false>),
-                                                dim3(lv.nbox, nchunk), dim3(kThreads), sh, st, W16, H,
-                                                lv.Gm16.as<uint16_t>(), lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
-                                                lv.cid.as<int32_t>(), P, nrhs));
-        HTLR_HIP(hipGetLastError());
-        }
-      }
-    } else {
-    T* W = A.ws.W[l].as<T>();
-    { ProfScope ps(A, "up", l, st);
-    hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, st, u, W, V, A.uniform ? 1 : 0, d,
-                       n, lm, lB, p, nrhs);
-    HTLR_HIP(hipGetLastError()); }
-    ProfScope ps(A, "core", l, st);
-    if (A.uniform && core_mfma_ok(A, prec)) {
-      launch_core_mfma(A, lv, prec, W, H, A.ws.zero.ptr, nrhs, st, A.ws.parts);
-    } else if (A.uniform) {
-      const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
-      if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
-      const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(T));
-      const int nchunk = (nrhs + rc - 1) / rc;
-      size_t sh = (size_t)rc * P * sizeof(T);
-      HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, false>), dim3(lv.nbox, nchunk), dim3(kThreads),
-                                              sh, st, W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
-                                              lv.cid.as<int32_t>(), P, nrhs));
-    } else {
-      const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T), (size_t)P * sizeof(T));
-      const int nchunk = (nrhs + rc - 1) / rc;
-      size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T);
-      HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_tensor<KID, T, RC>), dim3(lv.nbox, nchunk),
-                                                                     dim3(kThreads), sh, st, W, H, lv.cheb64.as<double>(),
-                                                                     lv.ptr.as<int64_t>(), lv.src.as<int32_t>(), d, p, lB,
-                                                                     nrhs, pm1)));
-    }
-    HTLR_HIP(hipGetLastError());
-    }
+    if (fork) HTLR_HIP(hipStreamWaitEvent(st, A.ev_level[li], 0));
     size_t sh_dn = ((size_t)P + (size_t)p * p + (size_t)lm * p) * sizeof(T);
     if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
     ProfScope ps(A, "down", l, st);
@@ -1038,10 +1082,10 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         TuneParams t;
         double md = 0, mb = 0;
         bool found = false;
-        // key ks_target near_kind near_nw tile core_mode near_ks near_tpw ms_default ms_best
+        // key ks_target near_kind near_nw tile core_mode near_ks near_tpw serial ms_default ms_best
         while (std::fgets(line, sizeof(line), fp))
-          if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw,
-                          &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw, &md, &mb) == 10 &&
+          if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw,
+                          &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw, &t.serial, &md, &mb) == 11 &&
               std::strcmp(k2, key) == 0) {
             A->tune[{nrhs, (int)prec}] = t;
             res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
@@ -1158,6 +1202,12 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
+    {
+      TuneParams t = best;
+      t.serial = 1;
+      const double ms = time_with(t);
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
     A->tune[{nrhs, (int)prec}] = best;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1168,8 +1218,9 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "a");
       if (fp) {
-        std::fprintf(fp, "%s %d %d %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind, best.near_nw,
-                     best.tile, best.core_mode, best.near_ks, best.near_tpw, res.ms_default, best_ms);
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind,
+                     best.near_nw, best.tile, best.core_mode, best.near_ks, best.near_tpw, best.serial,
+                     res.ms_default, best_ms);
         std::fclose(fp);
       }
     }

@@ -226,7 +226,7 @@ struct ServerImpl {
     HTLR_CHECK_ST(htlr_info(S->A, &inf));
     size_t wsb = 0;
     HTLR_CHECK_ST(htlr_workspace_bytes(S->A, S->cap, HTLR_FP64, &wsb));
-    S->bytes = inf.device_bytes + wsb + S->A->ws.parts.bytes + S->A->ws.pairs.bytes + S->A->ws.nparts.bytes + S->U64.bytes + S->F64.bytes + S->U32.bytes + S->F32.bytes + S->partial.bytes;
+    S->bytes = inf.device_bytes + wsb + S->A->ws.extra_bytes() + S->U64.bytes + S->F64.bytes + S->U32.bytes + S->F32.bytes + S->partial.bytes;
     Structure* raw = S.get();
     structs[q.key] = std::move(S);
     ++st.structures_built;

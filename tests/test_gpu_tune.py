@@ -79,7 +79,7 @@ def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mo
     pid = {"fp64": 0, "fp32": 1, "bf16": 2}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 0 1.0 1.0\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]
@@ -121,7 +121,7 @@ def test_every_near_variant_matches(torch, tmp_path, monkeypatch, prec, nrhs, ne
     pid = {"fp64": 0, "fp32": 1}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k1_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 {near_kind} {nw} 0 0 {ks} {tpw} 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 {near_kind} {nw} 0 0 {ks} {tpw} 0 1.0 1.0\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]
@@ -136,3 +136,29 @@ def test_every_near_variant_matches(torch, tmp_path, monkeypatch, prec, nrhs, ne
     f = M.matvec(ut, prec=prec).double().cpu().numpy()
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert np.linalg.norm(f - fo) / np.linalg.norm(fo) <= tol
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp32", 3)])
+def test_level_concurrency_is_bitwise_serial(torch, tmp_path, monkeypatch, prec, nrhs):
+    """Levels run on side streams concurrently with the near field; the down
+    expansions add into f in level order on the caller's stream, so the
+    product equals the all-serial launch order bit for bit."""
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] level concurrency vs serial {prec} nrhs={nrhs}")
+    n, p, leaf = 64, 4, 8
+    pid = {"fp64": 0, "fp32": 1}[prec]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u = torch.randn(nrhs, n ** 3, dtype=dt, generator=torch.Generator().manual_seed(7)).to("cuda").t()
+    outs = []
+    for serial in (0, 1):
+        cache = tmp_path / f"tune{serial}.txt"
+        key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
+        cache.write_text(f"{key} 2048 -1 0 0 0 0 0 {serial} 1.0 1.0\n")
+        monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
+        M = H.htlr_build(None, "inv_r", 3, n, p, leaf, a=np.ones(n ** 3))
+        assert sum(1 for x in M.info()["adm_pairs"] if x) >= 2
+        assert M.autotune(nrhs, prec)["candidates"] == 0
+        outs.append([M.matvec(u, prec=prec).cpu().numpy() for _ in range(2)])
+        M.free()
+    assert np.array_equal(outs[0][0], outs[0][1])
+    assert np.array_equal(outs[0][0], outs[1][0])
