@@ -67,10 +67,17 @@ constexpr int stage_bytes() {
   return (sizeof(TE) >= 4 && BMT == 128) ? 128 : 64;
 }
 
+// Stages in flight per thread (1 or 2): 2 where the extra register slot
+// keeps the same number of waves per SIMD.
+template <typename TE, int BMT, int BNT>
+constexpr int prefetch_depth() {
+  return (sizeof(TE) == 8 && BMT == 128 && BNT == 128) ? 1 : 2;
+}
+
 // BMT x BNT output tile per workgroup; 2 BMT threads; waves arranged
 // (BMT / 64) x 2, each owning 64 rows x BNT/2 columns.
 template <typename TE, int BMT, int BNT>
-__global__ __launch_bounds__(2 * BMT) void k_core_mfma(
+__global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) void k_core_mfma(
     const TE* __restrict__ G, const TE* __restrict__ W, const TE* __restrict__ zero,
     typename AccT<TE>::type* __restrict__ H, const int32_t* __restrict__ tile_tau,
     const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
@@ -80,6 +87,7 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
   constexpr int NT = 2 * BMT;             // threads
   constexpr int E = 16 / sizeof(TE);      // elements per 16-byte chunk
   constexpr int CB = stage_bytes<TE, BMT, BNT>();
+  constexpr int PD = prefetch_depth<TE, BMT, BNT>();
   constexpr int KBE = CB / sizeof(TE);    // K elements per stage
   constexpr int LDW = KBE + E;            // padded LDS row
   constexpr int CPR = CB / 16;            // 16-byte chunks per staged row
@@ -134,11 +142,14 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
 
   gptr<TE> gA = Gg;
   gptr<TE> gB[NBH];
-  u32x4 ra[NA], rb[NBH];
+  // two register slots of staged chunks: with prefetch depth 2 the loads of
+  // stage s + 2 are in flight while stage s is computed and stage s + 1 is
+  // written to LDS
+  u32x4 ra0[NA], rb0[NBH], ra1[NA], rb1[NBH];
 #pragma unroll
-  for (int h = 0; h < NBH; ++h) { gB[h] = zg; rb[h] = z4; }
+  for (int h = 0; h < NBH; ++h) { gB[h] = zg; rb0[h] = z4; rb1[h] = z4; }
 #pragma unroll
-  for (int i = 0; i < NA; ++i) ra[i] = z4;
+  for (int i = 0; i < NA; ++i) { ra0[i] = z4; ra1[i] = z4; }
 
   const int wm = wv >> 1, wn = wv & 1;
   constexpr bool k16 = std::is_same<TE, double>::value;   // 16x16 tiles for f64
@@ -160,96 +171,128 @@ __global__ __launch_bounds__(2 * BMT) void k_core_mfma(
   }
 // Out-of-range chunks read the zero tensor (a select between two pointers,
 // not between a loaded value and a zero held in memory).
-#define HTLR_GLOAD(K0)                                                                                   \
+#define HTLR_GLOAD(RA, RB, K0)                                                                           \
   {                                                                                                      \
     const int k_ = (K0) + part * E;                                                                      \
     const bool kin_ = k_ < P;                                                                            \
     _Pragma("unroll") for (int i = 0; i < NA; ++i) {                                                     \
       const int ar_ = m0 + srow + i * RPP;                                                               \
       const gptr<TE> pa_ = (kin_ && ar_ < P) ? gA + (int64_t)ar_ * P + k_ : zg;                          \
-      ra[i] = *(gptr<u32x4>)pa_;                                                                         \
+      RA[i] = *(gptr<u32x4>)pa_;                                                                         \
     }                                                                                                    \
     _Pragma("unroll") for (int h = 0; h < NBH; ++h) {                                                    \
       const gptr<TE> pb_ = kin_ ? gB[h] + k_ : zg;                                                       \
-      rb[h] = *(gptr<u32x4>)pb_;                                                                         \
+      RB[h] = *(gptr<u32x4>)pb_;                                                                         \
     }                                                                                                    \
   }
-#define HTLR_SSTORE(BUF)                                                                              \
+#define HTLR_SSTORE(RA, RB, BUF)                                                                      \
   {                                                                                                   \
     _Pragma("unroll") for (int i = 0; i < NA; ++i)                                                    \
-      *reinterpret_cast<u32x4*>(&As[BUF][(srow + i * RPP) * LDW + part * E]) = ra[i];                 \
+      *reinterpret_cast<u32x4*>(&As[BUF][(srow + i * RPP) * LDW + part * E]) = RA[i];                 \
     _Pragma("unroll") for (int h = 0; h < NBH; ++h)                                                   \
-      *reinterpret_cast<u32x4*>(&Bs[BUF][(srow + h * RPP) * LDW + part * E]) = rb[h];                 \
+      *reinterpret_cast<u32x4*>(&Bs[BUF][(srow + h * RPP) * LDW + part * E]) = RB[h];                 \
+  }
+
+// Advance (EL, KSL) to the next stage and load it into (RA, RB).
+#define HTLR_LOAD_NEXT(RA, RB)                   \
+  {                                              \
+    if (++ksL == ksteps) { ksL = 0; ++eL; }      \
+    if (ksL == 0) HTLR_SET_DELTA(eL);            \
+    HTLR_GLOAD(RA, RB, ksL * KBE);               \
+  }
+#define HTLR_COMPUTE(CUR)                                                                                                        \
+  {                                                                                                                        \
+      const TE* Asb = As[CUR] + (wm * 64) * LDW;                                                                           \
+      const TE* Bsb = Bs[CUR] + (wn * WNC) * LDW;                                                                          \
+      if constexpr (std::is_same<TE, uint16_t>::value) {                                                                   \
+_Pragma("unroll")                                                                                                          \
+        for (int kk = 0; kk < KBE; kk += 16) {                                                                             \
+          bf16x8 a[TI], b[TJ];                                                                                             \
+_Pragma("unroll")                                                                                                          \
+          for (int i = 0; i < TI; ++i)                                                                                     \
+            a[i] = *reinterpret_cast<const bf16x8*>(&Asb[(i * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);            \
+_Pragma("unroll")                                                                                                          \
+          for (int j = 0; j < TJ; ++j)                                                                                     \
+            b[j] = *reinterpret_cast<const bf16x8*>(&Bsb[(j * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);            \
+_Pragma("unroll")                                                                                                          \
+          for (int i = 0; i < TI; ++i)                                                                                     \
+_Pragma("unroll")                                                                                                          \
+            for (int j = 0; j < TJ; ++j)                                                                                   \
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0); \
+        }                                                                                                                  \
+      } else if constexpr (std::is_same<TE, float>::value) {                                                               \
+_Pragma("unroll")                                                                                                          \
+        for (int kk = 0; kk < KBE; kk += 2) {                                                                              \
+          float a[TI], b[TJ];                                                                                              \
+_Pragma("unroll")                                                                                                          \
+          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];                        \
+_Pragma("unroll")                                                                                                          \
+          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];                        \
+_Pragma("unroll")                                                                                                          \
+          for (int i = 0; i < TI; ++i)                                                                                     \
+_Pragma("unroll")                                                                                                          \
+            for (int j = 0; j < TJ; ++j)                                                                                   \
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);  \
+        }                                                                                                                  \
+      } else {                                                                                                             \
+_Pragma("unroll")                                                                                                          \
+        for (int kk = 0; kk < KBE; kk += 4) {                                                                              \
+          double a[TI], b[TJ];                                                                                             \
+_Pragma("unroll")                                                                                                          \
+          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];                        \
+_Pragma("unroll")                                                                                                          \
+          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];                        \
+_Pragma("unroll")                                                                                                          \
+          for (int i = 0; i < TI; ++i)                                                                                     \
+_Pragma("unroll")                                                                                                          \
+            for (int j = 0; j < TJ; ++j)                                                                                   \
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);  \
+        }                                                                                                                  \
+      }                                                                                                                    \
+  }
+// One stage S held in LDS buffer CUR: (RAN, RBN) hold or receive stage
+// S + 1, (RAF, RBF) receive stage S + 2 (prefetch depth 2).
+#define HTLR_STEP(CUR, RAF, RBF, RAN, RBN, S)                       \
+  {                                                                 \
+    if constexpr (PD == 2) {                                        \
+      if ((S) + 2 < nstage) HTLR_LOAD_NEXT(RAF, RBF);               \
+    } else {                                                        \
+      if ((S) + 1 < nstage) HTLR_LOAD_NEXT(RAN, RBN);               \
+    }                                                               \
+    HTLR_COMPUTE(CUR);                                              \
+    if ((S) + 1 < nstage) HTLR_SSTORE(RAN, RBN, (CUR) ^ 1);         \
+    __syncthreads();                                                \
   }
 
   if (nstage > 0) {
+    int64_t eL = e0;   // position (offset entry, K step) of the last stage loaded
+    int ksL = 0;
     HTLR_SET_DELTA(e0);
-    HTLR_GLOAD(0);
-    HTLR_SSTORE(0);
+    HTLR_GLOAD(ra0, rb0, 0);
+    HTLR_SSTORE(ra0, rb0, 0);
+    if constexpr (PD == 2) {
+      if (nstage > 1) HTLR_LOAD_NEXT(ra1, rb1);
+    }
     __syncthreads();
-    int64_t e = e0;
-    int ks = 0;
-    for (int64_t st = 0; st < nstage; ++st) {
-      const int cur = (int)(st & 1);
-      int64_t en = e;
-      int ksn = ks + 1;
-      if (ksn == ksteps) { ksn = 0; ++en; }
-      const bool more = st + 1 < nstage;
-      if (more) {
-        if (ksn == 0) HTLR_SET_DELTA(en);
-        HTLR_GLOAD(ksn * KBE);
+    int64_t st = 0;
+    if constexpr (PD == 2) {
+      for (; st + 1 < nstage; st += 2) {
+        HTLR_STEP(0, ra0, rb0, ra1, rb1, st);
+        HTLR_STEP(1, ra1, rb1, ra0, rb0, st + 1);
       }
-      const TE* Asb = As[cur] + (wm * 64) * LDW;
-      const TE* Bsb = Bs[cur] + (wn * WNC) * LDW;
-      if constexpr (std::is_same<TE, uint16_t>::value) {
-#pragma unroll
-        for (int kk = 0; kk < KBE; kk += 16) {
-          bf16x8 a[TI], b[TJ];
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-            a[i] = *reinterpret_cast<const bf16x8*>(&Asb[(i * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-#pragma unroll
-          for (int j = 0; j < TJ; ++j)
-            b[j] = *reinterpret_cast<const bf16x8*>(&Bsb[(j * 32 + (lane & 31)) * LDW + kk + (lane >> 5) * 8]);
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-      } else if constexpr (std::is_same<TE, float>::value) {
-#pragma unroll
-        for (int kk = 0; kk < KBE; kk += 2) {
-          float a[TI], b[TJ];
-#pragma unroll
-          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 32 + (lane & 31)) * LDW + kk + (lane >> 5)];
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < KBE; kk += 4) {
-          double a[TI], b[TJ];
-#pragma unroll
-          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
+      if (st < nstage) HTLR_STEP(0, ra0, rb0, ra1, rb1, st);
+    } else {
+      // one register slot: stage s + 1 is loaded into it while s is computed
+      for (; st + 1 < nstage; st += 2) {
+        HTLR_STEP(0, ra1, rb1, ra0, rb0, st);
+        HTLR_STEP(1, ra1, rb1, ra0, rb0, st + 1);
       }
-      if (more) HTLR_SSTORE(cur ^ 1);
-      __syncthreads();
-      e = en;
-      ks = ksn;
+      if (st < nstage) HTLR_STEP(0, ra1, rb1, ra0, rb0, st);
     }
   }
+#undef HTLR_STEP
+#undef HTLR_COMPUTE
+#undef HTLR_LOAD_NEXT
 #undef HTLR_SET_DELTA
 #undef HTLR_GLOAD
 #undef HTLR_SSTORE
