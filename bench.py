@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
     ap.add_argument("--write-traffic", action="store_true",
                     help="with --summarize-profile: store per-launch HBM bytes for the roofline's traffic field")
+    ap.add_argument("--summarize-counters", default=None, metavar="DIR",
+                    help="print a markdown summary of rocprofv3 SQ counter passes (p1/, p2/) and exit")
     ap.add_argument("--summarize-profile", default=None, metavar="DIR",
                     help="print a markdown summary of a rocprofv3 run directory (stats/, fetch/, write/) and exit")
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
@@ -364,8 +366,47 @@ def summarize_profile(d, command, workload, prec):
     return "\n".join(lines) + "\n", fam
 
 
+def summarize_counters(d, command, workload, prec):
+    """Markdown summary of rocprofv3 SQ counter passes (CSV under d/p1, d/p2):
+    per kernel, MFMA and VALU utilisation against the chip's issue capacity.
+    Kernel cycles = GRBM_GUI_ACTIVE / 8 (the counter is summed over the 8
+    XCDs); 1024 SIMDs; an f64 16x16x4 MFMA keeps its SIMD's matrix pipe busy
+    64 cycles (SQ_VALU_MFMA_BUSY_CYCLES reads exactly that times
+    SQ_INSTS_MFMA); a wave64 VALU instruction issues over 4 cycles."""
+    import csv
+    import glob
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    for sub in ("p1", "p2"):
+        for f in glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                k = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")[:60]
+                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = [f"# rocprofv3 SQ counters: {workload}, {prec}", "", "Commands:", "", "```", command, "```", "",
+             "| kernel | dispatches | kernel us | MFMA busy | VALU busy | VALU instr / MFMA | LDS bank-conflict "
+             "cycles / LDS instr | waves |", "|---|---|---|---|---|---|---|---|"]
+    for k, v in sorted(vals.items(), key=lambda kv: -sum(kv[1].get("GRBM_GUI_ACTIVE", [0]))):
+        if "GRBM_GUI_ACTIVE" not in v or "SQ_INSTS_VALU" not in v:
+            continue
+        n = len(v["GRBM_GUI_ACTIVE"])
+        cyc = sum(v["GRBM_GUI_ACTIVE"]) / n / 8
+        mf = sum(v.get("SQ_VALU_MFMA_BUSY_CYCLES", [0])) / n
+        mi = sum(v.get("SQ_INSTS_MFMA", [0])) / n
+        va = sum(v["SQ_INSTS_VALU"]) / n - mi
+        li = sum(v.get("SQ_INSTS_LDS", [0])) / n
+        bc = sum(v.get("SQ_LDS_BANK_CONFLICT", [0])) / n
+        wv = sum(v.get("SQ_WAVES", [0])) / n
+        cap = cyc * 1024
+        lines.append(f"| {k} | {n} | {cyc / 2400:.1f} | {100 * mf / cap:.1f}% | {100 * 4 * va / cap:.1f}% | "
+                     f"{(va / mi) if mi else float('nan'):.2f} | {(bc / li) if li else 0:.2f} | {wv:.0f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.profile_command, args.workload, args.prec or ""))
+        return
     if args.summarize_profile:
         md, fam = summarize_profile(args.summarize_profile, args.profile_command, args.workload, args.prec or "")
         print(md)
