@@ -1082,10 +1082,11 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         TuneParams t;
         double md = 0, mb = 0;
         bool found = false;
-        // key ks_target near_kind near_nw tile core_mode near_ks near_tpw serial ms_default ms_best
+        // key ks_target near_kind near_nw tile core_mode near_ks near_tpw near_ct serial ms_default ms_best
         while (std::fgets(line, sizeof(line), fp))
-          if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind, &t.near_nw,
-                          &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw, &t.serial, &md, &mb) == 11 &&
+          if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind,
+                          &t.near_nw, &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw, &t.near_ct, &t.serial, &md,
+                          &mb) == 12 &&
               std::strcmp(k2, key) == 0) {
             A->tune[{nrhs, (int)prec}] = t;
             res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
@@ -1177,10 +1178,12 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
       if (ms < best_ms) { best_ms = ms; best = t; }
     }
     if (near_lv) {
+      for (int ct : {1, 2})
       for (int tpw : {4, 8})
-        for (int ks : {1, 2, 4, 8, 16, 32}) {
+        for (int ks : {1, 2, 4, 8, 12, 16, 24, 32}) {
           TuneParams t = best;
           t.near_kind = 2;
+          t.near_ct = ct;
           t.near_tpw = tpw;
           t.near_ks = ks;
           const double ms = time_with(t);
@@ -1218,8 +1221,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "a");
       if (fp) {
-        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind,
-                     best.near_nw, best.tile, best.core_mode, best.near_ks, best.near_tpw, best.serial,
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind,
+                     best.near_nw, best.tile, best.core_mode, best.near_ks, best.near_tpw, best.near_ct, best.serial,
                      res.ms_default, best_ms);
         std::fclose(fp);
       }

@@ -18,7 +18,8 @@
 // when that leaf lies outside the domain.  One 16x16x4 MFMA then does 1024
 // multiply-adds for one table read and one staged source value per lane,
 // where a row-per-lane VALU loop needs a table read for every few
-// multiply-adds.  A group holds 16 / nrhs leaves with equal or similar near
+// multiply-adds; with two 16-column tiles per wave each gathered value feeds
+// two MFMAs.  A group holds 16 CT / nrhs leaves with equal or similar near
 // offset lists (sorted by list, then Morton order), and its offset list is
 // the union of its members' (checked on the host to equal each member's own
 // list inside the domain).
@@ -41,9 +42,6 @@ namespace {
 typedef float nl_f32x4 __attribute__((ext_vector_type(4)));
 typedef double nl_f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNlLdu = 17;     // padded column stride of the staged sources
-constexpr int kNlJH = 256;     // source points staged at a time (half a leaf)
-
 __device__ __forceinline__ int64_t nl_lin3(int i0, int i1, int i2, int n) {
   return (int64_t)i0 + (int64_t)n * ((int64_t)i1 + (int64_t)n * i2);
 }
@@ -51,22 +49,36 @@ __device__ __forceinline__ int64_t nl_lin3(int i0, int i1, int i2, int n) {
 // Column descriptor: target leaf coordinates and rhs, or x = -1 (empty).
 struct NlCol { int x, y, z, r; };
 
-// TPW 16-row MFMA tiles per wave; 4 waves; a workgroup covers 64 * TPW rows.
-template <typename T, int TPW>
+// Staging: 2048 (source point, column) values per round, i.e. 128 source
+// points for 16 columns or 64 for 32; rows padded by one element.  The next
+// round is loaded into registers while the current one is computed.
+template <int CT> struct NlStage {
+  static constexpr int NC = 16 * CT;          // columns
+  static constexpr int JH = 2048 / NC;        // source points per round
+  static constexpr int LDU = NC + 1;          // padded row of the staged sources
+};
+
+// TPW 16-row MFMA tiles per wave, CT 16-column tiles (each gathered kernel
+// value feeds CT MFMAs); 4 waves; a workgroup covers 64 * TPW rows.
+template <typename T, int TPW, int CT>
 __global__ __launch_bounds__(256) void k_near_leaves(
     const T* __restrict__ u, T* __restrict__ out, const T* __restrict__ a, const int32_t* __restrict__ gmem,
     const int64_t* __restrict__ gptr, const int4* __restrict__ goff, const T* __restrict__ table, int tsize, int n,
     int B, int nrhs, int lpc, int64_t ngroups, int ksplit, int64_t part_stride) {
   using V4 = typename std::conditional<std::is_same<T, double>::value, nl_f64x4, nl_f32x4>::type;
+  using S = NlStage<CT>;
+  constexpr int NC = S::NC, JH = S::JH, LDU = S::LDU;
   constexpr int RB = 64 * TPW;           // rows per workgroup
   constexpr int NRB = 512 / RB;          // row blocks per leaf
   constexpr int TZ = TPW / 4;            // distinct z rows of a lane's tiles
+  constexpr int CPT = NC * JH / 256;     // staged values per thread per round (8)
   static_assert(TPW == 4 || TPW == 8, "4 or 8 tiles per wave");
+  static_assert(CT == 1 || CT == 2, "one or two column tiles");
   extern __shared__ unsigned char smem_raw[];
   T* tab = reinterpret_cast<T*>(smem_raw);
   const int tpad = (tsize + 3) & ~3;
-  T* us = tab + tpad;                                       // [kNlJH][kNlLdu]
-  NlCol* ccol = reinterpret_cast<NlCol*>(us + kNlJH * kNlLdu);   // [16]
+  T* us = tab + tpad;                                       // [JH][LDU]
+  NlCol* ccol = reinterpret_cast<NlCol*>(us + JH * LDU);    // [NC]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
   // Work items are dealt to the 8 XCDs round robin; consecutive items (one
@@ -80,7 +92,7 @@ __global__ __launch_bounds__(256) void k_near_leaves(
   const int64_t grp = q / ((int64_t)ksplit * NRB);
 
   for (int s = tid; s < tsize; s += 256) tab[s] = table[s];
-  if (tid < 16) {
+  if (tid < NC) {
     const int lc = tid / nrhs, r = tid % nrhs;
     NlCol c{-1, 0, 0, 0};
     if (lc < lpc) {
@@ -109,11 +121,32 @@ __global__ __launch_bounds__(256) void k_near_leaves(
 #pragma unroll
   for (int k = 0; k < TZ; ++k) iz[k] = (wbase >> 6) + k;
 
-  V4 acc[TPW];
+  V4 acc[TPW][CT];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = V4{T(0), T(0), T(0), T(0)};
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[t][c] = V4{T(0), T(0), T(0), T(0)};
 
   const int64_t N = (int64_t)n * n * n;
+  // staged value k of this thread: source point jj of the round, column cs + k * (256 / JH)
+  const int jj = tid % JH, cs = tid / JH;
+  constexpr int NR = 512 / JH;            // rounds per offset
+  T pre[CPT];                              // the next round, loaded ahead
+#define NL_LOAD(OFF, RND)                                                                              \
+  {                                                                                                    \
+    const int j_ = (RND) * JH + jj;                                                                    \
+    const int jx_ = j_ & 7, jy_ = (j_ >> 3) & 7, jz_ = j_ >> 6;                                        \
+    _Pragma("unroll") for (int k = 0; k < CPT; ++k) {                                                  \
+      const NlCol cc = ccol[cs + k * (256 / JH)];                                                      \
+      const int sx = cc.x + (OFF).x, sy = cc.y + (OFF).y, sz = cc.z + (OFF).z;                         \
+      const bool ok = cc.x >= 0 && sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B;        \
+      pre[k] = ok ? u[(int64_t)cc.r * N + nl_lin3(sx * 8 + jx_, sy * 8 + jy_, sz * 8 + jz_, n)] : T(0); \
+    }                                                                                                  \
+  }
+  if (e0 < e1) {
+    const int4 o0 = goff[e0];
+    NL_LOAD(o0, 0);
+  }
   for (int64_t e = e0; e < e1; ++e) {
     const int4 o = goff[e];
     // point displacement I - J = (i - j) - 8 Delta, per dimension
@@ -123,71 +156,73 @@ __global__ __launch_bounds__(256) void k_near_leaves(
     for (int k = 0; k < 4; ++k) cy[k] = iy[k] - 8 * o.y;
 #pragma unroll
     for (int k = 0; k < TZ; ++k) cz[k] = iz[k] - 8 * o.z;
-    for (int half = 0; half < 2; ++half) {
+    for (int round = 0; round < NR; ++round) {
       __syncthreads();
-      {
-        // stage u at source points j = 256 half + tid of the 16 columns
-        const int j = half * kNlJH + tid;
-        const int jx = j & 7, jy = (j >> 3) & 7, jz = j >> 6;
-#pragma unroll 4
-        for (int c = 0; c < 16; ++c) {
-          const NlCol cc = ccol[c];
-          const int sx = cc.x + o.x, sy = cc.y + o.y, sz = cc.z + o.z;
-          const bool ok = cc.x >= 0 && sx >= 0 && sx < B && sy >= 0 && sy < B && sz >= 0 && sz < B;
-          us[tid * kNlLdu + c] = ok ? u[(int64_t)cc.r * N + nl_lin3(sx * 8 + jx, sy * 8 + jy, sz * 8 + jz, n)] : T(0);
-        }
-      }
-      __syncthreads();
-      const T* ub = us + l15;
-      for (int zz = 0; zz < 4; ++zz) {
-        const int jz = half * 4 + zz;
-        int dz2[TZ];
 #pragma unroll
-        for (int k = 0; k < TZ; ++k) dz2[k] = (cz[k] - jz) * (cz[k] - jz);
-        for (int jy = 0; jy < 8; ++jy) {
-          int dyz[TPW];
+      for (int k = 0; k < CPT; ++k) us[jj * LDU + cs + k * (256 / JH)] = pre[k];
+      __syncthreads();
+      if (round + 1 < NR) {
+        NL_LOAD(o, round + 1);
+      } else if (e + 1 < e1) {
+        const int4 on = goff[e + 1];
+        NL_LOAD(on, 0);
+      }
+      const T* ub = us + l15;
+      // the round's source points are whole x-lines: JH / 8 lines, 2 K steps each
+      for (int line = 0; line < JH / 8; ++line) {
+        const int jabs = round * JH + line * 8;      // first point of the line
+        const int jy = (jabs >> 3) & 7, jz = jabs >> 6;
+        int dyz[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          const int dy = cy[t & 3] - jy, dz = cz[t >> 2] - jz;
+          dyz[t] = dy * dy + dz * dz;
+        }
+#pragma unroll
+        for (int xh = 0; xh < 2; ++xh) {
+          const int jx = 4 * xh + jl;
+          const int dx = cx - jx;
+          const int dx2 = dx * dx;
+          const int jloc = line * 8 + jx;              // staged row of this lane's source
+          T b[CT];
+#pragma unroll
+          for (int c = 0; c < CT; ++c) b[c] = ub[jloc * LDU + 16 * c];
 #pragma unroll
           for (int t = 0; t < TPW; ++t) {
-            const int dy = cy[t & 3] - jy;
-            dyz[t] = dy * dy + dz2[t >> 2];
-          }
+            const T av = tab[dx2 + dyz[t]];
 #pragma unroll
-          for (int xh = 0; xh < 2; ++xh) {
-            const int jx = 4 * xh + jl;
-            const int dx = cx - jx;
-            const int dx2 = dx * dx;
-            const int jloc = zz * 64 + jy * 8 + jx;     // staged row of this lane's source
-            const T b = ub[jloc * kNlLdu];
-#pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-              const T av = tab[dx2 + dyz[t]];
+            for (int c = 0; c < CT; ++c) {
               if constexpr (std::is_same<T, double>::value)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[t], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[c], acc[t][c], 0, 0, 0);
               else
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[t], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[c], acc[t][c], 0, 0, 0);
             }
           }
         }
       }
     }
   }
+#undef NL_LOAD
 
-  // write the owned tile: f (single split, with the diagonal) or a partial sum
-  const NlCol cc = ccol[l15];
-  if (cc.x < 0) return;
+  // write the owned tiles: f (single split, with the diagonal) or a partial sum
   T* o = out + (ksplit > 1 ? (int64_t)split * part_stride : 0);
 #pragma unroll
-  for (int t = 0; t < TPW; ++t)
+  for (int c = 0; c < CT; ++c) {
+    const NlCol cc = ccol[16 * c + l15];
+    if (cc.x < 0) continue;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // accumulator layouts of 16x16x4: f32 register v holds row 4 (lane/16) + v,
-      // f64 register v holds row lane/16 + 4 v; the column is lane % 16
-      const int row = std::is_same<T, double>::value ? jl + 4 * v : 4 * jl + v;
-      const int i = wbase + 16 * t + row;
-      const int64_t g = nl_lin3(cc.x * 8 + (i & 7), cc.y * 8 + ((i >> 3) & 7), cc.z * 8 + (i >> 6), n);
-      const int64_t idx = (int64_t)cc.r * N + g;
-      o[idx] = ksplit > 1 ? acc[t][v] : acc[t][v] + a[g] * u[idx];
-    }
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // accumulator layouts of 16x16x4: f32 register v holds row 4 (lane/16) + v,
+        // f64 register v holds row lane/16 + 4 v; the column is lane % 16
+        const int row = std::is_same<T, double>::value ? jl + 4 * v : 4 * jl + v;
+        const int i = wbase + 16 * t + row;
+        const int64_t g = nl_lin3(cc.x * 8 + (i & 7), cc.y * 8 + ((i >> 3) & 7), cc.z * 8 + (i >> 6), n);
+        const int64_t idx = (int64_t)cc.r * N + g;
+        o[idx] = ksplit > 1 ? acc[t][c][v] : acc[t][c][v] + a[g] * u[idx];
+      }
+  }
 }
 
 // f = sum of the K-split parts in split order + a(x_i) u_i.
@@ -209,8 +244,9 @@ uint64_t nl_morton3(uint32_t x, uint32_t y, uint32_t z) {
   return m;
 }
 
-size_t nl_lds_bytes(const htlr_matrix_impl& A, size_t esz) {
-  return (((size_t)A.Tsize + 3) & ~size_t(3)) * esz + (size_t)kNlJH * kNlLdu * esz + 16 * sizeof(NlCol);
+size_t nl_lds_bytes(const htlr_matrix_impl& A, size_t esz, int ct) {
+  const size_t stage = ct == 2 ? (size_t)NlStage<2>::JH * NlStage<2>::LDU : (size_t)NlStage<1>::JH * NlStage<1>::LDU;
+  return (((size_t)A.Tsize + 3) & ~size_t(3)) * esz + stage * esz + 16 * ct * sizeof(NlCol);
 }
 
 // Groups of lpc leaves, built on first use; nullptr when some leaf's near
@@ -294,14 +330,15 @@ NearGroups* groups_for(htlr_matrix_impl& A, int lpc, bool frozen) {
 bool near_leaves_ok(const htlr_matrix_impl& A, int nrhs, int prec) {
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
   return A.uniform && A.d == 3 && A.plan.m[A.L] == 8 && A.kid != HTLR_K_POLY_TEST && nrhs >= 1 && nrhs <= 8 &&
-         nl_lds_bytes(A, esz) <= 64 * 1024;
+         nl_lds_bytes(A, esz, 1) <= 64 * 1024 && nl_lds_bytes(A, esz, 2) <= 64 * 1024;
 }
 
 // Tiles per wave and K splits of the leaf-column near kernel.
 NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool frozen) {
   NearLeavesShape s;
   (void)prec;
-  s.lpc = 16 / nrhs;
+  s.ct = A.cur.near_ct == 2 ? 2 : 1;
+  s.lpc = 16 * s.ct / nrhs;
   NearGroups* G = groups_for(A, s.lpc, frozen);
   if (!G) return s;
   s.ok = true;
@@ -310,9 +347,9 @@ NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool 
   if (A.cur.near_ks > 0) {
     s.ks = A.cur.near_ks;
   } else {
-    // aim for about 1024 workgroups (3 per CU fit the LDS), at least 4 offsets per split
-    s.ks = 1;
-    while (s.ks < 32 && base * s.ks < 1024 && G->maxlist / (s.ks * 2) >= 4) s.ks *= 2;
+    // aim for about 768 workgroups (3 per CU, as the LDS allows), at least 4 offsets per split
+    s.ks = (int)std::max<int64_t>(1, std::min<int64_t>((768 + base / 2) / std::max<int64_t>(base, 1),
+                                                       std::max<int64_t>(G->maxlist / 4, 1)));
   }
   s.ks = (int)std::max<int64_t>(1, std::min<int64_t>(s.ks, std::max<int64_t>(G->maxlist, 1)));
   s.parts_bytes = s.ks > 1 ? (size_t)s.ks * A.N * nrhs * (prec == HTLR_FP64 ? 8 : 4) : 0;
@@ -346,15 +383,17 @@ void launch_near_leaves(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int pre
   const int64_t nitems = G->ngroups * (512 / (64 * s.tpw)) * s.ks;
   const int64_t grid = (nitems + 7) / 8 * 8;
   if (grid > 0x7fffffff) fail(HTLR_ERR_UNSUPPORTED, "near-field work list too large");
-  const size_t sh = nl_lds_bytes(A, sizeof(T));
-  if (s.tpw == 4)
-    hipLaunchKernelGGL((k_near_leaves<T, 4>), dim3((unsigned)grid), dim3(256), sh, st, u, out, a,
-                       G->mem.as<int32_t>(), G->ptr.as<int64_t>(), G->off.as<int4>(), tab, A.Tsize, A.n, B, nrhs,
-                       s.lpc, G->ngroups, s.ks, total);
-  else
-    hipLaunchKernelGGL((k_near_leaves<T, 8>), dim3((unsigned)grid), dim3(256), sh, st, u, out, a,
-                       G->mem.as<int32_t>(), G->ptr.as<int64_t>(), G->off.as<int4>(), tab, A.Tsize, A.n, B, nrhs,
-                       s.lpc, G->ngroups, s.ks, total);
+  const size_t sh = nl_lds_bytes(A, sizeof(T), s.ct);
+#define HTLR_NL(TPWV, CTV)                                                                                      \
+  hipLaunchKernelGGL((k_near_leaves<T, TPWV, CTV>), dim3((unsigned)grid), dim3(256), sh, st, u, out, a,        \
+                     G->mem.as<int32_t>(), G->ptr.as<int64_t>(), G->off.as<int4>(), tab, A.Tsize, A.n, B, nrhs, \
+                     s.lpc, G->ngroups, s.ks, total)
+  if (s.tpw == 4) {
+    if (s.ct == 2) HTLR_NL(4, 2); else HTLR_NL(4, 1);
+  } else {
+    if (s.ct == 2) HTLR_NL(8, 2); else HTLR_NL(8, 1);
+  }
+#undef HTLR_NL
   HTLR_HIP(hipGetLastError());
   if (s.ks > 1) {
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);

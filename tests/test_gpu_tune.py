@@ -79,7 +79,7 @@ def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mo
     pid = {"fp64": 0, "fp32": 1, "bf16": 2}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 0 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 0 0 1.0 1.0\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]
@@ -107,21 +107,22 @@ _NEAR_REF = {}
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("nrhs", [1, 5])
-@pytest.mark.parametrize("near_kind,nw,ks,tpw", [(1, 0, 0, 0), (0, 1, 0, 0), (0, 8, 0, 0), (2, 0, 1, 8), (2, 0, 4, 4),
-                                                 (2, 0, 32, 8)])
-def test_every_near_variant_matches(torch, tmp_path, monkeypatch, prec, nrhs, near_kind, nw, ks, tpw):
+@pytest.mark.parametrize("near_kind,nw,ks,tpw,ct", [(1, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 0, 0, 0), (2, 0, 1, 8, 1),
+                                                    (2, 0, 4, 4, 1), (2, 0, 32, 8, 1), (2, 0, 1, 8, 2),
+                                                    (2, 0, 8, 4, 2)])
+def test_every_near_variant_matches(torch, tmp_path, monkeypatch, prec, nrhs, near_kind, nw, ks, tpw, ct):
     """Force the near-field variant through the tuner's cache file and compare
     with the oracle: matrix cores with right-hand sides as columns (1), VALU
     rows with 1 or 8 waves per leaf (0), matrix cores with target leaves as
-    columns (2) at several K splits and tiles per wave."""
+    columns (2) at several K splits, row tiles and column tiles per wave."""
     import paper_2508_05958_amd as H
     from oracle import geometry, htlr
-    _say(f"[gpu] forced near kind={near_kind} nw={nw} ks={ks} tpw={tpw} {prec} nrhs={nrhs}")
+    _say(f"[gpu] forced near kind={near_kind} nw={nw} ks={ks} tpw={tpw} ct={ct} {prec} nrhs={nrhs}")
     n, p, leaf = 32, 4, 8
     pid = {"fp64": 0, "fp32": 1}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k1_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 {near_kind} {nw} 0 0 {ks} {tpw} 0 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 {near_kind} {nw} 0 0 {ks} {tpw} {ct} 0 1.0 1.0\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]
@@ -153,7 +154,7 @@ def test_level_concurrency_is_bitwise_serial(torch, tmp_path, monkeypatch, prec,
     for serial in (0, 1):
         cache = tmp_path / f"tune{serial}.txt"
         key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-        cache.write_text(f"{key} 2048 -1 0 0 0 0 0 {serial} 1.0 1.0\n")
+        cache.write_text(f"{key} 2048 -1 0 0 0 0 0 0 {serial} 1.0 1.0\n")
         monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
         M = H.htlr_build(None, "inv_r", 3, n, p, leaf, a=np.ones(n ** 3))
         assert sum(1 for x in M.info()["adm_pairs"] if x) >= 2
