@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
+    ap.add_argument("--no-tables", action="store_true", help="skip construction at the paper's table shapes")
     ap.add_argument("--write-traffic", action="store_true",
                     help="with --summarize-profile: store per-launch HBM bytes for the roofline's traffic field")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
@@ -210,6 +211,60 @@ def cpu_baseline(w, count, f_gpu):
             "sample": f"{len(pick)} seeded leaf boxes ({len(rows)} rows x {w.nrhs} rhs) of {w.name}; plain NumPy "
                       f"FP64 HTLR product (Alg. 4.2) restricted to those rows, one leaf per task on {cores} "
                       f"processes: {wall:.1f} s wall, {busy:.1f} s CPU"}, err
+
+
+# Construction at the shapes of the paper's Tables 5.1-5.4 (a = 0, FP64):
+# (table, d, kernel, admissibility, p, leaf threshold, n, the paper's
+# printed t_c in s and m_h in GB on its CPU).  Strong admissibility takes
+# eta^2 = d, as in Prop. 3.9; the paper's kernels carry constants 1/(2 pi),
+# 1/(4 pi) that do not change relative errors or timings.
+PAPER_SHAPES = [
+    ("5.1", 2, "gauss", "weak", 8, 16, [(256, 1.5, 0.16), (512, 3.8, 0.65), (1024, 16, 2.6), (2048, 68, 10),
+                                        (4096, 280, 41)]),
+    ("5.2", 2, "neg_log", "strong", 8, 16, [(256, 7.6, 1.3), (512, 30, 5.4), (1024, 130, 23), (2048, 540, 92),
+                                            (4096, 2100, 370)]),
+    ("5.3", 3, "gauss", "weak", 4, 5, [(32, 4.0, 0.14), (64, 27, 1.2), (128, 220, 9.2), (256, 1800, 74)]),
+    ("5.4", 3, "inv_r", "strong", 4, 5, [(32, 48, 2.1), (64, 540, 23), (128, 5100, 210)]),
+]
+
+
+def paper_tables_block(H, torch, np):
+    """Build time t_c (host planning + GPU construction, synchronised), device
+    bytes m_h and the FP64 product time at the paper's shapes.  Accuracy at
+    these shapes is checked against the oracle in the GPU tests."""
+    H.htlr_build(None, "gauss", 2, 64, 8, 16, a=np.zeros(64 * 64), admissibility="weak").free()   # warm-up
+    rows = []
+    for table, d, kern, adm, p, leaf, sizes in PAPER_SHAPES:
+        for n, tc_paper, mh_paper in sizes:
+            N = n ** d
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            M = H.htlr_build(None, kern, d, n, p, leaf, a=np.zeros(N), eta2=float(d) if adm == "strong" else 1.0,
+                             admissibility=adm, precisions=["fp64"])
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            info = M.info()
+            u = torch.randn(N, dtype=torch.float64, device="cuda", generator=None)
+            f = M.matvec(u, prec="fp64")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                M.matvec(u, f, prec="fp64")
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            rows.append({"table": table, "d": d, "kernel": KERNEL_LABEL[kern], "admissibility": adm, "p": p,
+                         "leaf": leaf, "n": n, "N": N, "t_c_s": round(tc, 4),
+                         "m_h_GB": round(info["device_bytes"] / 1e9, 4), "matvec_ms": round(ms, 3),
+                         "paper_t_c_s": tc_paper, "paper_m_h_GB": mh_paper})
+            print(f"[bench]   table {table} n={n}: t_c {tc:.3f} s, {info['device_bytes'] / 1e9:.3f} GB, "
+                  f"matvec {ms:.2f} ms", file=sys.stderr, flush=True)
+            M.free()
+            del u, f
+            torch.cuda.empty_cache()
+    return {"note": "t_c and m_h as the paper's Tables 5.1-5.4 define them, on one MI355X; the paper's figures "
+                    "are from a Xeon Gold 6226R in MATLAB and store one block per admissible leaf",
+            "rows": rows}
 
 
 def solve_block(H, torch, np, W):
@@ -484,6 +539,10 @@ def main():
             del f3
             torch.cuda.empty_cache()
         out["w3d_invr_n128_r16"] = block
+    if not args.no_tables:
+        print("[bench] construction at the paper's table shapes", file=sys.stderr, flush=True)
+        out["paper_tables"] = paper_tables_block(H, torch, np)
+        torch.cuda.empty_cache()
     if not args.no_solve:
         print("[bench] warped-grid solve (FP32-IR and FP64 GMRES)", file=sys.stderr, flush=True)
         out["w3d_exp_warp_n96_solve"] = solve_block(H, torch, np, W)

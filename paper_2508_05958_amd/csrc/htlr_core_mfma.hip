@@ -64,27 +64,33 @@ __device__ __forceinline__ gptr<TE> col_src(gptr<TE> W, gptr<TE> zero, int ct, i
 // bfloat16 and the 256-row tile (LDS and registers).
 template <typename TE, int BMT, int BNT>
 constexpr int stage_bytes() {
-  return (sizeof(TE) >= 4 && BMT == 128) ? 128 : 64;
+  return (sizeof(TE) >= 4 && BMT == 128 && !(sizeof(TE) == 8 && BNT == 64)) ? 128 : 64;
 }
+
+// Rows per wave: 64, or 112 (seven 16-row f64 MFMA tiles) for the 224-row
+// tile, which holds p^d = 216 (p = 6, d = 3) core rows in one block.
+constexpr int core_wave_rows(int bmt) { return bmt == 224 ? 112 : 64; }
+constexpr int core_threads(int bmt) { return 128 * (bmt / core_wave_rows(bmt)); }
 
 // Stages in flight per thread (1 or 2): 2 where the extra register slot
 // keeps the same number of waves per SIMD.
 template <typename TE, int BMT, int BNT>
 constexpr int prefetch_depth() {
-  return (sizeof(TE) == 8 && BMT == 128 && BNT == 128) ? 1 : 2;
+  return (sizeof(TE) == 8) ? 1 : 2;
 }
 
-// BMT x BNT output tile per workgroup; 2 BMT threads; waves arranged
-// (BMT / 64) x 2, each owning 64 rows x BNT/2 columns.
+// BMT x BNT output tile per workgroup; waves arranged (BMT / WR) x 2, each
+// owning WR rows x BNT/2 columns (WR = core_wave_rows(BMT)).
 template <typename TE, int BMT, int BNT>
-__global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) void k_core_mfma(
+__global__ __launch_bounds__(core_threads(BMT)) __attribute__((amdgpu_waves_per_eu(2))) void k_core_mfma(
     const TE* __restrict__ G, const TE* __restrict__ W, const TE* __restrict__ zero,
     typename AccT<TE>::type* __restrict__ H, const int32_t* __restrict__ tile_tau,
     const int64_t* __restrict__ tile_ptr, const int4* __restrict__ tile_off, const int32_t* __restrict__ items,
     int nitems, int ksplit, int64_t part_stride, int P, int nrhs, int NB, int B, const int32_t* __restrict__ tile_out) {
   using TA = typename AccT<TE>::type;
   const gptr<TE> Gg = (gptr<TE>)G, Wg = (gptr<TE>)W, zg = (gptr<TE>)zero;
-  constexpr int NT = 2 * BMT;             // threads
+  constexpr int NT = core_threads(BMT);   // threads
+  constexpr int WR = core_wave_rows(BMT); // rows per wave
   constexpr int E = 16 / sizeof(TE);      // elements per 16-byte chunk
   constexpr int CB = stage_bytes<TE, BMT, BNT>();
   constexpr int PD = prefetch_depth<TE, BMT, BNT>();
@@ -92,10 +98,11 @@ __global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) vo
   constexpr int LDW = KBE + E;            // padded LDS row
   constexpr int CPR = CB / 16;            // 16-byte chunks per staged row
   constexpr int RPP = NT / CPR;           // rows staged per pass of all threads
-  constexpr int NA = BMT / RPP;           // A rows staged per thread
+  constexpr int NA = (BMT + RPP - 1) / RPP;   // A rows staged per thread (the last pass may be partial)
   constexpr int NBH = BNT / RPP;          // B columns staged per thread
   constexpr int WNC = BNT / 2;            // columns per wave
-  static_assert(NA >= 1 && NBH >= 1 && NA * RPP == BMT && NBH * RPP == BNT, "staging shape");
+  static_assert(NA >= 1 && NBH >= 1 && NBH * RPP == BNT, "staging shape");
+  constexpr bool APART = NA * RPP != BMT;     // rows srow + (NA - 1) RPP >= BMT are not staged
   __shared__ __align__(16) TE As[2][BMT * LDW];
   __shared__ __align__(16) TE Bs[2][BNT * LDW];
 
@@ -154,7 +161,8 @@ __global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) vo
   const int wm = wv >> 1, wn = wv & 1;
   constexpr bool k16 = std::is_same<TE, double>::value;   // 16x16 tiles for f64
   constexpr int TM = k16 ? 16 : 32;                        // MFMA tile side
-  constexpr int TI = 64 / TM, TJ = WNC / TM;               // MFMA tiles per wave
+  constexpr int TI = WR / TM, TJ = WNC / TM;               // MFMA tiles per wave
+  static_assert(TI * TM == WR, "wave rows in whole MFMA tiles");
   using AccV = typename std::conditional<k16, f64x4, f32x16>::type;
   AccV acc[TI][TJ];
 #pragma unroll
@@ -177,7 +185,8 @@ __global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) vo
     const bool kin_ = k_ < P;                                                                            \
     _Pragma("unroll") for (int i = 0; i < NA; ++i) {                                                     \
       const int ar_ = m0 + srow + i * RPP;                                                               \
-      const gptr<TE> pa_ = (kin_ && ar_ < P) ? gA + (int64_t)ar_ * P + k_ : zg;                          \
+      const bool ain_ = !APART || srow + i * RPP < BMT;                                                  \
+      const gptr<TE> pa_ = (kin_ && ain_ && ar_ < P) ? gA + (int64_t)ar_ * P + k_ : zg;                  \
       RA[i] = *(gptr<u32x4>)pa_;                                                                         \
     }                                                                                                    \
     _Pragma("unroll") for (int h = 0; h < NBH; ++h) {                                                    \
@@ -188,7 +197,8 @@ __global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) vo
 #define HTLR_SSTORE(RA, RB, BUF)                                                                      \
   {                                                                                                   \
     _Pragma("unroll") for (int i = 0; i < NA; ++i)                                                    \
-      *reinterpret_cast<u32x4*>(&As[BUF][(srow + i * RPP) * LDW + part * E]) = RA[i];                 \
+      if (!APART || srow + i * RPP < BMT)                                                             \
+        *reinterpret_cast<u32x4*>(&As[BUF][(srow + i * RPP) * LDW + part * E]) = RA[i];               \
     _Pragma("unroll") for (int h = 0; h < NBH; ++h)                                                   \
       *reinterpret_cast<u32x4*>(&Bs[BUF][(srow + h * RPP) * LDW + part * E]) = RB[h];                 \
   }
@@ -202,7 +212,7 @@ __global__ __launch_bounds__(2 * BMT) __attribute__((amdgpu_waves_per_eu(2))) vo
   }
 #define HTLR_COMPUTE(CUR)                                                                                                        \
   {                                                                                                                        \
-      const TE* Asb = As[CUR] + (wm * 64) * LDW;                                                                           \
+      const TE* Asb = As[CUR] + (wm * WR) * LDW;                                                                           \
       const TE* Bsb = Bs[CUR] + (wn * WNC) * LDW;                                                                          \
       if constexpr (std::is_same<TE, uint16_t>::value) {                                                                   \
 _Pragma("unroll")                                                                                                          \
@@ -313,13 +323,13 @@ _Pragma("unroll")                                                               
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           // f64 16x16x4 accumulator: register v holds row lane/16 + 4 v
-          const int row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
+          const int row = m0 + wm * WR + i * 16 + (lane >> 4) + 4 * v;
           if (row < P) Ho[row] = acc[i][j][v];
         }
       } else {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int row = m0 + wm * 64 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+          const int row = m0 + wm * WR + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
           if (row < P) Ho[row] = acc[i][j][v];
         }
       }
@@ -421,18 +431,29 @@ static int core_mfma_nb(int nrhs, int bnt) {
 }
 
 // Tile shape for one level: 1 = 128x128, 2 = 128x64 (few columns), 3 = 256x128.
+// 64-column tiles in FP64 take the 224-row shape when p^d fits it better
+// than 128-row blocks do (192 < p^d <= 224).
+static int narrow_variant(const htlr_matrix_impl& A, int prec) {
+  return (prec == HTLR_FP64 && A.P > 192 && A.P <= 224) ? 4 : 2;
+}
+
 static int pick_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
-  if (A.cur.tile >= 1 && A.cur.tile <= 3) return A.cur.tile;
+  if (A.cur.tile >= 1 && A.cur.tile <= 4) return A.cur.tile;
   const int64_t class_boxes = lv.nbox >> A.d;
-  if (class_boxes * nrhs <= 64) return 2;
+  if (class_boxes * nrhs <= 64) return narrow_variant(A, prec);
   if (prec == HTLR_BF16_CORE && A.P >= 256) return 3;
   return 1;
 }
 
-static void variant_shape(int v, int* bmt, int* bnt) {
-  *bmt = v == 3 ? 256 : 128;
-  *bnt = v == 2 ? 64 : 128;
+// Tile shape of a variant: 1 = 128x128, 2 = 128x64, 3 = 256x128, 4 = 224x64
+// (FP64; the other precisions run variant 4 as 128x64).
+static void variant_shape(int v, int prec, int* bmt, int* bnt) {
+  *bmt = v == 3 ? 256 : (v == 4 && prec == HTLR_FP64 ? 224 : 128);
+  *bnt = (v == 2 || v == 4) ? 64 : 128;
 }
+
+template <typename TE> struct NarrowRows { static constexpr int value = 128; };
+template <> struct NarrowRows<double> { static constexpr int value = 224; };
 
 // Sums the K-split partial results in a fixed order: H = sum_s part_s.
 template <typename TA>
@@ -477,7 +498,7 @@ static void launch_variant(const TE* G, const TE* W, const TE* zero, void* H, co
                            int nb, int B, hipStream_t st) {
   using TA = typename AccT<TE>::type;
   const unsigned nwg = (unsigned)(((I.n + 7) / 8) * 8);
-  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(2 * BMT), 0, st, G, W, zero, (TA*)H, tau, ptr, off,
+  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(core_threads(BMT)), 0, st, G, W, zero, (TA*)H, tau, ptr, off,
                      I.buf.as<int32_t>(), I.n, ks, helems, P, nrhs, nb, B, (const int32_t*)nullptr);
 }
 
@@ -486,7 +507,7 @@ static void launch_variant_out(const TE* G, const TE* W, const TE* zero, void* H
                                int P, int nrhs, int B, hipStream_t st) {
   using TA = typename AccT<TE>::type;
   const unsigned nwg = (unsigned)(((T.nitems + 7) / 8) * 8);
-  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(2 * BMT), 0, st, G, W, zero, (TA*)H,
+  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(core_threads(BMT)), 0, st, G, W, zero, (TA*)H,
                      T.tau.as<int32_t>(), T.ptr.as<int64_t>(), T.off.as<int4>(), T.items.as<int32_t>(), T.nitems, 1,
                      (int64_t)0, P, nrhs, T.nb, B, T.out.as<int32_t>());
 }
@@ -602,10 +623,10 @@ static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int
 
 // Tile shape of the offset-major mode: 128x64 unless an offset's boxes
 // times right-hand sides fill well over 128 columns on average.
-static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs) {
-  if (A.cur.tile >= 1 && A.cur.tile <= 3) return A.cur.tile;
+static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
+  if (A.cur.tile >= 1 && A.cur.tile <= 4) return A.cur.tile;
   const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
-  return avg * nrhs <= 128 ? 2 : 1;
+  return avg * nrhs <= 128 ? narrow_variant(A, prec) : 1;
 }
 
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
@@ -616,9 +637,9 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   DevBuf& pairs = A.ws.pairs[lv.level];
   if (nrhs > kBNmax) fail(HTLR_ERR_UNSUPPORTED, "too many right-hand sides for the matrix-core tile");
   if (use_offset_major(A, lv, nrhs, prec)) {
-    const int var = offset_major_variant(A, lv, nrhs);
+    const int var = offset_major_variant(A, lv, nrhs, prec);
     int bmt, bnt;
-    variant_shape(var, &bmt, &bnt);
+    variant_shape(var, prec, &bmt, &bnt);
     const int nb = core_mfma_nb(nrhs, bnt);
     const int nmb = (A.P + bmt - 1) / bmt;
     LevelData::OffsetTiles& T = offset_tiles_for(A, lv, nb, nmb, A.ws.frozen);
@@ -632,6 +653,8 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
 #define HTLR_LVO(TE, GPTR)                                                                                         \
   switch (var) {                                                                                                 \
     case 2: launch_variant_out<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
+    case 4: launch_variant_out<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs,  \
+                                                             lv.B, st); break;                                       \
     case 3: launch_variant_out<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;  \
     default: launch_variant_out<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break; \
   }
@@ -656,7 +679,7 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   }
   const int var = pick_variant(A, lv, nrhs, prec);
   int bmt, bnt;
-  variant_shape(var, &bmt, &bnt);
+  variant_shape(var, prec, &bmt, &bnt);
   const int nb = core_mfma_nb(nrhs, bnt);
   LevelData::Tiles& T = tiles_for(A, lv, nb);
   if (T.ntile == 0) return;
@@ -681,6 +704,8 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
 #define HTLR_LV(TE, GPTR)                                                                                          \
   switch (var) {                                                                                                 \
     case 2: launch_variant<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
+                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+    case 4: launch_variant<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
                                         A.P, nrhs, nb, lv.B, st); break;                                         \
     case 3: launch_variant<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems, \
                                          A.P, nrhs, nb, lv.B, st); break;                                        \
@@ -727,13 +752,13 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
         const int l = lv.level;
         if (use_offset_major(A, lv, c, prec)) {
           int bmt, bnt;
-          variant_shape(offset_major_variant(A, lv, c), &bmt, &bnt);
+          variant_shape(offset_major_variant(A, lv, c, prec), prec, &bmt, &bnt);
           offset_tiles_for(A, lv, core_mfma_nb(c, bnt), (A.P + bmt - 1) / bmt, false);
           pairs_need[l] = std::max(pairs_need[l], (size_t)lv.npairs * c * A.P * esz);
           continue;
         }
         int bmt, bnt;
-        variant_shape(pick_variant(A, lv, c, prec), &bmt, &bnt);
+        variant_shape(pick_variant(A, lv, c, prec), prec, &bmt, &bnt);
         LevelData::Tiles& T = tiles_for(A, lv, core_mfma_nb(c, bnt));
         if (T.ntile == 0) continue;
         const int nmb = (A.P + bmt - 1) / bmt;

@@ -89,12 +89,13 @@ struct Workspace {
   int nrhs = 0;
   bool frozen = false;               // reserved: products must not reallocate
   std::vector<DevBuf> W, H, W16;     // per level
+  std::vector<DevBuf> UP;            // per level: partial up contractions of split boxes
   DevBuf zero;                       // a zero source tensor (matrix-core kernel)
   // per level (levels run concurrently): K-split partial sums of the
   // matrix-core kernel, per-pair products of the offset-major mode
   std::vector<DevBuf> parts, pairs;
   DevBuf nparts;                     // K-split partial sums (leaf-column near field)
-  size_t bytes = 0;                  // W, H and zero
+  size_t bytes = 0;                  // W, H, UP and zero
   size_t extra_bytes() const {
     size_t b = nparts.bytes;
     for (const DevBuf& x : parts) b += x.bytes;

@@ -428,18 +428,18 @@ __global__ __launch_bounds__(kThreads) void k_near_tensor(
 
 // ---------------------------------------------------------------------------
 // Up contraction: W_sigma = u~_sigma x_1 V_1^T ... x_d V_d^T, one block per
-// (box, right-hand side), slice by slice along the last dimension.
-// V is [m][p] (uniform: vstride = 0) or [d][B][m][p] (per box).
+// (box, right-hand side, chunk), slice by slice along the last dimension.
+// V is [m][p] (uniform: vstride = 0) or [d][B][m][p] (per box).  Large boxes
+// of coarse levels are split over gridDim.z chunks of rpc slices; each chunk
+// writes a partial W (part != nullptr), summed in chunk order by k_up_reduce.
 template <typename T, typename TW>
 __global__ __launch_bounds__(kThreads) void k_up(const T* __restrict__ u, TW* __restrict__ W,
                                                  const T* __restrict__ V, int uniform, int d, int n, int m,
-                                                 int B, int p, int nrhs) {
+                                                 int B, int p, int nrhs, int rpc, T* __restrict__ part, int rows) {
   extern __shared__ unsigned char smem_raw[];
-  T* sl = reinterpret_cast<T*>(smem_raw);   // slice, m*m (d=3) or m (d=2)
-  T* t1 = sl + (d == 3 ? m * m : m);         // p*m
-  T* t12 = t1 + p * m;                       // p*p
   const int tid = threadIdx.x;
   const int box = blockIdx.x, r = blockIdx.y;
+  const int lo = blockIdx.z * rpc, hi = min(m, lo + rpc);
   const int P = (d == 3) ? p * p * p : p * p;
   const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
   int bb[3] = {box % B, (box / B) % B, d == 3 ? box / (B * B) : 0};
@@ -455,18 +455,25 @@ __global__ __launch_bounds__(kThreads) void k_up(const T* __restrict__ u, TW* __
   for (int q = 0; q < WPT; ++q) acc[q] = T(0);
   const T* ur = u + (int64_t)r * N;
   if (d == 3) {
-    for (int j2 = 0; j2 < m; ++j2) {
-      __syncthreads();
-      for (int idx = tid; idx < m * m; idx += kThreads) {
-        int j0 = idx % m, j1 = idx / m;
-        sl[idx] = ur[lin3(bb[0] * m + j0, bb[1] * m + j1, bb[2] * m + j2, n)];
-      }
-      __syncthreads();
-      for (int idx = tid; idx < p * m; idx += kThreads) {
-        int s0 = idx % p, j1 = idx / p;
-        T v = T(0);
-        for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * sl[j1 * m + j0];
-        t1[idx] = v;  // [j1][s0]
+    // a slice is staged in chunks of `rows` rows (all of it when it fits)
+    T* sl = reinterpret_cast<T*>(smem_raw);   // rows*m
+    T* t1 = sl + rows * m;                     // p*m
+    T* t12 = t1 + p * m;                       // p*p
+    for (int j2 = lo; j2 < hi; ++j2) {
+      for (int ja = 0; ja < m; ja += rows) {
+        const int nr = min(rows, m - ja);
+        __syncthreads();
+        for (int idx = tid; idx < m * nr; idx += kThreads) {
+          int j0 = idx % m, jr = idx / m;
+          sl[idx] = ur[lin3(bb[0] * m + j0, bb[1] * m + ja + jr, bb[2] * m + j2, n)];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < p * nr; idx += kThreads) {
+          int s0 = idx % p, jr = idx / p;
+          T v = T(0);
+          for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * sl[jr * m + j0];
+          t1[(ja + jr) * p + s0] = v;  // [j1][s0]
+        }
       }
       __syncthreads();
       for (int idx = tid; idx < p * p; idx += kThreads) {
@@ -483,14 +490,27 @@ __global__ __launch_bounds__(kThreads) void k_up(const T* __restrict__ u, TW* __
       }
     }
   } else {
-    for (int j1 = 0; j1 < m; ++j1) {
+    // each row's p dot products of length m are split over kThreads / p
+    // thread groups and combined through LDS in group order
+    T* sl = reinterpret_cast<T*>(smem_raw);   // row, m
+    T* red = sl + m;                           // kThreads partial sums
+    T* t1 = red + kThreads;                    // p
+    const int G = kThreads / p;
+    const int s0g = tid % p, g = tid / p;
+    for (int j1 = lo; j1 < hi; ++j1) {
       __syncthreads();
       for (int j0 = tid; j0 < m; j0 += kThreads) sl[j0] = ur[(int64_t)(bb[0] * m + j0) + (int64_t)n * (bb[1] * m + j1)];
       __syncthreads();
-      for (int s0 = tid; s0 < p; s0 += kThreads) {
+      if (g < G) {
         T v = T(0);
-        for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * sl[j0];
-        t1[s0] = v;
+        for (int j0 = g; j0 < m; j0 += G) v += V0[j0 * p + s0g] * sl[j0];
+        red[g * p + s0g] = v;
+      }
+      __syncthreads();
+      if (tid < p) {
+        T v = T(0);
+        for (int k = 0; k < G; ++k) v += red[k * p + tid];
+        t1[tid] = v;
       }
       __syncthreads();
 #pragma unroll
@@ -500,6 +520,15 @@ __global__ __launch_bounds__(kThreads) void k_up(const T* __restrict__ u, TW* __
       }
     }
   }
+  if (part) {
+    T* Po = part + (((int64_t)blockIdx.z * gridDim.x + box) * nrhs + r) * P;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      int t = tid + q * kThreads;
+      if (t < P) Po[t] = acc[q];
+    }
+    return;
+  }
   TW* Wo = W + ((int64_t)box * nrhs + r) * P;
 #pragma unroll
   for (int q = 0; q < WPT; ++q) {
@@ -508,18 +537,31 @@ __global__ __launch_bounds__(kThreads) void k_up(const T* __restrict__ u, TW* __
   }
 }
 
-// Down expansion: f_tau += H_tau x_1 U_1 ... x_d U_d, one block per (box, rhs).
+// W = sum over the chunks of the partial up contractions, in chunk order.
+template <typename T, typename TW>
+__global__ void k_up_reduce(const T* __restrict__ part, TW* __restrict__ W, int64_t count, int chunks) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    T v = part[i];
+    for (int c = 1; c < chunks; ++c) v += part[c * count + i];
+    W[i] = store_cast<TW>(v);
+  }
+}
+
+// Down expansion: f_tau += H_tau x_1 U_1 ... x_d U_d, one block per (box,
+// rhs, chunk of rpc slices along the last dimension; chunks write disjoint
+// parts of f).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ H, T* __restrict__ f,
                                                    const T* __restrict__ U, int uniform, int d, int n, int m,
-                                                   int B, int p, int nrhs) {
+                                                   int B, int p, int nrhs, int rpc) {
   extern __shared__ unsigned char smem_raw[];
   const int P = (d == 3) ? p * p * p : p * p;
   T* hs = reinterpret_cast<T*>(smem_raw);  // P
-  T* z = hs + P;                           // p*p   [t1][t0]
-  T* y = z + p * p;                        // m*p   [i1][t0]
+  T* z = hs + P;                           // p*p (3D: [t1][t0]) or p (2D)
+  T* y = z + p * p;                        // m*p   [i1][t0] (3D)
   const int tid = threadIdx.x;
   const int box = blockIdx.x, r = blockIdx.y;
+  const int lo = blockIdx.z * rpc, hi = min(m, lo + rpc);
   const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
   int bb[3] = {box % B, (box / B) % B, d == 3 ? box / (B * B) : 0};
   auto Uk = [&](int k) -> const T* {
@@ -532,7 +574,7 @@ __global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ H, T* _
   for (int t = tid; t < P; t += kThreads) hs[t] = Hb[t];
   T* fr = f + (int64_t)r * N;
   if (d == 3) {
-    for (int i2 = 0; i2 < m; ++i2) {
+    for (int i2 = lo; i2 < hi; ++i2) {
       __syncthreads();
       for (int idx = tid; idx < p * p; idx += kThreads) {
         T v = T(0);
@@ -555,7 +597,7 @@ __global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ H, T* _
       }
     }
   } else {
-    for (int i1 = 0; i1 < m; ++i1) {
+    for (int i1 = lo; i1 < hi; ++i1) {
       __syncthreads();
       for (int t0 = tid; t0 < p; t0 += kThreads) {
         T v = T(0);
@@ -722,6 +764,22 @@ static int pick_rc(int nrhs, size_t fixed_bytes, size_t per_rc_bytes) {
 // Work buffers
 
 
+// Chunks of the up contraction and down expansion of a level: levels with
+// few, large boxes spread each box over several blocks (at least 4 slices
+// each), aiming at about 512 blocks.
+static int level_chunks(const LevelData& lv, int nrhs) {
+  const int64_t base = lv.nbox * (int64_t)nrhs;
+  if (lv.m < 16 || base >= 256) return 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(lv.m / 4, (512 + base - 1) / base));
+}
+
+// Elements of a level's partial up-contraction buffer, enough for every
+// right-hand-side count up to nrhs (chunks x boxes x rhs <= 512 + boxes x nrhs).
+static size_t up_part_elems(const LevelData& lv, int nrhs, int P) {
+  if (level_chunks(lv, 1) <= 1) return 0;
+  return (size_t)(512 + lv.nbox * (int64_t)nrhs) * P;
+}
+
 static size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
   (void)prec;
   size_t tot = 0;
@@ -729,6 +787,7 @@ static size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
     if (lv.npairs == 0) continue;
     size_t cnt = (size_t)lv.nbox * nrhs * A.P;
     tot += 2 * ((cnt * sizeof(double) + 255) & ~size_t(255));
+    tot += up_part_elems(lv, nrhs, A.P) * sizeof(double);
   }
   return tot;
 }
@@ -742,15 +801,18 @@ void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
   if (ws.frozen) fail(HTLR_ERR_INVALID, "nrhs exceeds the reserved work buffers");
   ws.W.clear();
   ws.H.clear();
+  ws.UP.clear();
   ws.W.resize(A.L + 1);
   ws.H.resize(A.L + 1);
+  ws.UP.resize(A.L + 1);
   ws.bytes = 0;
   for (const LevelData& lv : A.levels) {
     if (lv.npairs == 0) continue;
     size_t cnt = (size_t)lv.nbox * nrhs * A.P;
     ws.W[lv.level].alloc(cnt * sizeof(double));
     ws.H[lv.level].alloc(cnt * sizeof(double));
-    ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes;
+    ws.UP[lv.level].alloc(up_part_elems(lv, nrhs, A.P) * sizeof(double));
+    ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes + ws.UP[lv.level].bytes;
   }
   ws.zero.alloc((size_t)A.P * sizeof(double));
   HTLR_HIP(hipMemset(ws.zero.ptr, 0, ws.zero.bytes));
@@ -848,16 +910,26 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
     const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
     T* H = A.ws.H[l].as<T>();
-    size_t sh_up = ((size_t)(d == 3 ? lm * lm : lm) + (size_t)p * lm + (size_t)p * p) * sizeof(T);
+    // 3D: rows of a slice staged at a time, as many as the LDS budget allows
+    const int up_rows = d == 3 ? (int)std::max<int64_t>(1, std::min<int64_t>(lm, ((int64_t)(kLdsBudget / sizeof(T)) -
+                                                         (int64_t)p * lm - (int64_t)p * p) / lm)) : 0;
+    const size_t sh_up = (d == 3 ? (size_t)up_rows * lm + (size_t)p * lm + (size_t)p * p
+                                 : (size_t)lm + (size_t)kThreads + (size_t)p) * sizeof(T);
     if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
+    const int nch = level_chunks(lv, nrhs), rpc = (lm + nch - 1) / nch;
+    T* upart = nch > 1 ? A.ws.UP[l].as<T>() : nullptr;
+    const int64_t wcount = lv.nbox * (int64_t)nrhs * P;
     if (prec == HTLR_BF16_CORE) {
       if constexpr (!std::is_same<T, double>::value) {
         if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
         if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
         uint16_t* W16 = A.ws.W[l].as<uint16_t>();
         { ProfScope ps(A, "up", l, ls);
-        hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, ls, u, W16, V,
-                           1, d, n, lm, lB, p, nrhs);
+        hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W16, V,
+                           1, d, n, lm, lB, p, nrhs, rpc, (float*)upart, up_rows);
+        if (nch > 1)
+          hipLaunchKernelGGL((k_up_reduce<float, uint16_t>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)),
+                             dim3(256), 0, ls, (const float*)upart, W16, wcount, nch);
         HTLR_HIP(hipGetLastError()); }
         ProfScope ps(A, "core", l, ls);
         if (core_mfma_ok(A, prec)) {
@@ -876,8 +948,11 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     } else {
     T* W = A.ws.W[l].as<T>();
     { ProfScope ps(A, "up", l, ls);
-    hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_up, ls, u, W, V, A.uniform ? 1 : 0, d,
-                       n, lm, lB, p, nrhs);
+    hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W, V, A.uniform ? 1 : 0,
+                       d, n, lm, lB, p, nrhs, rpc, upart, up_rows);
+    if (nch > 1)
+      hipLaunchKernelGGL((k_up_reduce<T, T>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)), dim3(256), 0,
+                         ls, (const T*)upart, W, wcount, nch);
     HTLR_HIP(hipGetLastError()); }
     ProfScope ps(A, "core", l, ls);
     if (A.uniform && core_mfma_ok(A, prec)) {
@@ -1008,11 +1083,12 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
     T* H = A.ws.H[l].as<T>();
     if (fork) HTLR_HIP(hipStreamWaitEvent(st, A.ev_level[li], 0));
-    size_t sh_dn = ((size_t)P + (size_t)p * p + (size_t)lm * p) * sizeof(T);
+    const size_t sh_dn = ((size_t)P + (d == 3 ? (size_t)p * p + (size_t)lm * p : (size_t)p)) * sizeof(T);
     if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
+    const int nch = level_chunks(lv, nrhs), rpc = (lm + nch - 1) / nch;
     ProfScope ps(A, "down", l, st);
-    hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_dn, st, H, f, U, A.uniform ? 1 : 0, d, n,
-                       lm, lB, p, nrhs);
+    hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_dn, st, H, f, U, A.uniform ? 1 : 0, d,
+                       n, lm, lB, p, nrhs, rpc);
     HTLR_HIP(hipGetLastError());
   }
 }
@@ -1153,7 +1229,7 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
-      for (int tile : {1, 2, 3}) {
+      for (int tile : {1, 2, 3, 4}) {
         TuneParams t = best;
         t.tile = tile;
         const double ms = time_with(t);
