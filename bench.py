@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
     ap.add_argument("--no-tables", action="store_true", help="skip construction at the paper's table shapes")
+    ap.add_argument("--serial", action="store_true",
+                    help="time the profiled, serially issued product (for kernel-trace runs: every kernel's "
+                         "duration is its own, as in the roofline pass)")
     ap.add_argument("--write-traffic", action="store_true",
                     help="with --summarize-profile: store per-launch HBM bytes for the roofline's traffic field")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
@@ -101,7 +104,7 @@ def traffic_for(workload, prec, step, launches):
     return t["kernels"][key]["hbm_bytes_per_launch"]
 
 
-def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False):
+def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False, serial=False):
     a = w.a()
     t0 = time.time()
     M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=a)
@@ -122,7 +125,9 @@ def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False):
     for _ in range(warmup):
         M.matvec(ut, f, prec=prec)
     torch.cuda.synchronize()
-    if profile:
+    # timed region: the product as it runs in use (levels concurrent), or
+    # with serial=True the profiled, serially issued product
+    if serial:
         M.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -130,9 +135,20 @@ def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False):
         M.matvec(ut, f, prec=prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = M.profile_read() if profile else {}
-    M.profile(False)
     ms = (t1 - t0) / steps * 1e3
+    prof = {}
+    if profile:
+        # per-kernel durations: a second timed pass of the same steps with the
+        # profiler on, which issues every launch in order so that each
+        # duration is the kernel's own
+        if not serial:
+            M.profile(True)
+            torch.cuda.synchronize()
+            for _ in range(steps):
+                M.matvec(ut, f, prec=prec)
+            torch.cuda.synchronize()
+        prof = M.profile_read()
+    M.profile(False)
     return M, info, f, u, nrhs, ms, prof, build_s
 
 
@@ -153,7 +169,8 @@ def roofline(info, w, prec, nrhs, prof, workload):
     return {"kernel": dom, "bound": d["bound"], "achieved": round(d["achieved_tflops"], 3), "peak": d["peak_tflops"],
             "unit": "TFLOP/s", "frac": round(d["frac"], 4),
             "traffic": traffic_for(workload, prec, dom, prof[dom][0]),
-            "work_per_launch_flop": work[dom], "avg_launch_ms": round(d["ms"], 4)}, per
+            "work_per_launch_flop": work[dom], "avg_launch_ms": round(d["ms"], 4),
+            "timing": "hipEvents around each launch in a profiled pass of the same steps, launches issued in order"}, per
 
 
 _ORACLE = {}
@@ -486,7 +503,7 @@ def main():
     print(f"[bench] {w.name} {prec}: build + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
     M, info, f, u, nrhs, ms, prof, build_s = run_workload(H, torch, w, prec, args.steps, args.warmup,
-                                                          tune=not args.no_tune)
+                                                          tune=not args.no_tune, serial=args.serial)
     value = w.N * nrhs / (ms * 1e-3) / 1e9
     roof, per = roofline(info, w, prec, nrhs, prof, w.name)
     f_host = f.detach().cpu().numpy()

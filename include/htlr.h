@@ -191,6 +191,9 @@ htlr_status htlr_info(htlr_matrix A, htlr_info_t* info);
  * launch stream.  htlr_profile_read synchronises those events and returns,
  * per step name ("near", "up_l4", "core_l4", "down_l4", ...), the number of
  * launches and their summed duration in milliseconds since the last reset.
+ * While enabled, a product issues all its launches on the caller's stream
+ * in order (the levels do not run concurrently), so that each duration is
+ * that launch's alone; results are bitwise the same either way.
  * Enabling or disabling clears the record. */
 typedef struct {
   char name[32];

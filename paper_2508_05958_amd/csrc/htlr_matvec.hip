@@ -896,7 +896,8 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   std::vector<LevelData*> act;
   for (LevelData& lv : A.levels)
     if (lv.npairs > 0) act.push_back(&lv);
-  const bool fork = A.cur.serial == 0 && !act.empty();
+  // (serial while profiling: each recorded duration is then one launch's alone)
+  const bool fork = A.cur.serial == 0 && !A.prof.on && !act.empty();
   const std::vector<hipStream_t>* side = fork ? &side_streams(A) : nullptr;
   if (fork) {
     HTLR_HIP(hipEventRecord(A.ev_fork, st));
