@@ -121,6 +121,8 @@ def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False, ser
     if u.ndim == 2:
         ut = torch.tensor(u.T.copy(), dtype=dt, device="cuda").t()   # column-major N x nrhs
     nrhs = 1 if u.ndim == 1 else u.shape[1]
+    if serial:
+        M.profile(True)          # every product of this run issued in order, warm-up included
     f = M.matvec(ut, prec=prec)
     for _ in range(warmup):
         M.matvec(ut, f, prec=prec)
@@ -128,7 +130,7 @@ def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False, ser
     # timed region: the product as it runs in use (levels concurrent), or
     # with serial=True the profiled, serially issued product
     if serial:
-        M.profile(True)
+        M.profile(True)          # clears the record
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
