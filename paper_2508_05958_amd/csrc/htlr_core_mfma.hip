@@ -37,7 +37,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // one 16-byte staged chunk
 
-constexpr int kBNmax = 128;  // widest output tile (columns)
+constexpr int kBNmax = 128;  // right-hand sides a matrix-core column tile can hold
 
 template <typename TE> struct AccT { using type = float; };
 template <> struct AccT<double> { using type = double; };
@@ -438,22 +438,25 @@ static int narrow_variant(const htlr_matrix_impl& A, int prec) {
 }
 
 static int pick_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
-  if (A.cur.tile >= 1 && A.cur.tile <= 4) return A.cur.tile;
+  if (A.cur.tile >= 1 && A.cur.tile <= 5) return A.cur.tile;
   const int64_t class_boxes = lv.nbox >> A.d;
   if (class_boxes * nrhs <= 64) return narrow_variant(A, prec);
-  if (prec == HTLR_BF16_CORE && A.P >= 256) return 3;
+  if (prec == HTLR_BF16_CORE && A.P >= 256) return class_boxes * nrhs >= 256 ? 5 : 3;
   return 1;
 }
 
 // Tile shape of a variant: 1 = 128x128, 2 = 128x64, 3 = 256x128, 4 = 224x64
-// (FP64; the other precisions run variant 4 as 128x64).
+// (FP64; the other precisions run variant 4 as 128x64), 5 = 256x256
+// (bfloat16, half the core reads per column; the others run it as 256x128).
 static void variant_shape(int v, int prec, int* bmt, int* bnt) {
-  *bmt = v == 3 ? 256 : (v == 4 && prec == HTLR_FP64 ? 224 : 128);
-  *bnt = (v == 2 || v == 4) ? 64 : 128;
+  *bmt = (v == 3 || v == 5) ? 256 : (v == 4 && prec == HTLR_FP64 ? 224 : 128);
+  *bnt = (v == 2 || v == 4) ? 64 : (v == 5 && prec == HTLR_BF16_CORE ? 256 : 128);
 }
 
 template <typename TE> struct NarrowRows { static constexpr int value = 128; };
 template <> struct NarrowRows<double> { static constexpr int value = 224; };
+template <typename TE> struct WideCols { static constexpr int value = 128; };
+template <> struct WideCols<uint16_t> { static constexpr int value = 256; };
 
 // Sums the K-split partial results in a fixed order: H = sum_s part_s.
 template <typename TA>
@@ -624,7 +627,7 @@ static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int
 // Tile shape of the offset-major mode: 128x64 unless an offset's boxes
 // times right-hand sides fill well over 128 columns on average.
 static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
-  if (A.cur.tile >= 1 && A.cur.tile <= 4) return A.cur.tile;
+  if (A.cur.tile >= 1 && A.cur.tile <= 5) return A.cur.tile;
   const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
   return avg * nrhs <= 128 ? narrow_variant(A, prec) : 1;
 }
@@ -655,6 +658,8 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     case 2: launch_variant_out<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
     case 4: launch_variant_out<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs,  \
                                                              lv.B, st); break;                                       \
+    case 5: launch_variant_out<TE, 256, WideCols<TE>::value>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs,   \
+                                                            lv.B, st); break;                                        \
     case 3: launch_variant_out<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;  \
     default: launch_variant_out<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break; \
   }
@@ -706,6 +711,8 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     case 2: launch_variant<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
                                         A.P, nrhs, nb, lv.B, st); break;                                         \
     case 4: launch_variant<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
+                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+    case 5: launch_variant<TE, 256, WideCols<TE>::value>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
                                         A.P, nrhs, nb, lv.B, st); break;                                         \
     case 3: launch_variant<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems, \
                                          A.P, nrhs, nb, lv.B, st); break;                                        \
