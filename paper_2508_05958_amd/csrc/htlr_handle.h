@@ -206,7 +206,7 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs);
 // Choices for a product of this shape: exact match, else the nearest tuned
 // smaller width of the same precision, else the defaults.
 TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec);
-// Leaf-column near field (uniform 3D grids, 8^3-point leaves, radial kernels, nrhs <= 8).
+// Leaf-column near field (uniform 3D grids, 8^3-point leaves, radial kernels, nrhs <= 16).
 bool near_leaves_ok(const htlr_matrix_impl& A, int nrhs, int prec);
 NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool frozen);
 // Whether the product of this shape, with the choices in A.cur, takes the leaf-column near kernel.

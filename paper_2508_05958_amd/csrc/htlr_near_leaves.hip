@@ -329,7 +329,7 @@ NearGroups* groups_for(htlr_matrix_impl& A, int lpc, bool frozen) {
 
 bool near_leaves_ok(const htlr_matrix_impl& A, int nrhs, int prec) {
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
-  return A.uniform && A.d == 3 && A.plan.m[A.L] == 8 && A.kid != HTLR_K_POLY_TEST && nrhs >= 1 && nrhs <= 8 &&
+  return A.uniform && A.d == 3 && A.plan.m[A.L] == 8 && A.kid != HTLR_K_POLY_TEST && nrhs >= 1 && nrhs <= 16 &&
          nl_lds_bytes(A, esz, 1) <= 64 * 1024 && nl_lds_bytes(A, esz, 2) <= 64 * 1024;
 }
 
@@ -339,6 +339,7 @@ NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool 
   (void)prec;
   s.ct = A.cur.near_ct == 2 ? 2 : 1;
   s.lpc = 16 * s.ct / nrhs;
+  if (s.lpc < 1) return s;
   NearGroups* G = groups_for(A, s.lpc, frozen);
   if (!G) return s;
   s.ok = true;
@@ -358,7 +359,8 @@ NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool 
 
 bool use_near_leaves(htlr_matrix_impl& A, int nrhs, int prec, bool frozen) {
   if (!near_leaves_ok(A, nrhs, prec)) return false;
-  if (!(A.cur.near_kind == 2 || A.cur.near_kind < 0)) return false;
+  // automatic choice up to 8 right-hand sides; above, only when tuned
+  if (!(A.cur.near_kind == 2 || (A.cur.near_kind < 0 && nrhs <= 8))) return false;
   return near_leaves_shape(A, nrhs, prec, frozen).ok;
 }
 
