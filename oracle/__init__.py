@@ -23,6 +23,9 @@ Low-Rank Matrices: Construction and Matrix-Vector Multiplication"
                    factors and cores (eq. 3.4).
 * ``htlr``      -- O2: HTLR construction (Alg. 4.1) and matrix-vector product
                    (Alg. 4.2, eq. 4.3), block by block, no batching.
+* ``quasi``     -- O5: the quasi-uniform grid through a uniform one, T Ahat S
+                   (Sec. 3.3, eq. 3.9): 1D cell-overlap interpolation
+                   matrices and their Kronecker application.
 * ``gmres``     -- O3: restarted GMRES and a dense direct solve, used to check
                    the solver (the paper itself has no solver).
 
