@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--cpu-leaves", type=int, default=96)
     ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
+    ap.add_argument("--no-quasi", action="store_true", help="skip the quasi-uniform transfer block")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
     ap.add_argument("--no-tables", action="store_true", help="skip construction at the paper's table shapes")
@@ -315,6 +316,65 @@ def solve_block(H, torch, np, W):
     return out
 
 
+def quasi_block(H, torch, np, W, steps=10):
+    """Quasi-uniform grid through the uniform grid of m = 2n cells (the
+    transfer form T Ahat S): product rate in FP64 and FP32, and the transfer
+    kernels against HBM bandwidth.  Per launch the S transfer reads u (N
+    values) and writes S u (M values); the T transfer reads Ahat S u (M),
+    u and a (N each) and writes f (N)."""
+    w = W.WORKLOADS["wq2d_log_n512_m1024"]
+    nd = w.nodes()
+    M_ = w.m ** w.d
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A = H.htlr_build_quasi(np.concatenate(nd), w.kernel, w.d, w.n, w.m, w.p, w.leaf, a=w.a(), eta2=w.eta2,
+                           precisions=["fp64", "fp32"])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = A.info()
+    out = {"workload": w.name, "d": w.d, "n": w.n, "N": w.N, "m": w.m, "M": M_, "rho": w.m / w.n,
+           "kernel": KERNEL_LABEL.get(w.kernel, w.kernel), "p": w.p, "leaf": w.leaf,
+           "admissibility": f"strong, eta^2={w.eta2:g}", "build_s": round(build_s, 3),
+           "device_bytes": info["device_bytes"], "u": "smooth u(x) of the paper's quasi-uniform experiment"}
+    u64 = torch.tensor(w.rhs(), dtype=torch.float64, device="cuda")
+    for prec in ("fp64", "fp32"):
+        u = u64 if prec == "fp64" else u64.float()
+        f = A.matvec(u, prec=prec)
+        for _ in range(2):
+            A.matvec(u, f, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            A.matvec(u, f, prec=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        A.profile(True)
+        for _ in range(steps):
+            A.matvec(u, f, prec=prec)
+        prof = A.profile_read()
+        A.profile(False)
+        esz = 8 if prec == "fp64" else 4
+        kern = {}
+        for name, nbytes in (("quasi_s", esz * (w.N + M_)), ("quasi_t", esz * (M_ + 3 * w.N))):
+            launches, total = prof[name]
+            avg = total / launches
+            gbs = nbytes / (avg * 1e-3) / 1e9
+            kern[name] = {"avg_launch_ms": round(avg, 4), "bound": "hbm", "algorithmic_bytes": nbytes,
+                          "achieved_GBs": round(gbs, 1), "peak_GBs": HBM_GBS,
+                          "frac": round(gbs / HBM_GBS, 4)}
+        inner_ms = sum(t for k, (c, t) in prof.items() if not k.startswith("quasi")) / steps
+        out[prec] = {"ms_per_product": round(ms, 4), "Gpt_s": round(w.N / (ms * 1e-3) / 1e9, 5),
+                     "ahat_ms_profiled": round(inner_ms, 4), "transfers": kern,
+                     "transfer_share": round(sum(v["avg_launch_ms"] for v in kern.values())
+                                             / (inner_ms + sum(v["avg_launch_ms"] for v in kern.values())), 4)}
+        print(f"[bench]   quasi {prec}: {ms:.3f} ms/product, S {kern['quasi_s']['avg_launch_ms']:.4f} ms "
+              f"({kern['quasi_s']['frac']:.2f} of HBM), T {kern['quasi_t']['avg_launch_ms']:.4f} ms",
+              file=sys.stderr, flush=True)
+        del f
+    A.free()
+    return out
+
+
 def serve_block(H, np, W, count):
     """Serving: Poisson arrivals of mixed solve requests (d, n, kernel, p drawn
     per request, f ~ N(0,1), a = 1 + x_1/2, relative residual 1e-8)."""
@@ -561,6 +621,10 @@ def main():
     if not args.no_tables:
         print("[bench] construction at the paper's table shapes", file=sys.stderr, flush=True)
         out["paper_tables"] = paper_tables_block(H, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_quasi:
+        print("[bench] quasi-uniform grid through a uniform one (T Ahat S)", file=sys.stderr, flush=True)
+        out["wq2d_log_n512_m1024"] = quasi_block(H, torch, np, W)
         torch.cuda.empty_cache()
     if not args.no_solve:
         print("[bench] warped-grid solve (FP32-IR and FP64 GMRES)", file=sys.stderr, flush=True)

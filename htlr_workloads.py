@@ -31,6 +31,20 @@ def warped_nodes(n: int, amp: float = 0.08) -> np.ndarray:
     return t + amp * np.sin(2.0 * np.pi * t) / (2.0 * np.pi)
 
 
+def skewed_nodes(n: int, c: float = 0.03) -> np.ndarray:
+    """Quasi-uniform nodes t_k + c (cos(2 pi t_k) - 1), t_k cell centres; not
+    symmetric about 1/2 (increasing for |c| < 1/(2 pi))."""
+    t = uniform_nodes(n)
+    return t + c * (np.cos(2.0 * np.pi * t) - 1.0)
+
+
+def smooth_u(points: np.ndarray) -> np.ndarray:
+    """u(x) = 1 + 0.5 exp(-(x1-0.3)^2 - (x2-0.6)^2) + sin(5 x1 x2), the input
+    function of the paper's quasi-uniform experiment (Sec. 5.4)."""
+    x1, x2 = points[:, 0], points[:, 1]
+    return 1.0 + 0.5 * np.exp(-(x1 - 0.3) ** 2 - (x2 - 0.6) ** 2) + np.sin(5.0 * x1 * x2)
+
+
 def grid_points(nodes_per_dim) -> np.ndarray:
     """All tensor-grid points, shape (N, d), natural order (first index fastest)."""
     d = len(nodes_per_dim)
@@ -62,10 +76,11 @@ class Workload:
     a_spec: str
     seed: int
     nrhs: int = 1
-    dist: str = "normal"          # "uniform" -> U[-1,1], "normal" -> N(0,1)
+    dist: str = "normal"          # "uniform" -> U[-1,1], "normal" -> N(0,1), "smooth" -> smooth_u
     grid: str = "uniform"         # "uniform" or "warped"
     eta2: float = 1.0             # eta^2 of the strong admissibility test
     gl_order: int = 0             # 0 -> 16 in 2D, 8 in 3D
+    m: int = 0                    # > 0: transfer to the uniform grid of m cells per dimension
     sample_rows: int = 0
     extra: dict = field(default_factory=dict)
 
@@ -86,7 +101,9 @@ class Workload:
     def rhs(self) -> np.ndarray:
         """Right-hand side(s), shape (N,) for one RHS else (N, nrhs) column-major."""
         rng = np.random.default_rng(self.seed)
-        if self.dist == "uniform":
+        if self.dist == "smooth":
+            u = smooth_u(self.points())
+        elif self.dist == "uniform":
             u = rng.uniform(-1.0, 1.0, self.N)
         elif self.nrhs == 1:
             u = rng.standard_normal(self.N)
@@ -110,6 +127,10 @@ WORKLOADS = {
                                   sample_rows=2048),
     "w3d_exp_warp_n96": Workload("w3d_exp_warp_n96", 3, 96, "exp", 6, 8, "two_plus_x1", 3,
                                  grid="warped"),
+    # quasi-uniform 2D grid through the uniform grid of m = 2n cells (rho = 2),
+    # the SLP kernel with strong admissibility, p and leaf of the 2D tables
+    "wq2d_log_n512_m1024": Workload("wq2d_log_n512_m1024", 2, 512, "neg_log", 8, 16, "one", 5, dist="smooth",
+                                    grid="warped", eta2=2.0, m=1024),
 }
 
 

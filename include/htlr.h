@@ -119,6 +119,37 @@ typedef struct {
 htlr_status htlr_build(const double* points, htlr_kernel kernel, int d, int n, int p,
                        int leaf, const htlr_build_opts* opts, htlr_matrix* out);
 
+/* Builds the same operator on a quasi-uniform tensor grid by the transfer
+ * scheme of Sec. 3.3 (eq. 3.9): A ~ diag(a) + T Ahat S.
+ *
+ * Ahat is the HTLR matrix of the same kernel on the uniform cell-centred grid
+ * of m^d cells, with a = 0 (built as htlr_build(NULL, kernel, d, m, p, leaf);
+ * its diagonal integrals are those of the uniform cells).  S (m^d x n^d) and
+ * T (n^d x m^d) move a vector between the grids, reading it as piecewise
+ * constant on its cells:
+ *     S[t,i] = |Omega_t^uni cap Omega_i| / |Omega_t^uni|,
+ *     T[i,t] = |Omega_i cap Omega_t^uni| / |Omega_i|.
+ * On a tensor grid both are Kronecker products of 1D cell-overlap matrices;
+ * their rows sum to 1 and both conserve sum_i |Omega_i| u_i.  The term
+ * a_i u_i is applied on the quasi-uniform grid itself.
+ *
+ * points : host, d*n doubles as in htlr_build (cells are the 1D Voronoi
+ *          cells); NULL means the uniform grid of n cells.
+ * m      : uniform cells per dimension (m = rho n with oversampling rho);
+ *          m must halve exactly down to Ahat's leaf level, otherwise
+ *          HTLR_ERR_UNSUPPORTED.
+ * opts   : as in htlr_build; opts->a holds a(x_i) at the n^d points.
+ * out    : host; receives the handle.
+ *
+ * The handle is used like any other: htlr_matvec and htlr_solve (vectors of
+ * n^d rows), htlr_workspace_bytes, htlr_autotune (tunes Ahat's products),
+ * htlr_profile_* (adds the steps "quasi_s" and "quasi_t"), htlr_info
+ * (structure of Ahat with d, n of the quasi-uniform grid and uniform_m = m)
+ * and htlr_free.  Runs synchronously on the null stream of the current
+ * device; failures leave *out NULL. */
+htlr_status htlr_build_quasi(const double* points, htlr_kernel kernel, int d, int n, int m, int p,
+                             int leaf, const htlr_build_opts* opts, htlr_matrix* out);
+
 /* Device bytes htlr_build would hold for the same arguments (cores, factors,
  * geometry, near-field tables, block lists), without allocating; used for
  * admission by memory footprint.  Work buffers of products and solves are
@@ -182,6 +213,7 @@ typedef struct {
   int64_t near_pairs;                 /* inadmissible leaves                            */
   size_t device_bytes;                /* what htlr_footprint reports                    */
   double diag0;                       /* D_0 = K_00 |Omega_0| (uniform: every D_i)       */
+  int uniform_m;                      /* htlr_build_quasi handles: m; otherwise 0        */
 } htlr_info_t;
 
 htlr_status htlr_info(htlr_matrix A, htlr_info_t* info);

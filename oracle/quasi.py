@@ -52,11 +52,13 @@ def t_1d(e_quasi, e_uni) -> np.ndarray:
 
 def _kron_apply(mats, x: np.ndarray, n_in) -> np.ndarray:
     """Apply per-dimension matrices to a vector in natural order (first index
-    fastest): returns (mats[d-1] x ... x mats[0]) x."""
-    X = x.reshape(tuple(n_in), order="F")
+    fastest): returns (mats[d-1] x ... x mats[0]) x, column by column for an
+    (N, nrhs) array."""
+    cols = x.shape[1:]
+    X = x.reshape(tuple(n_in) + cols, order="F")
     for l, Mt in enumerate(mats):
         X = np.moveaxis(np.tensordot(Mt, X, axes=([1], [l])), 0, l)
-    return X.reshape(-1, order="F")
+    return X.reshape((-1,) + cols, order="F")
 
 
 def s_apply(gq: geometry.Grid, m: int, u: np.ndarray) -> np.ndarray:
@@ -72,7 +74,8 @@ def t_apply(gq: geometry.Grid, m: int, v: np.ndarray) -> np.ndarray:
 def matvec(gq: geometry.Grid, m: int, kernel: str, p: int, leaf: int, a: np.ndarray, u: np.ndarray,
            khat: str = "htlr", **htlr_kw) -> np.ndarray:
     """f = a o u + T Khat S u, Khat on the uniform m^d grid (a = 0): the HTLR
-    oracle O2 (khat="htlr") or the dense product O1 (khat="dense")."""
+    oracle O2 (khat="htlr") or the dense product O1 (khat="dense").  u has
+    shape (N,) or (N, nrhs)."""
     gu = geometry.uniform_grid(gq.d, m)
     uh = s_apply(gq, m, u)
     zero = np.zeros(gu.N)
@@ -80,4 +83,4 @@ def matvec(gq: geometry.Grid, m: int, kernel: str, p: int, leaf: int, a: np.ndar
         fh = dense.matvec(gu, kernel, p, zero, uh)
     else:
         fh = htlr.HTLR(gu, kernel, p, leaf, zero, **htlr_kw).matvec(uh)
-    return a * u + t_apply(gq, m, fh)
+    return a.reshape((-1,) + (1,) * (u.ndim - 1)) * u + t_apply(gq, m, fh)

@@ -53,7 +53,7 @@ class _Info(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("p", ctypes.c_int), ("leaf_side", ctypes.c_int),
                 ("levels", ctypes.c_int), ("uniform", ctypes.c_int), ("adm_pairs", ctypes.c_int64 * 16),
                 ("unique_cores", ctypes.c_int64 * 16), ("near_pairs", ctypes.c_int64),
-                ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double)]
+                ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double), ("uniform_m", ctypes.c_int)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -80,6 +80,8 @@ def lib() -> ctypes.CDLL:
         L.htlr_last_error.restype = ctypes.c_char_p
         L.htlr_build.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)]
+        L.htlr_build_quasi.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(_BuildOpts), ctypes.POINTER(_vp)]
         L.htlr_footprint.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.POINTER(_BuildOpts), ctypes.POINTER(ctypes.c_size_t)]
         L.htlr_workspace_bytes.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
@@ -98,7 +100,7 @@ def lib() -> ctypes.CDLL:
         L.htlr_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_TuneResult)]
         L.htlr_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.htlr_profile_read.argtypes = [_vp, ctypes.POINTER(_ProfEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-        for name in ("htlr_build", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec", "htlr_solve",
+        for name in ("htlr_build", "htlr_build_quasi", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec", "htlr_solve",
                      "htlr_info", "htlr_plan_counts", "htlr_plan_pairs", "htlr_profile_enable",
                      "htlr_profile_read", "htlr_autotune"):
             getattr(L, name).restype = ctypes.c_int
@@ -149,18 +151,24 @@ class SolveInfo:
 
 
 class HTLRMatrix:
-    """An HTLR matrix resident on the current GPU (wraps htlr_matrix)."""
+    """An HTLR matrix resident on the current GPU (wraps htlr_matrix).
+
+    With ``m`` given, the quasi-uniform transfer form of htlr_build_quasi:
+    diag(a) + T Ahat S, Ahat on the uniform grid of m cells per dimension."""
 
     def __init__(self, points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
-                 a=None, precisions=0):
-        self.d, self.n, self.p, self.leaf = d, n, p, leaf
+                 a=None, precisions=0, m=None):
+        self.d, self.n, self.p, self.leaf, self.m = d, n, p, leaf, m
         self.N = n ** d
         self.kernel = kernel
         keep_pts, pts = _points_arg(points, d, n)
         o, keep_a = _opts(eta2, admissibility, gl_order, a, precisions)
         h = _vp()
         kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-        _check(lib().htlr_build(pts, kid, d, n, p, leaf, ctypes.byref(o), ctypes.byref(h)))
+        if m is None:
+            _check(lib().htlr_build(pts, kid, d, n, p, leaf, ctypes.byref(o), ctypes.byref(h)))
+        else:
+            _check(lib().htlr_build_quasi(pts, kid, d, n, int(m), p, leaf, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         del keep_pts, keep_a
 
@@ -204,7 +212,7 @@ class HTLRMatrix:
         return {"d": i.d, "n": i.n, "p": i.p, "leaf_side": i.leaf_side, "levels": i.levels,
                 "uniform": bool(i.uniform), "adm_pairs": list(i.adm_pairs[: i.levels + 1]),
                 "unique_cores": list(i.unique_cores[: i.levels + 1]), "near_pairs": i.near_pairs,
-                "device_bytes": i.device_bytes, "diag0": i.diag0}
+                "device_bytes": i.device_bytes, "diag0": i.diag0, "uniform_m": i.uniform_m}
 
     def workspace_bytes(self, nrhs=1, prec="fp64") -> int:
         b = ctypes.c_size_t()
@@ -365,6 +373,10 @@ class Server:
 
 def htlr_build(points, kernel, d, n, p, leaf, **kw) -> HTLRMatrix:
     return HTLRMatrix(points, kernel, d, n, p, leaf, **kw)
+
+
+def htlr_build_quasi(points, kernel, d, n, m, p, leaf, **kw) -> HTLRMatrix:
+    return HTLRMatrix(points, kernel, d, n, p, leaf, m=m, **kw)
 
 
 def htlr_footprint(points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,

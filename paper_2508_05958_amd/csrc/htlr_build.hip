@@ -431,19 +431,22 @@ htlr_status htlr_info(htlr_matrix A, htlr_info_t* info) {
   if (!A || !info) { g_last_error = "null argument"; return HTLR_ERR_INVALID; }
   return guarded([&] {
     std::memset(info, 0, sizeof(*info));
+    // quasi-uniform handles: the structure is that of the uniform-grid matrix
+    const htlr_matrix_impl& S = A->quasi ? quasi_inner(*A) : *A;
     info->d = A->d;
     info->n = A->n;
     info->p = A->p;
-    info->leaf_side = A->plan.m[A->L];
-    info->levels = A->L;
+    info->leaf_side = S.plan.m[S.L];
+    info->levels = S.L;
     info->uniform = A->uniform ? 1 : 0;
-    for (int l = 0; l <= A->L && l < 16; ++l) {
-      info->adm_pairs[l] = A->plan.adm[l].nnz();
-      info->unique_cores[l] = A->levels[l].ncore;
+    for (int l = 0; l <= S.L && l < 16; ++l) {
+      info->adm_pairs[l] = S.plan.adm[l].nnz();
+      info->unique_cores[l] = S.levels[l].ncore;
     }
-    info->near_pairs = A->plan.near.nnz();
+    info->near_pairs = S.plan.near.nnz();
     info->device_bytes = A->device_bytes;
-    info->diag0 = A->D0;
+    info->diag0 = S.D0;
+    info->uniform_m = A->quasi ? S.n : 0;
   });
 }
 

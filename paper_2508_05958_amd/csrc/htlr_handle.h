@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -157,6 +158,9 @@ struct NearLeavesShape {
   size_t parts_bytes = 0;
 };
 
+// Transfer data of a handle from htlr_build_quasi (defined with its kernels).
+struct QuasiData;
+
 struct htlr_matrix_impl {
   int d = 0, n = 0, p = 0, leaf = 0, L = 0, P = 0, kid = 0;
   int64_t N = 0;
@@ -183,6 +187,7 @@ struct htlr_matrix_impl {
   TuneParams cur;                    // choices of the product being issued
   hipEvent_t ev_fork = nullptr;      // level concurrency: fork from and join into the caller's stream
   hipEvent_t ev_level[kMaxLevels] = {};
+  std::shared_ptr<QuasiData> quasi;  // set on quasi-uniform handles: T Ahat S (Sec. 3.3)
   htlr_matrix_impl() = default;
   htlr_matrix_impl(const htlr_matrix_impl&) = delete;
   htlr_matrix_impl& operator=(const htlr_matrix_impl&) = delete;
@@ -190,6 +195,26 @@ struct htlr_matrix_impl {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (hipEvent_t e : ev_level)
       if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// Brackets one launch with events when the handle's profiler is on.
+struct ProfScope {
+  Profiler& p;
+  hipStream_t st;
+  bool on;
+  Profiler::Rec rec;
+  ProfScope(htlr_matrix_impl& A, const char* name, int level, hipStream_t s) : p(A.prof), st(s), on(A.prof.on) {
+    if (!on) return;
+    rec.name = level >= 0 ? std::string(name) + "_l" + std::to_string(level) : std::string(name);
+    rec.a = p.get();
+    rec.b = p.get();
+    HTLR_HIP(hipEventRecord(rec.a, st));
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.b, st);
+    p.recs.push_back(rec);
   }
 };
 
@@ -215,6 +240,17 @@ template <typename T>
 void launch_near_leaves(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st);
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st);
+// Work buffers of a product of this shape (handles from htlr_build).
+size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec);
+// f = A u on a handle from htlr_build (work buffers on demand); the caller
+// holds A.ws_mu.  u, f: f64 for FP64, f32 otherwise.
+void product(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st);
+// Quasi-uniform handles: the uniform-grid matrix Ahat, the product
+// f = a o u + T Ahat S u (the caller holds A.ws_mu), and the transfer
+// buffers a product of this shape adds to Ahat's work buffers.
+htlr_matrix_impl& quasi_inner(htlr_matrix_impl& A);
+void quasi_matvec(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st);
+size_t quasi_buffer_bytes(const htlr_matrix_impl& A, int nrhs, int prec);
 
 }  // namespace htlr
 

@@ -780,7 +780,7 @@ static size_t up_part_elems(const LevelData& lv, int nrhs, int P) {
   return (size_t)(512 + lv.nbox * (int64_t)nrhs) * P;
 }
 
-static size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
+size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
   (void)prec;
   size_t tot = 0;
   for (const LevelData& lv : A.levels) {
@@ -822,26 +822,6 @@ void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
 
 // ---------------------------------------------------------------------------
 // Driver
-
-// Brackets one launch with events when the handle's profiler is on.
-struct ProfScope {
-  Profiler& p;
-  hipStream_t st;
-  bool on;
-  Profiler::Rec rec;
-  ProfScope(htlr_matrix_impl& A, const char* name, int level, hipStream_t s) : p(A.prof), st(s), on(A.prof.on) {
-    if (!on) return;
-    rec.name = level >= 0 ? std::string(name) + "_l" + std::to_string(level) : std::string(name);
-    rec.a = p.get();
-    rec.b = p.get();
-    HTLR_HIP(hipEventRecord(rec.a, st));
-  }
-  ~ProfScope() {
-    if (!on) return;
-    (void)hipEventRecord(rec.b, st);
-    p.recs.push_back(rec);
-  }
-};
 
 const std::vector<hipStream_t>& side_streams(htlr_matrix_impl& A) {
   constexpr int kSideStreams = 4;
@@ -1094,6 +1074,12 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   }
 }
 
+void product(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st) {
+  ensure_workspace(A, nrhs, prec);
+  if (prec == HTLR_FP64) run_matvec<double>(A, (const double*)u, (double*)f, nrhs, prec, st);
+  else run_matvec<float>(A, (const float*)u, (float*)f, nrhs, prec, st);
+}
+
 }  // namespace htlr
 
 using namespace htlr;
@@ -1102,7 +1088,12 @@ extern "C" {
 
 htlr_status htlr_workspace_bytes(htlr_matrix A, int nrhs, htlr_precision prec, size_t* bytes) {
   if (!A || !bytes || nrhs < 1) { g_last_error = "invalid argument"; return HTLR_ERR_INVALID; }
-  *bytes = workspace_bytes(*A, nrhs, prec);
+  try {
+    *bytes = A->quasi ? workspace_bytes(quasi_inner(*A), nrhs, prec) + quasi_buffer_bytes(*A, nrhs, prec)
+                      : workspace_bytes(*A, nrhs, prec);
+  } catch (const Error& e) {
+    return record(e);
+  }
   return HTLR_OK;
 }
 
@@ -1125,10 +1116,9 @@ htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_pr
     HTLR_HIP(hipGetDevice(&dev));
     if (dev != A->device) fail(HTLR_ERR_INVALID, "current device differs from the build device");
     std::lock_guard<std::mutex> lk(A->ws_mu);
-    ensure_workspace(*A, nrhs, prec);
     hipStream_t st = (hipStream_t)stream;
-    if (prec == HTLR_FP64) run_matvec<double>(*A, (const double*)u, (double*)f, nrhs, prec, st);
-    else run_matvec<float>(*A, (const float*)u, (float*)f, nrhs, prec, st);
+    if (A->quasi) quasi_matvec(*A, u, f, nrhs, prec, st);
+    else product(*A, u, f, nrhs, prec, st);
     return HTLR_OK;
   } catch (const Error& e) {
     return record(e);
@@ -1142,6 +1132,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
   try {
     g_last_error.clear();
     if (!A) fail(HTLR_ERR_INVALID, "null handle");
+    // quasi-uniform handles: the transfers have no variants; tune Ahat
+    if (A->quasi) return htlr_autotune(static_cast<htlr_matrix_s*>(&quasi_inner(*A)), nrhs, prec, out);
     if (nrhs < 1 || nrhs > 64) fail(HTLR_ERR_INVALID, "nrhs out of range (1..64)");
     if (prec != HTLR_FP64 && prec != HTLR_FP32 && prec != HTLR_BF16_CORE) fail(HTLR_ERR_INVALID, "unknown precision");
     if (!(A->precisions & (1 << prec))) fail(HTLR_ERR_UNSUPPORTED, "matrix built without this precision");
@@ -1319,6 +1311,12 @@ htlr_status htlr_profile_enable(htlr_matrix A, int enable) {
   std::lock_guard<std::mutex> lk(A->ws_mu);
   A->prof.clear();
   A->prof.on = enable != 0;
+  if (A->quasi) {
+    htlr_matrix_impl& I = quasi_inner(*A);
+    std::lock_guard<std::mutex> li(I.ws_mu);
+    I.prof.clear();
+    I.prof.on = enable != 0;
+  }
   return HTLR_OK;
 }
 
@@ -1329,7 +1327,12 @@ htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, i
     std::vector<std::string> names;
     std::vector<double> tot;
     std::vector<int> cnt;
-    for (auto& r : A->prof.recs) {
+    std::vector<const Profiler::Rec*> recs;
+    for (auto& r : A->prof.recs) recs.push_back(&r);
+    if (A->quasi)
+      for (auto& r : quasi_inner(*A).prof.recs) recs.push_back(&r);
+    for (const Profiler::Rec* rp : recs) {
+      const Profiler::Rec& r = *rp;
       HTLR_HIP(hipEventSynchronize(r.b));
       float ms = 0.f;
       HTLR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
