@@ -7,6 +7,9 @@ Construction follows Alg. 4.1 leaf by leaf of the block cluster tree:
   Omega_tau and Omega_sigma, factors U_l, V_l and core G by interpolation
   (eq. 3.4); optionally a thin QR of every factor, U_l = W_l R_l,
   V_l = Q_l T_l, and G <- G x_1 R_1 ... x_d R_d x_{d+1} T_1 ... x_{2d} T_d;
+  or the same with QR with column pivoting truncated at a relative pivot
+  tolerance, which lowers the Tucker rank where a factor is rank deficient
+  (Sec. 2.1: more points per dimension than the box has, p > m);
 * inadmissible leaf: the dense block a_i delta_ij + K_ij |Omega_j| (eq. 4.1),
   with K_ii |Omega_i| = D_i.
 
@@ -32,6 +35,7 @@ decays with p; symmetry; QR and raw forms agree; worked-example counts).
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 from . import geometry, interp
 from .tree import Admissibility, ClusterTree, block_leaves, node_indices
@@ -45,13 +49,14 @@ def mode_product(T: np.ndarray, M: np.ndarray, mode: int) -> np.ndarray:
 class HTLR:
     def __init__(self, grid, kernel: str, p: int, leaf: int, a: np.ndarray,
                  adm_kind: str = "strong", eta2=1, gl_order: int = 0,
-                 orthonormalize: bool = False):
+                 orthonormalize=False, rank_tol: float = 1e-13):
         self.grid = grid
         self.kernel = kernel
         self.p = p
         self.a = np.asarray(a, dtype=np.float64)
         self.gl_order = gl_order
-        self.orthonormalize = orthonormalize
+        self.orthonormalize = orthonormalize    # False, True (QR) or "qrcp"
+        self.rank_tol = rank_tol
         self.tree = ClusterTree(grid, leaf)
         self.adm = Admissibility(self.tree, adm_kind, eta2)
 
@@ -71,8 +76,8 @@ class HTLR:
         if self.orthonormalize:
             Gt = G.reshape([p] * (2 * g.d), order="F")
             for l in range(g.d):
-                Wq, R = np.linalg.qr(U[l], mode="reduced")
-                Qq, T = np.linalg.qr(V[l], mode="reduced")
+                Wq, R = self._orth(U[l])
+                Qq, T = self._orth(V[l])
                 U[l], V[l] = Wq, Qq
                 Gt = mode_product(Gt, R, l)
                 Gt = mode_product(Gt, T, g.d + l)
@@ -80,6 +85,20 @@ class HTLR:
             rs = [V[l].shape[1] for l in range(g.d)]
             G = Gt.reshape(int(np.prod(rt)), int(np.prod(rs)), order="F")
         return U, V, G
+
+    def _orth(self, F):
+        """F = Q R with orthonormal Q (Alg. 4.1's QR step).  With
+        orthonormalize="qrcp", QR with column pivoting (Sec. 2.1) F P = Q R,
+        truncated to the pivots with |R_kk| > rank_tol |R_00|; R's columns are
+        put back in F's order, so that F ~ Q R."""
+        if self.orthonormalize != "qrcp":
+            return np.linalg.qr(F, mode="reduced")
+        Q, R, piv = scipy.linalg.qr(F, mode="economic", pivoting=True)
+        diag = np.abs(np.diag(R))
+        r = max(1, int(np.count_nonzero(diag > self.rank_tol * diag[0])))
+        Rf = np.empty((r, F.shape[1]))
+        Rf[:, piv] = R[:r]
+        return Q[:, :r], Rf
 
     def dense_block(self, tau, sigma, rows=None):
         g = self.grid

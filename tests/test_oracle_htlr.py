@@ -84,6 +84,43 @@ def test_qr_form_equals_raw_form():
         assert _rel(f1, f0) < 1e-13
 
 
+def _first_ranks(O):
+    """Tucker rank of the factors of the first admissible leaf of every box side."""
+    from oracle.tree import block_leaves
+    seen = {}
+    for k, tau, sigma in block_leaves(O.tree, O.adm):
+        side = tau.hi[0] - tau.lo[0]
+        if k == "A" and side not in seen:
+            seen[side] = O.tlr_block(tau, sigma)[0][0].shape[1]
+    return seen
+
+
+def test_qrcp_truncation_is_exact_when_factors_are_rank_deficient():
+    """With more Chebyshev points than box points (p > m) a Lagrange factor
+    has rank m: QRCP keeps exactly m columns, the Tucker rank drops below p,
+    and the operator is unchanged (uniform and warped grids)."""
+    for g, leaf, p in ((geometry.uniform_grid(2, 16), 2, 8),
+                       (geometry.tensor_grid([W.warped_nodes(24)] * 2), 3, 6)):
+        a = np.ones(g.N)
+        u = np.random.default_rng(8).standard_normal(g.N)
+        f0 = htlr.HTLR(g, "inv_r", p, leaf, a).matvec(u)
+        O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp", rank_tol=1e-13)
+        assert all(r == min(side, p) for side, r in _first_ranks(O).items())
+        assert _rel(O.matvec(u), f0) < 1e-13
+
+
+def test_qrcp_loose_tolerance_truncates_full_rank_factors():
+    """A loose pivot tolerance cuts full-rank factors too: rank 4 of 6 on
+    8-point boxes, at the price of an approximation error."""
+    g = geometry.uniform_grid(2, 32)
+    a = np.ones(g.N)
+    u = np.random.default_rng(8).standard_normal(g.N)
+    f0 = htlr.HTLR(g, "inv_r", 6, 4, a).matvec(u)
+    O = htlr.HTLR(g, "inv_r", 6, 4, a, orthonormalize="qrcp", rank_tol=0.3)
+    assert _first_ranks(O) == {4: 4, 8: 4}
+    assert 1e-5 < _rel(O.matvec(u), f0) < 5e-2
+
+
 def test_assembled_forms_agree_with_products():
     g = geometry.uniform_grid(2, 16)
     a = 1.0 + 0.5 * g.points()[:, 0]
