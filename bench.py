@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
     ap.add_argument("--no-quasi", action="store_true", help="skip the quasi-uniform transfer block")
+    ap.add_argument("--no-orth", action="store_true", help="skip the orthonormal / QRCP forms block")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
     ap.add_argument("--no-tables", action="store_true", help="skip construction at the paper's table shapes")
@@ -375,6 +376,45 @@ def quasi_block(H, torch, np, W, steps=10):
     return out
 
 
+def orth_block(H, torch, np, W, steps=10):
+    """Alg. 4.1's QR step and its QRCP truncation on the 64^3 FP64 workload:
+    rank, build time, product time and the product's deviation from the
+    interpolation form, per stored form."""
+    w = W.WORKLOADS["w3d_invr_n64"]
+    a = w.a()
+    u = torch.tensor(w.rhs(), dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "forms": {}}
+    ref = None
+    for label, kw in (("interpolation", {}), ("qr", {"orthonormalize": "qr"}),
+                      ("qrcp_1e-13", {"orthonormalize": "qrcp"}),
+                      ("qrcp_0.3", {"orthonormalize": "qrcp", "rank_tol": 0.3})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=a, precisions=["fp64"], **kw)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        f = M.matvec(u, prec="fp64")
+        for _ in range(2):
+            M.matvec(u, f, prec="fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            M.matvec(u, f, prec="fp64")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        if ref is None:
+            ref = f.clone()
+        info = M.info()
+        out["forms"][label] = {"rank": info["rank"], "build_s": round(build_s, 4), "device_bytes": info["device_bytes"],
+                               "ms_per_product": round(ms, 4),
+                               "rel_diff_vs_interpolation": float(torch.linalg.norm(f - ref) / torch.linalg.norm(ref))}
+        print(f"[bench]   {label}: rank {info['rank']}, build {build_s:.3f} s, {ms:.3f} ms/product",
+              file=sys.stderr, flush=True)
+        M.free()
+        del f
+    return out
+
+
 def serve_block(H, np, W, count):
     """Serving: Poisson arrivals of mixed solve requests (d, n, kernel, p drawn
     per request, f ~ N(0,1), a = 1 + x_1/2, relative residual 1e-8)."""
@@ -621,6 +661,10 @@ def main():
     if not args.no_tables:
         print("[bench] construction at the paper's table shapes", file=sys.stderr, flush=True)
         out["paper_tables"] = paper_tables_block(H, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_orth:
+        print("[bench] orthonormal and QRCP-truncated forms (Alg. 4.1 QR step)", file=sys.stderr, flush=True)
+        out["w3d_invr_n64_orth"] = orth_block(H, torch, np, W)
         torch.cuda.empty_cache()
     if not args.no_quasi:
         print("[bench] quasi-uniform grid through a uniform one (T Ahat S)", file=sys.stderr, flush=True)

@@ -92,6 +92,23 @@ typedef struct {
   int precisions;        /* bit mask of (1 << htlr_precision) the matrix will be
                             applied in; selects which core copies are kept;
                             0 selects all three                                    */
+  int orthonormalize;    /* Alg. 4.1's QR step (uniform grids; otherwise
+                            HTLR_ERR_UNSUPPORTED):
+                            0: interpolation form (Lagrange factors U, V and
+                               cores G = k(xi_t, eta_s), eq. 3.4);
+                            1: thin QR of the factors, U = W R, V = Q T, stored
+                               as W, Q with G <- G x_1 R ... x_{d+1} T ...; the
+                               same operator up to rounding;
+                            2: QR with column pivoting truncated at rank_tol
+                               (Sec. 2.1): a factor of numerical rank r < p
+                               keeps r columns.  One rank serves all levels (the
+                               largest level rank; smaller ones are padded with
+                               zero columns), so cores shrink to r^d x r^d only
+                               when every level's factor has rank <= r (for
+                               example p above the box side at every level
+                               with admissible leaves)                          */
+  double rank_tol;       /* orthonormalize = 2: keep pivots with
+                            |R_kk| > rank_tol |R_00|; <= 0 selects 1e-13       */
 } htlr_build_opts;
 
 /* Builds the HTLR matrix of the Nystrom operator above (Alg. 4.1).
@@ -214,6 +231,8 @@ typedef struct {
   size_t device_bytes;                /* what htlr_footprint reports                    */
   double diag0;                       /* D_0 = K_00 |Omega_0| (uniform: every D_i)       */
   int uniform_m;                      /* htlr_build_quasi handles: m; otherwise 0        */
+  int rank;                           /* Tucker rank of the stored factors and cores (p
+                                         unless QRCP truncated it)                       */
 } htlr_info_t;
 
 htlr_status htlr_info(htlr_matrix A, htlr_info_t* info);

@@ -36,7 +36,8 @@ class HTLRError(RuntimeError):
 
 class _BuildOpts(ctypes.Structure):
     _fields_ = [("eta2", ctypes.c_double), ("admissibility", ctypes.c_int), ("gl_order", ctypes.c_int),
-                ("a", ctypes.POINTER(ctypes.c_double)), ("precisions", ctypes.c_int)]
+                ("a", ctypes.POINTER(ctypes.c_double)), ("precisions", ctypes.c_int),
+                ("orthonormalize", ctypes.c_int), ("rank_tol", ctypes.c_double)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -53,7 +54,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("p", ctypes.c_int), ("leaf_side", ctypes.c_int),
                 ("levels", ctypes.c_int), ("uniform", ctypes.c_int), ("adm_pairs", ctypes.c_int64 * 16),
                 ("unique_cores", ctypes.c_int64 * 16), ("near_pairs", ctypes.c_int64),
-                ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double), ("uniform_m", ctypes.c_int)]
+                ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double), ("uniform_m", ctypes.c_int),
+                ("rank", ctypes.c_int)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -120,8 +122,13 @@ def _points_arg(points, d, n):
     return arr, arr.ctypes.data_as(_c_dp)
 
 
-def _opts(eta2, admissibility, gl_order, a, precisions):
+ORTH = {"none": 0, "qr": 1, "qrcp": 2}
+
+
+def _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize=0, rank_tol=0.0):
     o = _BuildOpts()
+    o.orthonormalize = ORTH[orthonormalize] if isinstance(orthonormalize, str) else int(orthonormalize)
+    o.rank_tol = float(rank_tol)
     o.eta2 = float(eta2)
     o.admissibility = ADM[admissibility] if isinstance(admissibility, str) else int(admissibility)
     o.gl_order = int(gl_order)
@@ -157,12 +164,12 @@ class HTLRMatrix:
     diag(a) + T Ahat S, Ahat on the uniform grid of m cells per dimension."""
 
     def __init__(self, points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
-                 a=None, precisions=0, m=None):
+                 a=None, precisions=0, m=None, orthonormalize=0, rank_tol=0.0):
         self.d, self.n, self.p, self.leaf, self.m = d, n, p, leaf, m
         self.N = n ** d
         self.kernel = kernel
         keep_pts, pts = _points_arg(points, d, n)
-        o, keep_a = _opts(eta2, admissibility, gl_order, a, precisions)
+        o, keep_a = _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize, rank_tol)
         h = _vp()
         kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         if m is None:
@@ -212,7 +219,7 @@ class HTLRMatrix:
         return {"d": i.d, "n": i.n, "p": i.p, "leaf_side": i.leaf_side, "levels": i.levels,
                 "uniform": bool(i.uniform), "adm_pairs": list(i.adm_pairs[: i.levels + 1]),
                 "unique_cores": list(i.unique_cores[: i.levels + 1]), "near_pairs": i.near_pairs,
-                "device_bytes": i.device_bytes, "diag0": i.diag0, "uniform_m": i.uniform_m}
+                "device_bytes": i.device_bytes, "diag0": i.diag0, "uniform_m": i.uniform_m, "rank": i.rank}
 
     def workspace_bytes(self, nrhs=1, prec="fp64") -> int:
         b = ctypes.c_size_t()
@@ -380,9 +387,9 @@ def htlr_build_quasi(points, kernel, d, n, m, p, leaf, **kw) -> HTLRMatrix:
 
 
 def htlr_footprint(points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
-                   precisions=0) -> int:
+                   precisions=0, orthonormalize=0, rank_tol=0.0) -> int:
     keep_pts, pts = _points_arg(points, d, n)
-    o, _ = _opts(eta2, admissibility, gl_order, None, precisions)
+    o, _ = _opts(eta2, admissibility, gl_order, None, precisions, orthonormalize, rank_tol)
     b = ctypes.c_size_t()
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     _check(lib().htlr_footprint(pts, kid, d, n, p, leaf, ctypes.byref(o), ctypes.byref(b)))

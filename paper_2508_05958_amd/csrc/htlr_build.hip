@@ -93,6 +93,30 @@ __global__ void k_downcast(const double* __restrict__ in, int64_t n, float* __re
   }
 }
 
+// Alg. 4.1's core update on a batch of cores: one mode product
+// out = in x_axis M (M: r x dims[axis], row-major), the axes in memory order
+// (fastest first: s_1..s_d, then t_1..t_d).  Grid: (blocks, cores).
+struct CoreDims { int n[6]; };
+
+__global__ void k_core_mode(const double* __restrict__ in, double* __restrict__ out, CoreDims dims, int axis,
+                            const double* __restrict__ M, int r, int64_t in_per_core, int64_t out_per_core) {
+  int64_t stride = 1;
+  for (int k = 0; k < axis; ++k) stride *= dims.n[k];
+  const int na = dims.n[axis];
+  const double* src = in + (int64_t)blockIdx.y * in_per_core;
+  double* dst = out + (int64_t)blockIdx.y * out_per_core;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < out_per_core;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pre = idx % stride, rest = idx / stride;
+    const int j = (int)(rest % r);
+    const int64_t post = rest / r;
+    const double* x = src + pre + stride * na * post;
+    double acc = 0.0;
+    for (int k = 0; k < na; ++k) acc += M[(int64_t)j * na + k] * x[stride * k];
+    dst[idx] = acc;
+  }
+}
+
 // Per-point diagonal integrals on a tensor grid (tensor Gauss-Legendre on
 // the cell of each point, eq. 1.4).
 template <int KID>
@@ -163,6 +187,82 @@ struct Builder {
     upload(b, f);
   }
 };
+
+// Alg. 4.1's QR step for one factor F (m x p, row-major): F = W R, W (m x r)
+// with orthonormal columns, R (r x p), by Householder reflections.  With
+// pivot, the column of largest remaining norm goes first and the
+// factorisation stops at the first pivot with |R_kk| <= tol |R_00| (QR with
+// column pivoting, truncated; the pivots' magnitudes do not increase).  R's
+// columns come back in F's order, so F ~ W R.  Returns r.
+static int orth_factor(const std::vector<double>& F, int m, int p, bool pivot, double tol, std::vector<double>* W,
+                       std::vector<double>* R) {
+  std::vector<double> A((size_t)m * p);                // column-major working copy
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < p; ++j) A[i + (size_t)m * j] = F[(size_t)i * p + j];
+  std::vector<int> perm(p);
+  for (int j = 0; j < p; ++j) perm[j] = j;
+  const int kmax = std::min(m, p);
+  std::vector<std::vector<double>> vs;
+  std::vector<double> vvs;
+  int r = kmax;
+  double r00 = 0.0;
+  for (int k = 0; k < kmax; ++k) {
+    if (pivot) {
+      int best = k;
+      double bn = -1.0;
+      for (int j = k; j < p; ++j) {
+        double sq = 0.0;
+        for (int i = k; i < m; ++i) sq += A[i + (size_t)m * j] * A[i + (size_t)m * j];
+        if (sq > bn) { bn = sq; best = j; }
+      }
+      if (best != k) {
+        for (int i = 0; i < m; ++i) std::swap(A[i + (size_t)m * k], A[i + (size_t)m * best]);
+        std::swap(perm[k], perm[best]);
+      }
+    }
+    double nrm = 0.0;
+    for (int i = k; i < m; ++i) nrm += A[i + (size_t)m * k] * A[i + (size_t)m * k];
+    nrm = std::sqrt(nrm);
+    const double alpha = A[k + (size_t)m * k] >= 0.0 ? -nrm : nrm;
+    std::vector<double> v(m - k);
+    for (int i = k; i < m; ++i) v[i - k] = A[i + (size_t)m * k];
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (double x : v) vv += x * x;
+    if (vv > 0.0)
+      for (int j = k; j < p; ++j) {
+        double dot = 0.0;
+        for (int i = k; i < m; ++i) dot += v[i - k] * A[i + (size_t)m * j];
+        const double f = 2.0 * dot / vv;
+        for (int i = k; i < m; ++i) A[i + (size_t)m * j] -= f * v[i - k];
+      }
+    vs.push_back(std::move(v));
+    vvs.push_back(vv);
+    const double rkk = std::fabs(A[k + (size_t)m * k]);
+    if (k == 0) r00 = rkk;
+    if (pivot && rkk <= tol * r00) { r = k; break; }
+  }
+  r = std::max(r, 1);
+  // W = first r columns of H_0 ... H_{r-1}
+  W->assign((size_t)m * r, 0.0);
+  std::vector<double> e(m);
+  for (int j = 0; j < r; ++j) {
+    std::fill(e.begin(), e.end(), 0.0);
+    e[j] = 1.0;
+    for (int k = std::min(r, (int)vs.size()) - 1; k >= 0; --k) {
+      if (vvs[k] <= 0.0) continue;
+      double dot = 0.0;
+      for (int i = k; i < m; ++i) dot += vs[k][i - k] * e[i];
+      const double f = 2.0 * dot / vvs[k];
+      for (int i = k; i < m; ++i) e[i] -= f * vs[k][i - k];
+    }
+    for (int i = 0; i < m; ++i) (*W)[(size_t)i * r + j] = e[i];
+  }
+  R->assign((size_t)r * p, 0.0);
+  for (int i = 0; i < r; ++i)
+    for (int j = i; j < p; ++j) (*R)[(size_t)i * p + perm[j]] = A[i + (size_t)m * j];
+  return r;
+}
 
 static bool translation_invariant(const htlr_matrix_impl& A) {
   // every kernel of the enumeration is a function of x - y; the grid decides
@@ -247,6 +347,40 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
     bd.upload_f32(A.T32, T);
   }
 
+  // Alg. 4.1's QR step (uniform grids: one factor per level).  One rank r
+  // serves every level, the largest level rank; W and R of a level with a
+  // smaller rank are padded with zero columns and rows (exact).
+  std::vector<std::vector<double>> orthW(A.L + 1), orthR(A.L + 1);
+  int rank = p;
+  if (A.orth) {
+    rank = 0;
+    std::vector<int> rl(A.L + 1, 0);
+    std::vector<double> ch(p);
+    for (int l = 0; l <= A.L; ++l) {
+      if (pl.adm[l].nnz() == 0) continue;
+      const int m = pl.m[l];
+      chebyshev_points(0.0, m * A.h, p, ch.data());
+      std::vector<double> xs(m), U((size_t)m * p);
+      for (int i = 0; i < m; ++i) xs[i] = (i + 0.5) * A.h;
+      lagrange_matrix(xs.data(), m, ch.data(), p, U.data());
+      rl[l] = orth_factor(U, m, p, A.orth == 2, A.rank_tol, &orthW[l], &orthR[l]);
+      rank = std::max(rank, rl[l]);
+    }
+    if (rank == 0) rank = p;
+    for (int l = 0; l <= A.L; ++l) {
+      if (rl[l] == 0 || rl[l] == rank) continue;
+      const int m = pl.m[l];
+      std::vector<double> W((size_t)m * rank, 0.0), R((size_t)rank * p, 0.0);
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < rl[l]; ++j) W[(size_t)i * rank + j] = orthW[l][(size_t)i * rl[l] + j];
+      std::copy(orthR[l].begin(), orthR[l].end(), R.begin());
+      orthW[l].swap(W);
+      orthR[l].swap(R);
+    }
+  }
+  int Pr = 1;
+  for (int k = 0; k < d; ++k) Pr *= rank;
+
   // admissible leaves, factors and cores per level
   A.levels.clear();
   A.levels.resize(A.L + 1);
@@ -268,8 +402,10 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
       chebyshev_points(0.0, m * A.h, p, cheb.data());
       std::vector<double> xs(m);
       for (int i = 0; i < m; ++i) xs[i] = (i + 0.5) * A.h;
-      std::vector<double> U((size_t)m * p), V((size_t)m * p);
+      std::vector<double> U((size_t)m * p), V;
       lagrange_matrix(xs.data(), m, cheb.data(), p, U.data());
+      if (A.orth) U = orthW[l];            // U = W R: store W (m x rank), R goes into the cores
+      V.resize(U.size());
       for (size_t i = 0; i < U.size(); ++i) V[i] = A.h * U[i];
       bd.upload(lv.U64, U);
       bd.upload(lv.V64, V);
@@ -321,7 +457,7 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
         }
       lv.ncore = (int)(lv.offsets.size() / 3);
       bd.upload(lv.cid, cid);
-      const size_t csz = (size_t)lv.ncore * P * P;
+      const size_t csz = (size_t)lv.ncore * Pr * Pr;      // stored cores, rank^d x rank^d each
       const bool want64 = A.precisions & (1 << HTLR_FP64);
       const bool want32 = A.precisions & (1 << HTLR_FP32);
       const bool want16 = A.precisions & (1 << HTLR_BF16_CORE);
@@ -339,11 +475,39 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
         chebyshev_points(0.0, m * A.h, p, crel.data());
         t2.upload(dcrel, crel);
         const int64_t PP = (int64_t)P * P;
+        // interpolation cores (eq. 3.4); with the QR step, into a work buffer
+        DevBuf raw, work, dR;
+        if (A.orth) {
+          raw.alloc((size_t)lv.ncore * PP * sizeof(double));
+          work.alloc((size_t)lv.ncore * PP * sizeof(double));
+          t2.upload(dR, orthR[l]);
+        }
+        double* Gbuild = A.orth ? raw.as<double>() : G64.as<double>();
         int bx = (int)std::min<int64_t>((PP + 255) / 256, 1024);
         HTLR_DISPATCH_KID(A.kid, hipLaunchKernelGGL(k_core_build<KID>, dim3(bx, lv.ncore), dim3(256), 0, 0,
                                                     doff.as<int>(), dcrel.as<double>(), m * A.h, d, p, P,
-                                                    pm1, G64.as<double>()));
+                                                    pm1, Gbuild));
         HTLR_HIP(hipGetLastError());
+        if (A.orth) {
+          // G <- G x_1 R ... x_d R x_{d+1} R ... x_{2d} R (U = W R and V = h W R),
+          // one mode product per axis, the last one into the stored cores
+          CoreDims dims{};
+          for (int k = 0; k < 2 * d; ++k) dims.n[k] = p;
+          double* bufs[2] = {raw.as<double>(), work.as<double>()};
+          int cur = 0;
+          int64_t in_per = PP;
+          for (int ax = 0; ax < 2 * d; ++ax) {
+            int64_t out_per = in_per / p * rank;
+            double* dst = ax == 2 * d - 1 ? G64.as<double>() : bufs[cur ^ 1];
+            int bm = (int)std::min<int64_t>((out_per + 255) / 256, 1024);
+            hipLaunchKernelGGL(k_core_mode, dim3(bm, lv.ncore), dim3(256), 0, 0, bufs[cur], dst, dims, ax,
+                               dR.as<double>(), rank, in_per, out_per);
+            HTLR_HIP(hipGetLastError());
+            dims.n[ax] = rank;
+            in_per = out_per;
+            cur ^= 1;
+          }
+        }
         int nb = (int)std::min<int64_t>(((int64_t)csz + 255) / 256, 65535);
         if (want32 || want16)
           hipLaunchKernelGGL(k_downcast, dim3(nb), dim3(256), 0, 0, G64.as<double>(), (int64_t)csz,
@@ -354,6 +518,9 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
       }
     }
   }
+  // products use the stored rank
+  A.rank = rank;
+  A.P = Pr;
 }
 
 static void init_handle(htlr_matrix_impl& A, const double* points, int kernel, int d, int n, int p,
@@ -376,10 +543,16 @@ static void init_handle(htlr_matrix_impl& A, const double* points, int kernel, i
   if (A.gl_order > 64) fail(HTLR_ERR_INVALID, "gl_order too large");
   A.precisions = (opts && opts->precisions) ? (opts->precisions & 7) : 7;
   if (!A.precisions) fail(HTLR_ERR_INVALID, "precisions mask selects nothing");
+  A.orth = opts ? opts->orthonormalize : 0;
+  if (A.orth < 0 || A.orth > 2) fail(HTLR_ERR_INVALID, "orthonormalize must be 0, 1 or 2");
+  A.rank_tol = (opts && opts->rank_tol > 0) ? opts->rank_tol : 1e-13;
+  A.rank = p;
   A.h = 1.0 / n;
   A.w0 = std::pow(A.h, d);
   A.plan = make_plan(A.grid, leaf, A.eta2, A.adm_kind);
   A.L = A.plan.L;
+  if (A.orth && !A.grid.uniform)
+    fail(HTLR_ERR_UNSUPPORTED, "orthonormal factors need a uniform grid (cores are shared by offset)");
   if (opts && opts->a) {
     for (int64_t i = 0; i < A.N; ++i)
       if (!std::isfinite(opts->a[i])) fail(HTLR_ERR_NUMERIC, "a(x) has NaN/Inf");
@@ -447,6 +620,7 @@ htlr_status htlr_info(htlr_matrix A, htlr_info_t* info) {
     info->device_bytes = A->device_bytes;
     info->diag0 = S.D0;
     info->uniform_m = A->quasi ? S.n : 0;
+    info->rank = S.rank;
   });
 }
 

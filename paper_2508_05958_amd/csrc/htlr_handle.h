@@ -167,6 +167,9 @@ struct htlr_matrix_impl {
   bool uniform = false;
   double eta2 = 1.0;
   int adm_kind = 0, gl_order = 0, precisions = 7;
+  int orth = 0;                      // Alg. 4.1's QR step: 0 none, 1 QR, 2 QRCP (truncated)
+  double rank_tol = 1e-13;
+  int rank = 0;                      // Tucker rank of stored factors and cores (P = rank^d)
   double h = 0, w0 = 0, D0 = 0;
   int device = 0;
   Grid grid;

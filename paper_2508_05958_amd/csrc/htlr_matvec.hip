@@ -858,7 +858,8 @@ TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
 
 template <typename T>
 static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st) {
-  const int d = A.d, p = A.p, P = A.P, n = A.n, pm1 = p - 1;
+  // p: Tucker rank of the stored factors; pm1: degree of the polynomial test kernel
+  const int d = A.d, p = A.rank, P = A.P, n = A.n, pm1 = A.p - 1;
   A.cur = find_tune(A, nrhs, prec);
   const bool f64 = std::is_same<T, double>::value;
   const Plan& pl = A.plan;
@@ -1141,8 +1142,9 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     htlr_tune_result res{};
     // cache lookup
     char key[256];
-    std::snprintf(key, sizeof(key), "d%d_n%d_p%d_leaf%d_k%d_%s_eta%.6g_adm%d_nrhs%d_prec%d", A->d, A->n, A->p, A->leaf,
-                  A->kid, A->uniform ? "uniform" : "tensor", A->eta2, A->adm_kind, nrhs, (int)prec);
+    std::snprintf(key, sizeof(key), "d%d_n%d_p%d_leaf%d_k%d_%s_eta%.6g_adm%d_nrhs%d_prec%d%s", A->d, A->n, A->p, A->leaf,
+                  A->kid, A->uniform ? "uniform" : "tensor", A->eta2, A->adm_kind, nrhs, (int)prec,
+                  A->rank != A->p ? ("_r" + std::to_string(A->rank)).c_str() : "");
     const char* cache = std::getenv("HTLR_TUNE_CACHE");
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "r");

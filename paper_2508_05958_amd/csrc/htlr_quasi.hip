@@ -253,6 +253,7 @@ htlr_status htlr_build_quasi(const double* points, htlr_kernel kernel, int d, in
     A->kid = kernel;
     A->N = N;
     A->P = I.P;
+    A->rank = I.rank;
     A->L = I.L;
     A->uniform = g.uniform;
     A->eta2 = I.eta2;

@@ -1,0 +1,119 @@
+"""GPU parity of Alg. 4.1's QR step (orthonormal factors, cores updated by
+the R factors) and of its QRCP truncation (Sec. 2.1), against the O2 oracle
+built the same way and against the interpolation form.
+
+Uniform grids only: there one factor per level serves every box, so the
+core update keeps one core per (level, offset).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry, htlr
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _gpu_matvec(torch, M, u, prec="fp64"):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ut = torch.tensor(np.asfortranarray(u), dtype=dt, device="cuda")
+    if u.ndim == 2:
+        ut = ut.t().contiguous().t()
+    f = M.matvec(ut, prec=prec)
+    torch.cuda.synchronize()
+    return f.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("d,n,leaf,p,kernel,nrhs,vs_oracle", [
+    (3, 32, 8, 6, "inv_r", 1, False),    # 216-row cores on the matrix cores; O2 here takes a minute
+    (2, 32, 4, 6, "neg_log", 3, True), (3, 16, 4, 4, "poly_test", 1, True), (3, 16, 4, 4, "exp", 9, True)])
+def test_qr_form(torch, d, n, leaf, p, kernel, nrhs, vs_oracle):
+    """The orthonormal form is the same operator: against the GPU
+    interpolation form (itself pinned to O2 by the uniform parity tests) and,
+    where O2 is quick, against O2 built with the QR step."""
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] QR form d={d} n={n} leaf={leaf} p={p} {kernel} nrhs={nrhs}")
+    g = geometry.uniform_grid(d, n)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal(g.N) if nrhs == 1 else np.asfortranarray(rng.standard_normal((g.N, nrhs)))
+    Mq = H.htlr_build(None, kernel, d, n, p, leaf, a=a, orthonormalize="qr")
+    Mr = H.htlr_build(None, kernel, d, n, p, leaf, a=a)
+    assert Mq.info()["rank"] == p
+    fq = _gpu_matvec(torch, Mq, u)
+    assert _rel(fq, _gpu_matvec(torch, Mr, u)) <= 1e-13
+    if vs_oracle:
+        O = htlr.HTLR(g, kernel, p, leaf, a, orthonormalize=True)
+        assert _rel(fq, O.matvec(u)) <= FP64_TOL
+    assert _rel(_gpu_matvec(torch, Mq, u, "fp32"), fq) <= 1e-5
+    assert _rel(_gpu_matvec(torch, Mq, u, "bf16"), fq) <= 5e-3
+
+
+@pytest.mark.parametrize("d,n,leaf,p,rank", [(2, 16, 2, 8, 4), (3, 8, 2, 5, 2), (2, 32, 4, 7, 7)])
+def test_qrcp_exact_truncation(torch, d, n, leaf, p, rank):
+    """Where factors are rank deficient (p above the box side) QRCP keeps the
+    operator: the handle's rank is the largest level rank, the product equals
+    the interpolation form and O2 with QRCP."""
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] QRCP exact d={d} n={n} leaf={leaf} p={p}")
+    g = geometry.uniform_grid(d, n)
+    a = np.ones(g.N)
+    u = np.random.default_rng(22).standard_normal(g.N)
+    M = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a, orthonormalize="qrcp")
+    info = M.info()
+    assert (info["p"], info["rank"]) == (p, rank)
+    f = _gpu_matvec(torch, M, u)
+    assert _rel(f, htlr.HTLR(g, "inv_r", p, leaf, a).matvec(u)) <= FP64_TOL
+    assert _rel(f, htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp").matvec(u)) <= FP64_TOL
+    assert _rel(_gpu_matvec(torch, M, u, "fp32"), f) <= 1e-5
+
+
+def test_qrcp_truncated_rank_cuts_cores(torch):
+    """A loose pivot tolerance truncates full-rank factors: rank 4 of 6, cores
+    (4^d)^2 instead of (6^d)^2, the same operator as O2 truncated alike."""
+    import paper_2508_05958_amd as H
+    _say("[gpu] QRCP truncated")
+    d, n, leaf, p = 2, 32, 4, 6
+    g = geometry.uniform_grid(d, n)
+    a = np.ones(g.N)
+    u = np.random.default_rng(23).standard_normal(g.N)
+    M = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a, orthonormalize="qrcp", rank_tol=0.3)
+    Mr = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a)
+    assert M.info()["rank"] == 4
+    assert M.info()["device_bytes"] < Mr.info()["device_bytes"]
+    f = _gpu_matvec(torch, M, u)
+    O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp", rank_tol=0.3)
+    assert _rel(f, O.matvec(u)) <= FP64_TOL
+    assert 1e-5 < _rel(f, _gpu_matvec(torch, Mr, u)) < 5e-2
+
+
+def test_orthonormal_needs_uniform_grid(torch):
+    import paper_2508_05958_amd as H
+    import htlr_workloads as W
+    _say("[gpu] orthonormalize on a warped grid")
+    x = W.warped_nodes(16)
+    with pytest.raises(H.HTLRError) as e:
+        H.htlr_build(np.concatenate([x] * 3), "inv_r", 3, 16, 4, 4, orthonormalize="qr")
+    assert e.value.status == -2
+    with pytest.raises(H.HTLRError) as e:
+        H.htlr_build(None, "inv_r", 3, 16, 4, 4, orthonormalize=3)
+    assert e.value.status == -1
