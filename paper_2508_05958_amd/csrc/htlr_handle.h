@@ -131,7 +131,8 @@ struct Profiler {
 struct TuneParams {
   int ks_target = 2048;              // matrix-core core apply: workgroups aimed for when splitting K
   int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel with
-                                     // right-hand sides as columns, 2 with target leaves as columns
+                                     // right-hand sides as columns, 2 with target leaves as columns,
+                                     // 3 the generic uniform-grid kernel (no row reuse)
   int near_nw = 0;                   // VALU row kernel: waves per leaf (0 automatic)
   int near_ks = 0;                   // leaf-column near kernel: K splits (0 automatic)
   int near_tpw = 0;                  // leaf-column near kernel: 16-row tiles per wave, 4 or 8 (0 = 8)
@@ -243,6 +244,11 @@ template <typename T>
 void launch_near_leaves(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st);
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
                       int nrhs, hipStream_t st);
+// Near field on uniform 2D grids with a radial kernel and leaves of 8 or 16
+// points per side: VALU kernel reusing each (row, row) block's 2m - 1 table values.
+bool near_rows2d_ok(const htlr_matrix_impl& A, int nrhs, int prec);
+template <typename T>
+void launch_near_rows2d(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st);
 // Work buffers of a product of this shape (handles from htlr_build).
 size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec);
 // f = A u on a handle from htlr_build (work buffers on demand); the caller

@@ -1032,6 +1032,8 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
 #undef HTLR_NEAR_NW
 #undef HTLR_NEAR_ROWS
 #undef HTLR_NEAR_ROWS3
+  } else if (A.uniform && d == 2 && A.cur.near_kind != 3 && near_rows2d_ok(A, nrhs, prec)) {
+    launch_near_rows2d<T>(A, u, f, nrhs, st);
   } else if (A.uniform) {
     const bool radial = A.kid != HTLR_K_POLY_TEST;
     const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
