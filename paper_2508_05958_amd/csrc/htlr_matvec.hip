@@ -614,6 +614,117 @@ __global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ H, T* _
   }
 }
 
+// Up contraction of a whole 2D box in one block (boxes of up to 64 x 64
+// points): the box X is staged in LDS, then T1[j1][s0] = sum_j0 V0[j0][s0]
+// X[j1][j0] and W[s1][s0] = sum_j1 V1[j1][s1] T1[j1][s0], two barriers per
+// box instead of a few per row.
+template <typename T, typename TW>
+__global__ __launch_bounds__(kThreads) void k_up2d_box(const T* __restrict__ u, TW* __restrict__ W,
+                                                       const T* __restrict__ V, int uniform, int n, int m, int B,
+                                                       int p, int nrhs) {
+  extern __shared__ unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);   // m*m  [j1][j0]
+  T* T1 = X + m * m;                       // m*p  [j1][s0]
+  const int tid = threadIdx.x;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int b0 = box % B, b1 = box / B;
+  const T* V0 = uniform ? V : V + (size_t)b0 * m * p;
+  const T* V1 = uniform ? V : V + ((size_t)B + b1) * m * p;
+  const T* ur = u + (int64_t)r * n * n;
+  for (int idx = tid; idx < m * m; idx += kThreads) {
+    const int j0 = idx % m, j1 = idx / m;
+    X[idx] = ur[(int64_t)(b0 * m + j0) + (int64_t)n * (b1 * m + j1)];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < m * p; idx += kThreads) {
+    const int s0 = idx % p, j1 = idx / p;
+    T v = T(0);
+    for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * X[j1 * m + j0];
+    T1[idx] = v;
+  }
+  __syncthreads();
+  TW* Wo = W + ((int64_t)box * nrhs + r) * p * p;
+  for (int idx = tid; idx < p * p; idx += kThreads) {
+    const int s0 = idx % p, s1 = idx / p;
+    T v = T(0);
+    for (int j1 = 0; j1 < m; ++j1) v += V1[j1 * p + s1] * T1[j1 * p + s0];
+    Wo[idx] = store_cast<TW>(v);
+  }
+}
+
+// Down expansion of a whole 2D box in one block (boxes of up to 64 x 64
+// points): Z[i1][t0] = sum_t1 U1[i1][t1] H[t1][t0], then
+// f[i1][i0] += sum_t0 U0[i0][t0] Z[i1][t0] (the sums of k_down, in its order).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_down2d_box(const T* __restrict__ H, T* __restrict__ f,
+                                                         const T* __restrict__ U, int uniform, int n, int m, int B,
+                                                         int p, int nrhs) {
+  extern __shared__ unsigned char smem_raw[];
+  T* hs = reinterpret_cast<T*>(smem_raw);  // p*p  [t1][t0]
+  T* Z = hs + p * p;                       // m*p  [i1][t0]
+  const int tid = threadIdx.x;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int b0 = box % B, b1 = box / B;
+  const T* U0 = uniform ? U : U + (size_t)b0 * m * p;
+  const T* U1 = uniform ? U : U + ((size_t)B + b1) * m * p;
+  const T* Hb = H + ((int64_t)box * nrhs + r) * p * p;
+  for (int t = tid; t < p * p; t += kThreads) hs[t] = Hb[t];
+  __syncthreads();
+  for (int idx = tid; idx < m * p; idx += kThreads) {
+    const int t0 = idx % p, i1 = idx / p;
+    T v = T(0);
+    for (int t1 = 0; t1 < p; ++t1) v += U1[i1 * p + t1] * hs[t1 * p + t0];
+    Z[idx] = v;
+  }
+  __syncthreads();
+  T* fr = f + (int64_t)r * n * n;
+  for (int idx = tid; idx < m * m; idx += kThreads) {
+    const int i0 = idx % m, i1 = idx / m;
+    T v = T(0);
+    for (int t0 = 0; t0 < p; ++t0) v += U0[i0 * p + t0] * Z[i1 * p + t0];
+    fr[(int64_t)(b0 * m + i0) + (int64_t)n * (b1 * m + i1)] += v;
+  }
+}
+
+// Down expansion of 2D boxes, R rows at a time (R m <= 4096 outputs):
+// Z[ir][t0] = sum_t1 U1[i1][t1] H[t1][t0], then
+// f[i1][i0] += sum_t0 U0[i0][t0] Z[ir][t0] (the sums of k_down, in its order).
+// Grid (boxes, rhs, row chunks); chunks write disjoint rows of f.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_down2d(const T* __restrict__ H, T* __restrict__ f,
+                                                     const T* __restrict__ U, int uniform, int n, int m, int B, int p,
+                                                     int nrhs, int rpc, int R) {
+  extern __shared__ unsigned char smem_raw[];
+  T* hs = reinterpret_cast<T*>(smem_raw);  // p*p  [t1][t0]
+  T* Z = hs + p * p;                       // R*p  [ir][t0]
+  const int tid = threadIdx.x;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int lo = blockIdx.z * rpc, hi = min(m, lo + rpc);
+  const int b0 = box % B, b1 = box / B;
+  const T* U0 = uniform ? U : U + (size_t)b0 * m * p;
+  const T* U1 = uniform ? U : U + ((size_t)B + b1) * m * p;
+  const T* Hb = H + ((int64_t)box * nrhs + r) * p * p;
+  for (int t = tid; t < p * p; t += kThreads) hs[t] = Hb[t];
+  T* fr = f + (int64_t)r * n * n;
+  for (int ia = lo; ia < hi; ia += R) {
+    const int nr = min(R, hi - ia);
+    __syncthreads();
+    for (int idx = tid; idx < nr * p; idx += kThreads) {
+      const int t0 = idx % p, ir = idx / p;
+      T v = T(0);
+      for (int t1 = 0; t1 < p; ++t1) v += U1[(ia + ir) * p + t1] * hs[t1 * p + t0];
+      Z[idx] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nr * m; idx += kThreads) {
+      const int i0 = idx % m, ir = idx / m;
+      T v = T(0);
+      for (int t0 = 0; t0 < p; ++t0) v += U0[i0 * p + t0] * Z[ir * p + t0];
+      fr[(int64_t)(b0 * m + i0) + (int64_t)n * (b1 * m + ia + ir)] += v;
+    }
+  }
+}
+
 // Core apply with one stored core per offset (uniform grids), plain VALU
 // version: one block per (target box, rhs chunk), one thread per core row t.
 // G layout: GT = true -> [core][s][t], false -> [core][t][s].
@@ -900,6 +1011,11 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
     const int nch = level_chunks(lv, nrhs), rpc = (lm + nch - 1) / nch;
     T* upart = nch > 1 ? A.ws.UP[l].as<T>() : nullptr;
+    // 2D boxes up to 64 points per side: one block contracts the whole box
+    // (larger boxes keep the row kernel, which spreads each row's dots over
+    // the whole block)
+    const bool box2d = d == 2 && nch == 1 && lm <= 64;
+    const size_t sh_box = ((size_t)lm * lm + (size_t)lm * p) * sizeof(T);
     const int64_t wcount = lv.nbox * (int64_t)nrhs * P;
     if (prec == HTLR_BF16_CORE) {
       if constexpr (!std::is_same<T, double>::value) {
@@ -907,6 +1023,10 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
         if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
         uint16_t* W16 = A.ws.W[l].as<uint16_t>();
         { ProfScope ps(A, "up", l, ls);
+        if (box2d)
+          hipLaunchKernelGGL((k_up2d_box<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W16, V,
+                             1, n, lm, lB, p, nrhs);
+        else
         hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W16, V,
                            1, d, n, lm, lB, p, nrhs, rpc, (float*)upart, up_rows);
         if (nch > 1)
@@ -930,6 +1050,10 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     } else {
     T* W = A.ws.W[l].as<T>();
     { ProfScope ps(A, "up", l, ls);
+    if (box2d)
+      hipLaunchKernelGGL((k_up2d_box<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W, V,
+                         A.uniform ? 1 : 0, n, lm, lB, p, nrhs);
+    else
     hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W, V, A.uniform ? 1 : 0,
                        d, n, lm, lB, p, nrhs, rpc, upart, up_rows);
     if (nch > 1)
@@ -1071,6 +1195,19 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
     const int nch = level_chunks(lv, nrhs), rpc = (lm + nch - 1) / nch;
     ProfScope ps(A, "down", l, st);
+    // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
+    // 256 points (measured faster than the row kernel there), the row kernel
+    // for larger boxes
+    if (d == 2 && nch == 1 && lm <= 64) {
+      hipLaunchKernelGGL((k_down2d_box<T>), dim3(lv.nbox, nrhs), dim3(kThreads),
+                         ((size_t)p * p + (size_t)lm * p) * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p,
+                         nrhs);
+    } else if (d == 2 && lm >= 128 && lm <= 256) {
+      const int R2 = std::max(1, std::min(rpc, 4096 / lm));
+      hipLaunchKernelGGL((k_down2d<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads),
+                         ((size_t)p * p + (size_t)R2 * p) * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p,
+                         nrhs, rpc, R2);
+    } else
     hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_dn, st, H, f, U, A.uniform ? 1 : 0, d,
                        n, lm, lB, p, nrhs, rpc);
     HTLR_HIP(hipGetLastError());
