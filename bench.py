@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-orth", action="store_true", help="skip the orthonormal / QRCP forms block")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2508_05958_amd", "tuned_mi355x.txt"),
+                    help="autotuner cache file (HTLR_TUNE_CACHE) used unless that variable is set; its lines are the "
+                         "tuner's own output, so runs of the same shape use the same kernel variants")
     ap.add_argument("--no-tables", action="store_true", help="skip construction at the paper's table shapes")
     ap.add_argument("--serial", action="store_true",
                     help="time the profiled, serially issued product (for kernel-trace runs: every kernel's "
@@ -600,6 +603,8 @@ def main():
     import paper_2508_05958_amd as H
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not os.environ.get("HTLR_TUNE_CACHE") and args.tune_cache and os.path.exists(args.tune_cache):
+        os.environ["HTLR_TUNE_CACHE"] = args.tune_cache
     w = W.WORKLOADS[args.workload]
     prec = args.prec or ("fp64" if w.nrhs == 1 else "bf16")
     print(f"[bench] {w.name} {prec}: build + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
@@ -620,6 +625,7 @@ def main():
                    "p": w.p, "leaf": w.leaf, "nrhs": nrhs, "precision": prec, "admissibility": "strong, eta=1",
                    "parallelism": "1 GPU", "autotuned": not args.no_tune},
         "build_s": round(build_s, 3), "device_bytes": info["device_bytes"],
+        "tune_cache": os.path.relpath(os.environ["HTLR_TUNE_CACHE"], ROOT) if os.environ.get("HTLR_TUNE_CACHE") else None,
         "roofline": roof, "kernels": per,
     }
     M.free()
