@@ -686,6 +686,66 @@ __global__ __launch_bounds__(kThreads) void k_down2d_box(const T* __restrict__ H
   }
 }
 
+// Up contraction of large 2D boxes (128 points per side and more): R rows
+// staged at a time (R m <= 4096, R p <= kThreads), each of a stage's R p dots
+// (length m) split over G = kThreads / (R p) threads and combined through LDS
+// in group order; thread t < p^2 accumulates W[s1][s0] over the rows in order.
+// Four barriers per stage of R rows.  Grid (boxes, rhs, row chunks); with
+// several chunks the partial sums go to part (summed by k_up_reduce).
+template <typename T, typename TW>
+__global__ __launch_bounds__(kThreads) void k_up2d_rows(const T* __restrict__ u, TW* __restrict__ W,
+                                                        const T* __restrict__ V, int uniform, int n, int m, int B,
+                                                        int p, int nrhs, int rpc, int R, T* __restrict__ part) {
+  extern __shared__ unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);   // R*m      [jr][j0]
+  T* red = X + R * m;                      // kThreads partial dots
+  T* T1 = red + kThreads;                  // R*p      [jr][s0]
+  const int tid = threadIdx.x;
+  const int box = blockIdx.x, r = blockIdx.y;
+  const int lo = blockIdx.z * rpc, hi = min(m, lo + rpc);
+  const int b0 = box % B, b1 = box / B;
+  const T* V0 = uniform ? V : V + (size_t)b0 * m * p;
+  const T* V1 = uniform ? V : V + ((size_t)B + b1) * m * p;
+  const T* ur = u + (int64_t)r * n * n;
+  const int P = p * p;
+  const int s0 = tid % p, s1 = tid / p;
+  T acc = T(0);
+  for (int ja = lo; ja < hi; ja += R) {
+    const int nr = min(R, hi - ja);
+    const int nout = nr * p, G = kThreads / nout;
+    __syncthreads();
+    for (int idx = tid; idx < nr * m; idx += kThreads) {
+      const int j0 = idx % m, jr = idx / m;
+      X[idx] = ur[(int64_t)(b0 * m + j0) + (int64_t)n * (b1 * m + ja + jr)];
+    }
+    __syncthreads();
+    {
+      const int o = tid % nout, g = tid / nout;
+      if (g < G) {
+        const int c0 = o % p, jr = o / p;
+        T v = T(0);
+        for (int j0 = g; j0 < m; j0 += G) v += V0[j0 * p + c0] * X[jr * m + j0];
+        red[g * nout + o] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < nout) {
+      T v = T(0);
+      for (int k = 0; k < G; ++k) v += red[k * nout + tid];
+      T1[tid] = v;
+    }
+    __syncthreads();
+    if (tid < P)
+      for (int jr = 0; jr < nr; ++jr) acc += V1[(ja + jr) * p + s1] * T1[jr * p + s0];
+  }
+  if (tid >= P) return;
+  if (part) {
+    part[(((int64_t)blockIdx.z * gridDim.x + box) * nrhs + r) * P + tid] = acc;
+    return;
+  }
+  W[((int64_t)box * nrhs + r) * P + tid] = store_cast<TW>(acc);
+}
+
 // Down expansion of 2D boxes, R rows at a time (R m <= 4096 outputs):
 // Z[ir][t0] = sum_t1 U1[i1][t1] H[t1][t0], then
 // f[i1][i0] += sum_t0 U0[i0][t0] Z[ir][t0] (the sums of k_down, in its order).
@@ -878,17 +938,24 @@ static int pick_rc(int nrhs, size_t fixed_bytes, size_t per_rc_bytes) {
 // Chunks of the up contraction and down expansion of a level: levels with
 // few, large boxes spread each box over several blocks (at least 4 slices
 // each), aiming at about 512 blocks.
-static int level_chunks(const LevelData& lv, int nrhs) {
+static int chunk_target(const LevelData& lv, int d) {
+  // 2D boxes of 128 points per side and more: about 2048 blocks (each block
+  // stages row chunks, and a level of such boxes has few of them)
+  return (d == 2 && lv.m >= 128) ? 2048 : 512;
+}
+
+static int level_chunks(const LevelData& lv, int nrhs, int d) {
   const int64_t base = lv.nbox * (int64_t)nrhs;
-  if (lv.m < 16 || base >= 256) return 1;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(lv.m / 4, (512 + base - 1) / base));
+  const int target = chunk_target(lv, d);
+  if (lv.m < 16 || base >= (target == 512 ? 256 : target)) return 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(lv.m / 4, (target + base - 1) / base));
 }
 
 // Elements of a level's partial up-contraction buffer, enough for every
-// right-hand-side count up to nrhs (chunks x boxes x rhs <= 512 + boxes x nrhs).
-static size_t up_part_elems(const LevelData& lv, int nrhs, int P) {
-  if (level_chunks(lv, 1) <= 1) return 0;
-  return (size_t)(512 + lv.nbox * (int64_t)nrhs) * P;
+// right-hand-side count up to nrhs (chunks x boxes x rhs <= target + boxes x rhs).
+static size_t up_part_elems(const LevelData& lv, int nrhs, int P, int d) {
+  if (level_chunks(lv, 1, d) <= 1) return 0;
+  return (size_t)(chunk_target(lv, d) + lv.nbox * (int64_t)nrhs) * P;
 }
 
 size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
@@ -898,7 +965,7 @@ size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
     if (lv.npairs == 0) continue;
     size_t cnt = (size_t)lv.nbox * nrhs * A.P;
     tot += 2 * ((cnt * sizeof(double) + 255) & ~size_t(255));
-    tot += up_part_elems(lv, nrhs, A.P) * sizeof(double);
+    tot += up_part_elems(lv, nrhs, A.P, A.d) * sizeof(double);
   }
   return tot;
 }
@@ -922,7 +989,7 @@ void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
     size_t cnt = (size_t)lv.nbox * nrhs * A.P;
     ws.W[lv.level].alloc(cnt * sizeof(double));
     ws.H[lv.level].alloc(cnt * sizeof(double));
-    ws.UP[lv.level].alloc(up_part_elems(lv, nrhs, A.P) * sizeof(double));
+    ws.UP[lv.level].alloc(up_part_elems(lv, nrhs, A.P, A.d) * sizeof(double));
     ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes + ws.UP[lv.level].bytes;
   }
   ws.zero.alloc((size_t)A.P * sizeof(double));
@@ -1009,13 +1076,17 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     const size_t sh_up = (d == 3 ? (size_t)up_rows * lm + (size_t)p * lm + (size_t)p * p
                                  : (size_t)lm + (size_t)kThreads + (size_t)p) * sizeof(T);
     if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
-    const int nch = level_chunks(lv, nrhs), rpc = (lm + nch - 1) / nch;
+    const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
     T* upart = nch > 1 ? A.ws.UP[l].as<T>() : nullptr;
     // 2D boxes up to 64 points per side: one block contracts the whole box
     // (larger boxes keep the row kernel, which spreads each row's dots over
     // the whole block)
     const bool box2d = d == 2 && nch == 1 && lm <= 64;
     const size_t sh_box = ((size_t)lm * lm + (size_t)lm * p) * sizeof(T);
+    // larger 2D boxes: staged rows with each dot split over the block
+    const bool rows2d = d == 2 && !box2d && lm >= 128;
+    const int Rr = std::max(1, std::min(std::min(rpc, 4096 / lm), kThreads / p));
+    const size_t sh_rows = ((size_t)Rr * lm + (size_t)kThreads + (size_t)Rr * p) * sizeof(T);
     const int64_t wcount = lv.nbox * (int64_t)nrhs * P;
     if (prec == HTLR_BF16_CORE) {
       if constexpr (!std::is_same<T, double>::value) {
@@ -1026,6 +1097,9 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
         if (box2d)
           hipLaunchKernelGGL((k_up2d_box<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W16, V,
                              1, n, lm, lB, p, nrhs);
+        else if (rows2d)
+          hipLaunchKernelGGL((k_up2d_rows<float, uint16_t>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_rows, ls, u,
+                             W16, V, 1, n, lm, lB, p, nrhs, rpc, Rr, (float*)upart);
         else
         hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W16, V,
                            1, d, n, lm, lB, p, nrhs, rpc, (float*)upart, up_rows);
@@ -1053,6 +1127,9 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     if (box2d)
       hipLaunchKernelGGL((k_up2d_box<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W, V,
                          A.uniform ? 1 : 0, n, lm, lB, p, nrhs);
+    else if (rows2d)
+      hipLaunchKernelGGL((k_up2d_rows<T, T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_rows, ls, u, W, V,
+                         A.uniform ? 1 : 0, n, lm, lB, p, nrhs, rpc, Rr, upart);
     else
     hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W, V, A.uniform ? 1 : 0,
                        d, n, lm, lB, p, nrhs, rpc, upart, up_rows);
@@ -1193,7 +1270,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     if (fork) HTLR_HIP(hipStreamWaitEvent(st, A.ev_level[li], 0));
     const size_t sh_dn = ((size_t)P + (d == 3 ? (size_t)p * p + (size_t)lm * p : (size_t)p)) * sizeof(T);
     if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
-    const int nch = level_chunks(lv, nrhs), rpc = (lm + nch - 1) / nch;
+    const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
     ProfScope ps(A, "down", l, st);
     // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
     // 256 points (measured faster than the row kernel there), the row kernel
