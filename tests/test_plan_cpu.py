@@ -94,3 +94,36 @@ def test_nodes_must_increase():
     with pytest.raises(H.HTLRError) as e:
         H.htlr_plan_counts(np.concatenate([x, x]), 2, 16, 4)
     assert e.value.status == -1
+
+
+def test_footprint_follows_the_qr_rank():
+    """The dry build runs the host QR(CP) of the shared factors.  Where every
+    level's factor has rank m < p (n = 16, leaf 2: boxes of 4 and 2 points,
+    p = 8) the stored rank is 4 and the cores shrink from (8^2)^2 to (4^2)^2
+    per offset; with p at most the box side everywhere the size is unchanged."""
+    full = H.htlr_footprint(None, "inv_r", 2, 16, 8, 2)
+    qr = H.htlr_footprint(None, "inv_r", 2, 16, 8, 2, orthonormalize="qr")
+    qrcp = H.htlr_footprint(None, "inv_r", 2, 16, 8, 2, orthonormalize="qrcp")
+    assert qr == qrcp and qr < full / 8
+    assert H.htlr_footprint(None, "inv_r", 2, 64, 6, 8, orthonormalize="qr") == H.htlr_footprint(None, "inv_r", 2, 64, 6, 8)
+    # a loose pivot tolerance truncates full-rank factors too (rank 4 of 6)
+    assert H.htlr_footprint(None, "inv_r", 2, 32, 6, 4, orthonormalize="qrcp", rank_tol=0.3) < \
+        H.htlr_footprint(None, "inv_r", 2, 32, 6, 4) / 4
+
+
+def test_orthonormalize_and_quasi_arguments_are_checked():
+    with pytest.raises(H.HTLRError) as e:
+        H.htlr_footprint(None, "inv_r", 2, 16, 8, 2, orthonormalize=3)
+    assert e.value.status == -1
+    x = W.warped_nodes(16)
+    with pytest.raises(H.HTLRError) as e:
+        H.htlr_footprint(np.concatenate([x] * 2), "inv_r", 2, 16, 4, 4, orthonormalize="qr")
+    assert e.value.status == -2
+    with pytest.raises(H.HTLRError) as e:
+        H.htlr_build_quasi(None, "inv_r", 3, 12, 0, 4, 4)
+    assert e.value.status == -1
+    bad = np.concatenate([W.warped_nodes(12)] * 3)
+    bad[3] = bad[2]
+    with pytest.raises(H.HTLRError) as e:
+        H.htlr_build_quasi(bad, "inv_r", 3, 12, 16, 4, 4)
+    assert e.value.status == -1
