@@ -433,24 +433,29 @@ static int core_mfma_nb(int nrhs, int bnt) {
 // Tile shape for one level: 1 = 128x128, 2 = 128x64 (few columns), 3 = 256x128.
 // 64-column tiles in FP64 take the 224-row shape when p^d fits it better
 // than 128-row blocks do (192 < p^d <= 224).
+// Cores of at most 64 rows (p^d <= 64, e.g. p = 4 in 3D, p = 8 in 2D) take
+// 64-row tiles: 7 = 64x64, 6 = 64x128 (no padded half of a 128-row tile).
 static int narrow_variant(const htlr_matrix_impl& A, int prec) {
+  if (A.P <= 64) return 7;
   return (prec == HTLR_FP64 && A.P > 192 && A.P <= 224) ? 4 : 2;
 }
 
 static int pick_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
-  if (A.cur.tile >= 1 && A.cur.tile <= 5) return A.cur.tile;
+  if (A.cur.tile >= 1 && A.cur.tile <= 7) return A.cur.tile;
   const int64_t class_boxes = lv.nbox >> A.d;
   if (class_boxes * nrhs <= 64) return narrow_variant(A, prec);
+  if (A.P <= 64) return 6;
   if (prec == HTLR_BF16_CORE && A.P >= 256) return class_boxes * nrhs >= 256 ? 5 : 3;
   return 1;
 }
 
 // Tile shape of a variant: 1 = 128x128, 2 = 128x64, 3 = 256x128, 4 = 224x64
 // (FP64; the other precisions run variant 4 as 128x64), 5 = 256x256
-// (bfloat16, half the core reads per column; the others run it as 256x128).
+// (bfloat16, half the core reads per column; the others run it as 256x128),
+// 6 = 64x128, 7 = 64x64.
 static void variant_shape(int v, int prec, int* bmt, int* bnt) {
-  *bmt = (v == 3 || v == 5) ? 256 : (v == 4 && prec == HTLR_FP64 ? 224 : 128);
-  *bnt = (v == 2 || v == 4) ? 64 : (v == 5 && prec == HTLR_BF16_CORE ? 256 : 128);
+  *bmt = (v == 6 || v == 7) ? 64 : (v == 3 || v == 5) ? 256 : (v == 4 && prec == HTLR_FP64 ? 224 : 128);
+  *bnt = (v == 2 || v == 4 || v == 7) ? 64 : (v == 5 && prec == HTLR_BF16_CORE ? 256 : 128);
 }
 
 template <typename TE> struct NarrowRows { static constexpr int value = 128; };
@@ -627,9 +632,9 @@ static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int
 // Tile shape of the offset-major mode: 128x64 unless an offset's boxes
 // times right-hand sides fill well over 128 columns on average.
 static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
-  if (A.cur.tile >= 1 && A.cur.tile <= 5) return A.cur.tile;
+  if (A.cur.tile >= 1 && A.cur.tile <= 7) return A.cur.tile;
   const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
-  return avg * nrhs <= 128 ? narrow_variant(A, prec) : 1;
+  return avg * nrhs <= 128 ? narrow_variant(A, prec) : (A.P <= 64 ? 6 : 1);
 }
 
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
@@ -661,6 +666,8 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     case 5: launch_variant_out<TE, 256, WideCols<TE>::value>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs,   \
                                                             lv.B, st); break;                                        \
     case 3: launch_variant_out<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;  \
+    case 6: launch_variant_out<TE, 64, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
+    case 7: launch_variant_out<TE, 64, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;    \
     default: launch_variant_out<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break; \
   }
     if (prec == HTLR_BF16_CORE) {
@@ -716,6 +723,10 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
                                         A.P, nrhs, nb, lv.B, st); break;                                         \
     case 3: launch_variant<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems, \
                                          A.P, nrhs, nb, lv.B, st); break;                                        \
+    case 6: launch_variant<TE, 64, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
+                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+    case 7: launch_variant<TE, 64, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,   \
+                                       A.P, nrhs, nb, lv.B, st); break;                                          \
     default: launch_variant<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks,       \
                                           helems, A.P, nrhs, nb, lv.B, st); break;                               \
   }

@@ -137,7 +137,8 @@ struct TuneParams {
   int near_ks = 0;                   // leaf-column near kernel: K splits (0 automatic)
   int near_tpw = 0;                  // leaf-column near kernel: 16-row tiles per wave, 4 or 8 (0 = 8)
   int near_ct = 0;                   // leaf-column near kernel: 16-column tiles per wave, 1 or 2 (0 = 1)
-  int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128
+  int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128,
+                                     // 4 224x64 (FP64), 5 256x256 (BF16), 6 64x128, 7 64x64
   int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
   int serial = 0;                    // 1: every launch on the caller's stream (no level concurrency)
 };

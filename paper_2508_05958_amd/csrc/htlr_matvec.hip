@@ -1440,7 +1440,7 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
-      for (int tile : {1, 2, 3, 4, 5}) {
+      for (int tile : {1, 2, 3, 4, 5, 6, 7}) {
         TuneParams t = best;
         t.tile = tile;
         const double ms = time_with(t);

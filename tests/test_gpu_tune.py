@@ -66,10 +66,10 @@ def test_server_with_autotune(torch):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("mode", [1, 2])
 def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mode):
-    """Force each matrix-core tile shape (128x128, 128x64, 256x128, 224x64, 256x256) through
+    """Force each matrix-core tile shape (128x128, 128x64, 256x128, 224x64, 256x256, 64x128, 64x64) through
     the tuner's cache file and compare with the oracle (FP64) or with the
     GPU FP64 product (FP32, BF16)."""
     import paper_2508_05958_amd as H
