@@ -785,6 +785,139 @@ __global__ __launch_bounds__(kThreads) void k_down2d(const T* __restrict__ H, T*
   }
 }
 
+// Up contraction of small 3D boxes (up to 8 points per side) in one pass:
+// nb boxes per block, each box staged in LDS, then
+//   T1[j2][j1][s0] = sum_j0 V0[j0][s0] X[j2][j1][j0],
+//   T2[j2][s1][s0] = sum_j1 V1[j1][s1] T1[j2][j1][s0],
+//   W[s2][s1][s0]  = sum_j2 V2[j2][s2] T2[j2][s1][s0]
+// (the sums of k_up, in its order), three barriers per block.
+template <typename T, typename TW>
+__global__ __launch_bounds__(kThreads) void k_up3d_small(const T* __restrict__ u, TW* __restrict__ W,
+                                                         const T* __restrict__ V, int uniform, int n, int m, int B,
+                                                         int p, int nrhs, int nb, int64_t nbox) {
+  extern __shared__ unsigned char smem_raw[];
+  const int m2 = m * m, m3 = m2 * m, pp = p * p, P = pp * p;
+  const int per = m3 + m2 * p + m * pp;    // LDS values per box
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x, r = blockIdx.y;
+  const int64_t box0 = (int64_t)blockIdx.x * nb;
+  const T* ur = u + (int64_t)r * n * n * n;
+  auto Vk = [&](int k, int64_t box) -> const T* {
+    if (uniform) return V;
+    const int64_t bk = k == 0 ? box % B : (k == 1 ? (box / B) % B : box / ((int64_t)B * B));
+    return V + ((size_t)k * B + bk) * (size_t)m * p;
+  };
+  for (int idx = tid; idx < nb * m3; idx += kThreads) {
+    const int bl = idx / m3, q = idx % m3;
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const int j0 = q % m, j1 = (q / m) % m, j2 = q / m2;
+    const int64_t b0 = box % B, b1 = (box / B) % B, b2 = box / ((int64_t)B * B);
+    sh[bl * per + q] = ur[lin3((int)(b0 * m + j0), (int)(b1 * m + j1), (int)(b2 * m + j2), n)];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * m2 * p; idx += kThreads) {
+    const int bl = idx / (m2 * p), q = idx % (m2 * p);
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const int s0 = q % p, j12 = q / p;           // j12 = j1 + m j2
+    const T* V0 = Vk(0, box);
+    const T* X = sh + bl * per + j12 * m;
+    T v = T(0);
+    for (int j0 = 0; j0 < m; ++j0) v += V0[j0 * p + s0] * X[j0];
+    sh[bl * per + m3 + q] = v;                   // T1[j2][j1][s0]
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * m * pp; idx += kThreads) {
+    const int bl = idx / (m * pp), q = idx % (m * pp);
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const int s0 = q % p, s1 = (q / p) % p, j2 = q / pp;
+    const T* V1 = Vk(1, box);
+    const T* T1 = sh + bl * per + m3 + j2 * m * p;
+    T v = T(0);
+    for (int j1 = 0; j1 < m; ++j1) v += V1[j1 * p + s1] * T1[j1 * p + s0];
+    sh[bl * per + m3 + m2 * p + q] = v;          // T2[j2][s1][s0]
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * P; idx += kThreads) {
+    const int bl = idx / P, t = idx % P;
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const T* V2 = Vk(2, box);
+    const T* T2 = sh + bl * per + m3 + m2 * p;
+    T v = T(0);
+    for (int j2 = 0; j2 < m; ++j2) v += V2[j2 * p + t / pp] * T2[j2 * pp + t % pp];
+    W[(box * nrhs + r) * P + t] = store_cast<TW>(v);
+  }
+}
+
+// Down expansion of small 3D boxes (up to 8 points per side) in one pass:
+//   Z2[i2][t1][t0] = sum_t2 U2[i2][t2] H[t2][t1][t0],
+//   Z1[i2][i1][t0] = sum_t1 U1[i1][t1] Z2[i2][t1][t0],
+//   f[i2][i1][i0] += sum_t0 U0[i0][t0] Z1[i2][i1][t0]
+// (the sums of k_down, in its order), nb boxes per block.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_down3d_small(const T* __restrict__ H, T* __restrict__ f,
+                                                           const T* __restrict__ U, int uniform, int n, int m, int B,
+                                                           int p, int nrhs, int nb, int64_t nbox) {
+  extern __shared__ unsigned char smem_raw[];
+  const int m2 = m * m, m3 = m2 * m, pp = p * p, P = pp * p;
+  const int per = P + m * pp + m2 * p;     // LDS values per box
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x, r = blockIdx.y;
+  const int64_t box0 = (int64_t)blockIdx.x * nb;
+  auto Uk = [&](int k, int64_t box) -> const T* {
+    if (uniform) return U;
+    const int64_t bk = k == 0 ? box % B : (k == 1 ? (box / B) % B : box / ((int64_t)B * B));
+    return U + ((size_t)k * B + bk) * (size_t)m * p;
+  };
+  for (int idx = tid; idx < nb * P; idx += kThreads) {
+    const int bl = idx / P, t = idx % P;
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    sh[bl * per + t] = H[(box * nrhs + r) * P + t];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * m * pp; idx += kThreads) {
+    const int bl = idx / (m * pp), q = idx % (m * pp);
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const int t01 = q % pp, i2 = q / pp;
+    const T* U2 = Uk(2, box);
+    const T* hs = sh + bl * per;
+    T v = T(0);
+    for (int t2 = 0; t2 < p; ++t2) v += U2[i2 * p + t2] * hs[t2 * pp + t01];
+    sh[bl * per + P + q] = v;                    // Z2[i2][t1][t0]
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * m2 * p; idx += kThreads) {
+    const int bl = idx / (m2 * p), q = idx % (m2 * p);
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const int t0 = q % p, i1 = (q / p) % m, i2 = q / (m * p);
+    const T* U1 = Uk(1, box);
+    const T* Z2 = sh + bl * per + P + i2 * pp;
+    T v = T(0);
+    for (int t1 = 0; t1 < p; ++t1) v += U1[i1 * p + t1] * Z2[t1 * p + t0];
+    sh[bl * per + P + m * pp + q] = v;           // Z1[i2][i1][t0]
+  }
+  __syncthreads();
+  T* fr = f + (int64_t)r * n * n * n;
+  for (int idx = tid; idx < nb * m3; idx += kThreads) {
+    const int bl = idx / m3, q = idx % m3;
+    const int64_t box = box0 + bl;
+    if (box >= nbox) continue;
+    const int i0 = q % m, i12 = q / m;           // i12 = i1 + m i2
+    const T* U0 = Uk(0, box);
+    const T* Z1 = sh + bl * per + P + m * pp + i12 * p;
+    T v = T(0);
+    for (int t0 = 0; t0 < p; ++t0) v += U0[i0 * p + t0] * Z1[t0];
+    const int64_t b0 = box % B, b1 = (box / B) % B, b2 = box / ((int64_t)B * B);
+    fr[lin3((int)(b0 * m + i0), (int)(b1 * m + i12 % m), (int)(b2 * m + i12 / m), n)] += v;
+  }
+}
+
 // Core apply with one stored core per offset (uniform grids), plain VALU
 // version: one block per (target box, rhs chunk), one thread per core row t.
 // G layout: GT = true -> [core][s][t], false -> [core][t][s].
@@ -1083,6 +1216,19 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     // the whole block)
     const bool box2d = d == 2 && nch == 1 && lm <= 64;
     const size_t sh_box = ((size_t)lm * lm + (size_t)lm * p) * sizeof(T);
+    // 3D boxes up to 8 points per side: whole boxes, several per block
+    const bool small3d = d == 3 && nch == 1 && lm <= 8;
+    int nb3 = 1;
+    size_t sh3 = 0;
+    if (small3d) {
+      const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, p * p * p));
+      const size_t per3 = (size_t)lm * lm * lm + (size_t)lm * lm * p + (size_t)lm * p * p;
+      nb3 = std::max(1, kThreads / S);
+      while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
+      sh3 = nb3 * per3 * sizeof(T);
+      if (sh3 > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
+    }
+    const unsigned g3 = (unsigned)((lv.nbox + nb3 - 1) / nb3);
     // larger 2D boxes: staged rows with each dot split over the block
     const bool rows2d = d == 2 && !box2d && lm >= 128;
     const int Rr = std::max(1, std::min(std::min(rpc, 4096 / lm), kThreads / p));
@@ -1094,7 +1240,10 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
         if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
         uint16_t* W16 = A.ws.W[l].as<uint16_t>();
         { ProfScope ps(A, "up", l, ls);
-        if (box2d)
+        if (small3d)
+          hipLaunchKernelGGL((k_up3d_small<float, uint16_t>), dim3(g3, nrhs), dim3(kThreads), sh3, ls, u, W16, V, 1, n,
+                             lm, lB, p, nrhs, nb3, (int64_t)lv.nbox);
+        else if (box2d)
           hipLaunchKernelGGL((k_up2d_box<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W16, V,
                              1, n, lm, lB, p, nrhs);
         else if (rows2d)
@@ -1124,7 +1273,10 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     } else {
     T* W = A.ws.W[l].as<T>();
     { ProfScope ps(A, "up", l, ls);
-    if (box2d)
+    if (small3d)
+      hipLaunchKernelGGL((k_up3d_small<T, T>), dim3(g3, nrhs), dim3(kThreads), sh3, ls, u, W, V, A.uniform ? 1 : 0,
+                         n, lm, lB, p, nrhs, nb3, (int64_t)lv.nbox);
+    else if (box2d)
       hipLaunchKernelGGL((k_up2d_box<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W, V,
                          A.uniform ? 1 : 0, n, lm, lB, p, nrhs);
     else if (rows2d)
@@ -1275,7 +1427,16 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
     // 256 points (measured faster than the row kernel there), the row kernel
     // for larger boxes
-    if (d == 2 && nch == 1 && lm <= 64) {
+    if (d == 3 && nch == 1 && lm <= 8) {
+      const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, P));
+      const size_t per3 = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
+      int nb3 = std::max(1, kThreads / S);
+      while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
+      if (nb3 * per3 * sizeof(T) > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
+      hipLaunchKernelGGL((k_down3d_small<T>), dim3((unsigned)((lv.nbox + nb3 - 1) / nb3), nrhs), dim3(kThreads),
+                         nb3 * per3 * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p, nrhs, nb3,
+                         (int64_t)lv.nbox);
+    } else if (d == 2 && nch == 1 && lm <= 64) {
       hipLaunchKernelGGL((k_down2d_box<T>), dim3(lv.nbox, nrhs), dim3(kThreads),
                          ((size_t)p * p + (size_t)lm * p) * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p,
                          nrhs);
