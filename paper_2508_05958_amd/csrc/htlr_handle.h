@@ -250,6 +250,10 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
 bool near_rows2d_ok(const htlr_matrix_impl& A, int nrhs, int prec);
 template <typename T>
 void launch_near_rows2d(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st);
+// Near field on uniform 3D grids with a radial kernel and leaves of 4 points per side.
+bool near_rows3d_ok(const htlr_matrix_impl& A, int nrhs, int prec);
+template <typename T>
+void launch_near_rows3d(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st);
 // Work buffers of a product of this shape (handles from htlr_build).
 size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec);
 // f = A u on a handle from htlr_build (work buffers on demand); the caller

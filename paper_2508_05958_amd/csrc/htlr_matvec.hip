@@ -1330,6 +1330,8 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     const T* tab = f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr;
     hipLaunchKernelGGL((k_near_mfma<T>), dim3(nleaf, (nrhs + 15) / 16), dim3(256), sh, st, u, f, a,
                        A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(), tab, A.Tsize, n, B, nrhs);
+  } else if (A.uniform && d == 3 && A.cur.near_kind != 3 && near_rows3d_ok(A, nrhs, prec)) {
+    launch_near_rows3d<T>(A, u, f, nrhs, st);
   } else if (A.uniform && d == 3 && m <= 8) {
     const bool radial = A.kid != HTLR_K_POLY_TEST;
     const T* tab = radial ? (f64 ? (const T*)A.T64.ptr : (const T*)A.T32.ptr) : nullptr;
