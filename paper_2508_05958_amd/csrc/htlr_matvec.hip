@@ -785,7 +785,7 @@ __global__ __launch_bounds__(kThreads) void k_down2d(const T* __restrict__ H, T*
   }
 }
 
-// Up contraction of small 3D boxes (up to 8 points per side) in one pass:
+// Up contraction of small 3D boxes (up to 16 points per side) in one pass:
 // nb boxes per block, each box staged in LDS, then
 //   T1[j2][j1][s0] = sum_j0 V0[j0][s0] X[j2][j1][j0],
 //   T2[j2][s1][s0] = sum_j1 V1[j1][s1] T1[j2][j1][s0],
@@ -852,7 +852,7 @@ __global__ __launch_bounds__(kThreads) void k_up3d_small(const T* __restrict__ u
   }
 }
 
-// Down expansion of small 3D boxes (up to 8 points per side) in one pass:
+// Down expansion of small 3D boxes (up to 16 points per side) in one pass:
 //   Z2[i2][t1][t0] = sum_t2 U2[i2][t2] H[t2][t1][t0],
 //   Z1[i2][i1][t0] = sum_t1 U1[i1][t1] Z2[i2][t1][t0],
 //   f[i2][i1][i0] += sum_t0 U0[i0][t0] Z1[i2][i1][t0]
@@ -1216,17 +1216,17 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     // the whole block)
     const bool box2d = d == 2 && nch == 1 && lm <= 64;
     const size_t sh_box = ((size_t)lm * lm + (size_t)lm * p) * sizeof(T);
-    // 3D boxes up to 8 points per side: whole boxes, several per block
-    const bool small3d = d == 3 && nch == 1 && lm <= 8;
+    // 3D boxes up to 16 points per side whose stages fit in LDS: whole boxes,
+    // several per block when small
+    const size_t per3 = (size_t)lm * lm * lm + (size_t)lm * lm * p + (size_t)lm * p * p;
+    const bool small3d = d == 3 && nch == 1 && lm <= 16 && per3 * sizeof(T) <= kLdsBudget;
     int nb3 = 1;
     size_t sh3 = 0;
     if (small3d) {
       const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, p * p * p));
-      const size_t per3 = (size_t)lm * lm * lm + (size_t)lm * lm * p + (size_t)lm * p * p;
       nb3 = std::max(1, kThreads / S);
       while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
       sh3 = nb3 * per3 * sizeof(T);
-      if (sh3 > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
     }
     const unsigned g3 = (unsigned)((lv.nbox + nb3 - 1) / nb3);
     // larger 2D boxes: staged rows with each dot split over the block
@@ -1429,12 +1429,12 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
     // 256 points (measured faster than the row kernel there), the row kernel
     // for larger boxes
-    if (d == 3 && nch == 1 && lm <= 8) {
+    const size_t per3d = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
+    if (d == 3 && nch == 1 && lm <= 16 && per3d * sizeof(T) <= kLdsBudget) {
       const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, P));
-      const size_t per3 = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
+      const size_t per3 = per3d;
       int nb3 = std::max(1, kThreads / S);
       while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
-      if (nb3 * per3 * sizeof(T) > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
       hipLaunchKernelGGL((k_down3d_small<T>), dim3((unsigned)((lv.nbox + nb3 - 1) / nb3), nrhs), dim3(kThreads),
                          nb3 * per3 * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p, nrhs, nb3,
                          (int64_t)lv.nbox);
