@@ -208,3 +208,23 @@ def test_info_profile_and_errors(torch):
     u = torch.zeros(12 ** 3, dtype=torch.float32, device="cuda")
     with pytest.raises(H.HTLRError):
         M.matvec(u, prec="fp64")
+
+
+def test_autotune_and_qr_form_on_quasi_handle(torch):
+    """htlr_autotune on a transfer-form handle tunes Ahat's products and keeps
+    the result; the build options (here Alg. 4.1's QR step) reach Ahat."""
+    import paper_2508_05958_amd as H
+    _say("[gpu] quasi autotune and QR form")
+    d, n, m = 3, 20, 32
+    nd = _nodes(d, n, "skewed")
+    gq = geometry.tensor_grid(nd)
+    a = 1.0 + 0.5 * gq.points()[:, 0]
+    u = _u(gq, 2, 14)
+    M = H.htlr_build_quasi(np.concatenate(nd), "inv_r", d, n, m, 6, 8, a=a)
+    f0 = _gpu_matvec(torch, M, u)
+    r = M.autotune(2, "fp64")
+    assert r["candidates"] >= 2 and r["ms_best"] <= r["ms_default"] * 1.0001
+    assert _rel(_gpu_matvec(torch, M, u), f0) <= 1e-13
+    Mq = H.htlr_build_quasi(np.concatenate(nd), "inv_r", d, n, m, 6, 8, a=a, orthonormalize="qr")
+    assert Mq.info()["rank"] == 6
+    assert _rel(_gpu_matvec(torch, Mq, u), f0) <= 1e-13
