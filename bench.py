@@ -376,6 +376,37 @@ def quasi_block(H, torch, np, W, steps=10):
               file=sys.stderr, flush=True)
         del f
     A.free()
+    # oversampling sweep (the paper's quasi-uniform experiment varies rho):
+    # the transfer form at m = rho n against the direct HTLR product on the
+    # same warped tensor grid (Def. 3.5, cores made in the product), which
+    # approximates the Nystrom operator at the warped points to the HTLR
+    # accuracy; FP64, u = the smooth u above
+    D = H.htlr_build(np.concatenate(nd), w.kernel, w.d, w.n, w.p, w.leaf, a=w.a(), eta2=w.eta2, precisions=["fp64"])
+    fd = D.matvec(u64, prec="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        D.matvec(u64, fd, prec="fp64")
+    torch.cuda.synchronize()
+    out["direct_tensor_grid_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 4)
+    D.free()
+    sweep = []
+    for m in (w.n, 2 * w.n, 4 * w.n):
+        Q = H.htlr_build_quasi(np.concatenate(nd), w.kernel, w.d, w.n, m, w.p, w.leaf, a=w.a(), eta2=w.eta2,
+                               precisions=["fp64"])
+        fq = Q.matvec(u64, prec="fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            Q.matvec(u64, fq, prec="fp64")
+        torch.cuda.synchronize()
+        sweep.append({"m": m, "rho": m / w.n, "ms_per_product": round((time.perf_counter() - t0) / 5 * 1e3, 4),
+                      "rel_diff_vs_direct": float(torch.linalg.norm(fq - fd) / torch.linalg.norm(fd))})
+        Q.free()
+        del fq
+    out["rho_sweep"] = sweep
+    print("[bench]   rho sweep: " + ", ".join(f"rho {r['rho']:g}: {r['ms_per_product']:.3f} ms, diff {r['rel_diff_vs_direct']:.2e}"
+                                         for r in sweep), file=sys.stderr, flush=True)
     return out
 
 
