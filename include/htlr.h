@@ -256,10 +256,13 @@ htlr_status htlr_profile_enable(htlr_matrix A, int enable);
 htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, int* count);
 
 /* Autotuner: times variants of the product's kernels for products with
- * nrhs right-hand sides in precision prec on this matrix (the split of the
- * core apply's reduction over workgroups, the near-field kernel variant and
- * its waves per leaf), and keeps the fastest for later products of that
- * shape.  With the environment variable HTLR_TUNE_CACHE naming a file, results
+ * nrhs right-hand sides in precision prec on this matrix (the core apply's
+ * matrix-core tile shape, its class-tile or offset-major mode and the split of
+ * its reduction over workgroups; the near-field kernel, its K splits, tiles
+ * per wave and waves per leaf; concurrent or serial level launches), and keeps
+ * the fastest for later products of that shape.  Results are bitwise
+ * independent of the choice for a given kernel family; across families they
+ * agree to rounding.  With the environment variable HTLR_TUNE_CACHE naming a file, results
  * are read from and appended to it, keyed by (d, n, p, leaf, kernel, grid,
  * nrhs, prec).  Allocates scratch vectors; synchronises the device. */
 typedef struct {
