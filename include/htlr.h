@@ -260,9 +260,9 @@ htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, i
  * matrix-core tile shape, its class-tile or offset-major mode and the split of
  * its reduction over workgroups; the near-field kernel, its K splits, tiles
  * per wave and waves per leaf; concurrent or serial level launches), and keeps
- * the fastest for later products of that shape.  Results are bitwise
- * independent of the choice for a given kernel family; across families they
- * agree to rounding.  With the environment variable HTLR_TUNE_CACHE naming a file, results
+ * the fastest for later products of that shape.  The choices change the
+ * order of summation, so results agree to rounding, not bit for bit; a given
+ * choice is deterministic.  With the environment variable HTLR_TUNE_CACHE naming a file, results
  * are read from and appended to it, keyed by (d, n, p, leaf, kernel, grid,
  * nrhs, prec).  Allocates scratch vectors; synchronises the device. */
 typedef struct {
