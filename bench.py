@@ -3,11 +3,16 @@
 
 A step is one HTLR product f = A u (near field + diagonal, up contraction,
 core apply and down expansion on every level) on a matrix already built and
-resident in HBM, with u resident in HBM.  Prints one JSON line.
+resident in HBM, with u resident in HBM.  Prints one compact JSON line on
+stdout; the full record of every block goes to stderr as a line starting
+with "[bench-detail]".
 
-Default workload: d = 3, n = 64 (N = 262,144), k = 1/|x-y|, p = 6, leaf 8^3,
-a = 1, FP64, u ~ N(0,1) (seed 1).  A second block reports the N = 128^3,
-16-right-hand-side workload in FP32 and bfloat16-core precision.
+Headline workload: d = 3, n = 128 (N = 2,097,152), k = 1/|x-y|, p = 8,
+leaf 8^3, a = 1, 16 right-hand sides u ~ N(0,1) (seed 2), FP64.  The same
+products in FP32 and bfloat16-core precision are sub-results with their
+errors against the FP64 product.  Further blocks: the n = 64 FP64 product,
+construction at the paper's table shapes, the QR / QRCP forms, the
+quasi-uniform transfer form, the warped-grid solve and the request server.
 """
 from __future__ import annotations
 
@@ -32,22 +37,31 @@ KERNEL_LABEL = {"inv_r": "1/|x-y|", "neg_log": "-log|x-y|", "exp": "exp(-|x-y|)"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="w3d_invr_n64")
-    ap.add_argument("--prec", default=None, help="fp64 | fp32 | bf16 (default: the workload's)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="w3d_invr_n128_r16")
+    ap.add_argument("--prec", default="fp64", help="fp64 | fp32 | bf16")
+    ap.add_argument("--prof-steps", type=int, default=3,
+                    help="steps of the profiled pass that times each kernel for the roofline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 128^3 mixed-precision block")
-    ap.add_argument("--cpu-leaves", type=int, default=96)
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 / bfloat16-core variants of the headline")
+    ap.add_argument("--no-small", action="store_true", help="skip the n = 64 FP64 block")
+    ap.add_argument("--cpu-leaves", type=int, default=32, help="leaf boxes of the CPU-oracle sample")
+    ap.add_argument("--cpu-procs", type=int, default=16, help="worker processes of the CPU-oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
     ap.add_argument("--no-quasi", action="store_true", help="skip the quasi-uniform transfer block")
     ap.add_argument("--no-orth", action="store_true", help="skip the orthonormal / QRCP forms block")
     ap.add_argument("--serve-requests", type=int, default=160)
-    ap.add_argument("--no-tune", action="store_true", help="time the default kernel variants (no autotuning)")
+    ap.add_argument("--serve-rates", default="0.5",
+                    help="Poisson arrival rates as multiples of the measured capacity, comma separated")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the headline product (otherwise its built-in kernel choices, the ones the "
+                         "full-size parity tests cover)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2508_05958_amd", "tuned_mi355x.txt"),
-                    help="autotuner cache file (HTLR_TUNE_CACHE) used unless that variable is set; its lines are the "
-                         "tuner's own output, so runs of the same shape use the same kernel variants")
+                    help="autotuner cache file (HTLR_TUNE_CACHE) used by the n = 64 block unless that variable is "
+                         "set; its lines are the tuner's own output, so runs of the same shape use the same kernel "
+                         "variants")
     ap.add_argument("--no-tables", action="store_true", help="skip construction at the paper's table shapes")
     ap.add_argument("--serial", action="store_true",
                     help="time the profiled, serially issued product (for kernel-trace runs: every kernel's "
@@ -61,24 +75,49 @@ def parse():
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-out", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-pick", default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
-def algorithmic_work(info, w, nrhs):
-    """Algorithmic flops per launch of each product step (no padding)."""
+def level_shapes(info, w):
+    """(level, boxes per dimension B, box side m) of every level."""
+    return [(l, 2 ** l, w.n // 2 ** l) for l in range(info["levels"] + 1)]
+
+
+def algorithmic_cost(info, w, nrhs, prec):
+    """Per launch of each product step: algorithmic flops (no padding) and
+    algorithmic HBM bytes (each operand read once, each result written
+    once)."""
     P = w.p ** w.d
     M = info["leaf_side"] ** w.d
-    work = {"near": 2.0 * info["near_pairs"] * M * M * nrhs}
-    for l, pairs in enumerate(info["adm_pairs"]):
-        if pairs:
-            work[f"core_l{l}"] = 2.0 * pairs * P * P * nrhs
-    return work
+    ev = 8 if prec == "fp64" else 4                      # vector and work-buffer element
+    eg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]         # core and staged source-tensor element
+    N = w.N
+    cost = {"near": (2.0 * info["near_pairs"] * M * M * nrhs, 2.0 * N * nrhs * ev)}
+    for l, B, m in level_shapes(info, w):
+        pairs = info["adm_pairs"][l]
+        if not pairs:
+            continue
+        nbox = B ** w.d
+        wbytes = nbox * P * nrhs
+        cost[f"up_l{l}"] = (2.0 * nbox * nrhs * sum(m ** (w.d - k) * w.p ** (k + 1) for k in range(w.d)),
+                            N * nrhs * ev + wbytes * eg)
+        cost[f"core_l{l}"] = (2.0 * pairs * P * P * nrhs,
+                              info["unique_cores"][l] * P * P * eg + wbytes * eg + wbytes * ev)
+        cost[f"down_l{l}"] = (2.0 * nbox * nrhs * sum(w.p ** (w.d - k) * m ** (k + 1) for k in range(w.d)),
+                              wbytes * ev + 2.0 * N * nrhs * ev)
+    return cost
 
 
 def peak_for(step, prec):
-    # the near field of these workloads (uniform 3D grid, 8^3-point leaves,
-    # radial kernel) runs on the matrix cores in FP64, or FP32 for the FP32
-    # and bfloat16-core products
+    """(bound, peak TFLOP/s) of a step.  The near field of these workloads
+    (uniform 3D grid, 8^3-point leaves, radial kernel) runs on the matrix
+    cores in FP64, or FP32 for the FP32 and bfloat16-core products; the up
+    and down contractions are bound by HBM."""
+    if step.startswith("up") or step.startswith("down"):
+        return ("hbm", None)
     if step == "near":
         return ("mfma", PEAK["fp64_mfma"] if prec == "fp64" else PEAK["fp32_mfma"])
     return ("mfma", {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16": PEAK["bf16_mfma"]}[prec])
@@ -109,23 +148,28 @@ def traffic_for(workload, prec, step, launches):
     return t["kernels"][key]["hbm_bytes_per_launch"]
 
 
-def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False, serial=False):
-    a = w.a()
-    t0 = time.time()
-    M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=a)
-    torch.cuda.synchronize()
-    build_s = time.time() - t0
+def to_device(torch, u, dt):
+    """Column-major device copy of u ((N,) or (N, nrhs))."""
+    if u.ndim == 2:
+        return torch.tensor(u.T.copy(), dtype=dt, device="cuda").t()
+    return torch.tensor(u, dtype=dt, device="cuda")
+
+
+def run_workload(H, torch, w, prec, steps, warmup, prof_steps=3, tune=False, serial=False, M=None, ut=None):
+    build_s = 0.0
+    if M is None:
+        t0 = time.time()
+        M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=w.a())
+        torch.cuda.synchronize()
+        build_s = time.time() - t0
     info = M.info()
-    u = w.rhs()
+    if ut is None:
+        ut = to_device(torch, w.rhs(), torch.float64 if prec == "fp64" else torch.float32)
+    nrhs = 1 if ut.dim() == 1 else ut.shape[1]
     if tune:
         # kernel variants chosen by timing (the server does this per structure);
         # outside the timed region, like the build
-        M.autotune(1 if u.ndim == 1 else u.shape[1], prec)
-    dt = torch.float64 if prec == "fp64" else torch.float32
-    ut = torch.tensor(u, dtype=dt, device="cuda")
-    if u.ndim == 2:
-        ut = torch.tensor(u.T.copy(), dtype=dt, device="cuda").t()   # column-major N x nrhs
-    nrhs = 1 if u.ndim == 1 else u.shape[1]
+        M.autotune(nrhs, prec)
     if serial:
         M.profile(True)          # every product of this run issued in order, warm-up included
     f = M.matvec(ut, prec=prec)
@@ -143,73 +187,99 @@ def run_workload(H, torch, w, prec, steps, warmup, profile=True, tune=False, ser
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) / steps * 1e3
-    prof = {}
-    if profile:
-        # per-kernel durations: a second timed pass of the same steps with the
-        # profiler on, which issues every launch in order so that each
-        # duration is the kernel's own
-        if not serial:
-            M.profile(True)
-            torch.cuda.synchronize()
-            for _ in range(steps):
-                M.matvec(ut, f, prec=prec)
-            torch.cuda.synchronize()
-        prof = M.profile_read()
+    if not serial:
+        # per-kernel durations: a second pass with the profiler on, which
+        # issues every launch in order so that each duration is the kernel's own
+        M.profile(True)
+        torch.cuda.synchronize()
+        for _ in range(max(1, prof_steps)):
+            M.matvec(ut, f, prec=prec)
+        torch.cuda.synchronize()
+    prof = M.profile_read()
     M.profile(False)
-    return M, info, f, u, nrhs, ms, prof, build_s
+    return M, info, f, nrhs, ms, prof, build_s
 
 
-def roofline(info, w, prec, nrhs, prof, workload):
-    work = algorithmic_work(info, w, nrhs)
+def roofline(info, w, prec, nrhs, prof, ms_meas, workload):
+    """The dominant kernel against its roofline, every kernel's own fraction,
+    and the whole product's T_roof / T_meas, T_roof = sum over steps of
+    max(algorithmic bytes / HBM bandwidth, algorithmic flops / peak)."""
+    cost = algorithmic_cost(info, w, nrhs, prec)
     per = {}
+    t_roof = 0.0
     for step, (launches, total) in prof.items():
         avg = total / max(launches, 1)
-        if step in work:
-            bound, peak = peak_for(step, prec)
-            ach = work[step] / (avg * 1e-3) / 1e12
-            per[step] = {"ms": avg, "bound": bound, "achieved_tflops": ach, "peak_tflops": peak,
-                         "frac": ach / peak}
+        if step not in cost:
+            per[step] = {"ms": round(avg, 4)}
+            continue
+        flops, nbytes = cost[step]
+        bound, peak = peak_for(step, prec)
+        t_mem = nbytes / (HBM_GBS * 1e9) * 1e3
+        if bound == "hbm":
+            gbs = nbytes / (avg * 1e-3) / 1e9
+            per[step] = {"ms": round(avg, 4), "bound": "hbm", "achieved_GBs": round(gbs, 1),
+                         "frac": round(gbs / HBM_GBS, 4)}
+            t_roof += t_mem
         else:
-            per[step] = {"ms": avg}
-    dom = max((s for s in per if s in work), key=lambda s: per[s]["ms"])
+            ach = flops / (avg * 1e-3) / 1e12
+            per[step] = {"ms": round(avg, 4), "bound": bound, "achieved_tflops": round(ach, 2), "peak_tflops": peak,
+                         "frac": round(ach / peak, 4)}
+            t_roof += max(t_mem, flops / (peak * 1e12) * 1e3)
+    mf = [s for s in per if s in cost and per[s]["bound"] != "hbm"]
+    dom = max(mf, key=lambda s: per[s]["ms"])
     d = per[dom]
-    return {"kernel": dom, "bound": d["bound"], "achieved": round(d["achieved_tflops"], 3), "peak": d["peak_tflops"],
-            "unit": "TFLOP/s", "frac": round(d["frac"], 4),
-            "traffic": traffic_for(workload, prec, dom, prof[dom][0]),
-            "work_per_launch_flop": work[dom], "avg_launch_ms": round(d["ms"], 4),
-            "timing": "hipEvents around each launch in a profiled pass of the same steps, launches issued in order"}, per
+    roof = {"bound": d["bound"], "achieved": d["achieved_tflops"], "peak": d["peak_tflops"], "unit": "TFLOP/s",
+            "frac": d["frac"], "traffic": traffic_for(workload, prec, dom, prof[dom][0]),
+            "kernel": dom, "flop_per_launch": cost[dom][0], "avg_launch_ms": d["ms"],
+            "product_frac": round(t_roof / ms_meas, 4), "T_roof_ms": round(t_roof, 3)}
+    return roof, per
 
 
-_ORACLE = {}
-
-
-def _oracle_init(wname):
-    """Worker set-up: the oracle's tree and inputs (not timed)."""
+def cpu_worker(wname, leaves_csv, out):
+    """One process of the CPU baseline: builds the oracle's tree and inputs
+    (not timed), reports ready, waits for "go" on stdin, then computes the
+    oracle rows of its leaf boxes and saves them to ``out``."""
+    import numpy as np
     import htlr_workloads as W
     from oracle import geometry, htlr
     w = W.WORKLOADS[wname]
     g = geometry.uniform_grid(w.d, w.n) if w.grid == "uniform" else geometry.tensor_grid(w.nodes())
-    _ORACLE["O"] = htlr.HTLR(g, w.kernel, w.p, w.leaf, w.a())
-    _ORACLE["u"] = w.rhs()
-
-
-def _oracle_leaf(leaf_index):
-    """CPU oracle rows of one leaf box (runs in a worker process)."""
-    O = _ORACLE["O"]
-    nd = O.tree.leaves()[leaf_index]
+    O = htlr.HTLR(g, w.kernel, w.p, w.leaf, w.a())
+    u = w.rhs()
+    leaves = O.tree.leaves()
+    pick = [leaves[int(i)] for i in leaves_csv.split(",")]
+    print("ready", flush=True)
+    sys.stdin.readline()
     t0 = time.perf_counter()
-    rows = O.matvec(_ORACLE["u"], [nd])
-    return leaf_index, O.leaf_rows([nd]), rows, time.perf_counter() - t0
+    vals = [O.matvec(u, [nd]) for nd in pick]
+    busy = time.perf_counter() - t0
+    np.savez(out, rows=O.leaf_rows(pick), vals=np.concatenate([v.reshape(v.shape[0], -1) for v in vals]),
+             busy=busy)
+    print("done", flush=True)
 
 
-def _noop(_):
-    return 0
+def host_cpu():
+    model = ""
+    try:
+        import subprocess
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return os.cpu_count(), model
 
 
-def cpu_baseline(w, count, f_gpu):
-    """The CPU FP64 HTLR oracle on a seeded sample of leaf boxes, one leaf per
-    task on a pool of host processes; also returns its rows for the error."""
-    import multiprocessing as mp
+def cpu_baseline(w, count, procs, f_gpu):
+    """The CPU FP64 HTLR oracle on a seeded sample of leaf boxes of the
+    workload, spread over worker processes (one BLAS thread each), timed from
+    the moment every worker is initialised; also returns the relative error
+    of the GPU rows against the oracle's.  Each worker is a child process
+    that is waited for, so none outlives the benchmark."""
+    import shutil
+    import subprocess
+    import tempfile
 
     import numpy as np
     import htlr_workloads as W
@@ -217,38 +287,65 @@ def cpu_baseline(w, count, f_gpu):
     while side > w.leaf:
         side //= 2
     nleaves = (w.n // side) ** w.d
-    pick = W.sample_leaves(w.seed, nleaves, count)
-    cores = min(len(pick), os.cpu_count() or 1, 16)
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(cores, initializer=_oracle_init, initargs=(w.name,)) as pool:
-        pool.map(_noop, range(cores), chunksize=1)          # workers up and initialised
+    pick = [int(i) for i in W.sample_leaves(w.seed, nleaves, count)]
+    procs = max(1, min(procs, len(pick), os.cpu_count() or 1))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    tmp = tempfile.mkdtemp(prefix="htlr_cpu_")
+    workers = []
+    try:
+        for k in range(procs):
+            mine = pick[k::procs]
+            out = os.path.join(tmp, f"w{k}.npz")
+            p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", w.name,
+                                  "--cpu-out", out, "--cpu-pick", ",".join(map(str, mine))],
+                                 stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env, cwd=ROOT)
+            workers.append((p, out))
+        for p, _ in workers:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("CPU baseline worker failed to start")
         t0 = time.perf_counter()
-        res = pool.map(_oracle_leaf, [int(i) for i in pick], chunksize=1)
+        for p, _ in workers:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        for p, _ in workers:
+            p.stdout.readline()
+            p.wait()
         wall = time.perf_counter() - t0
-    rows = np.concatenate([r[1] for r in res])
-    vals = np.concatenate([r[2].reshape(len(r[1]), -1) for r in res])
+        res = [np.load(out) for _, out in workers]
+    finally:
+        for p, _ in workers:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
+        shutil.rmtree(tmp, ignore_errors=True)
+    rows = np.concatenate([r["rows"] for r in res])
+    vals = np.concatenate([r["vals"] for r in res])
+    busy = float(sum(r["busy"] for r in res))
     npts = len(rows) * w.nrhs
     fg = f_gpu.reshape(w.N, -1)[rows]
     err = float(np.linalg.norm(fg - vals) / np.linalg.norm(vals))
-    busy = sum(r[3] for r in res)
-    return {"value": npts / wall / 1e9, "unit": "Gpt/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(pick)} seeded leaf boxes ({len(rows)} rows x {w.nrhs} rhs) of {w.name}; plain NumPy "
-                      f"FP64 HTLR product (Alg. 4.2) restricted to those rows, one leaf per task on {cores} "
-                      f"processes: {wall:.1f} s wall, {busy:.1f} s CPU"}, err
+    ncpu, model = host_cpu()
+    return {"value": npts / wall / 1e9, "unit": "Gpt/s", "cores": procs, "kind": "oracle",
+            "sample": f"{len(pick)} seeded leaf boxes of {nleaves} ({len(rows)} rows x {w.nrhs} rhs) of {w.name}: "
+                      f"plain NumPy FP64 HTLR product (Alg. 4.2) restricted to those rows, scaled by the rows "
+                      f"computed; {procs} processes x 1 BLAS thread, {wall:.1f} s wall, {busy:.1f} s CPU",
+            "host_cpus": ncpu, "host_model": model}, err
 
 
 # Construction at the shapes of the paper's Tables 5.1-5.4 (a = 0, FP64):
 # (table, d, kernel, admissibility, p, leaf threshold, n, the paper's
-# printed t_c in s and m_h in GB on its CPU).  Strong admissibility takes
+# printed t_c in s, m_h in GB on its CPU and e_apply;rand).  Strong admissibility takes
 # eta^2 = d, as in Prop. 3.9; the paper's kernels carry constants 1/(2 pi),
 # 1/(4 pi) that do not change relative errors or timings.
 PAPER_SHAPES = [
-    ("5.1", 2, "gauss", "weak", 8, 16, [(256, 1.5, 0.16), (512, 3.8, 0.65), (1024, 16, 2.6), (2048, 68, 10),
-                                        (4096, 280, 41)]),
-    ("5.2", 2, "neg_log", "strong", 8, 16, [(256, 7.6, 1.3), (512, 30, 5.4), (1024, 130, 23), (2048, 540, 92),
-                                            (4096, 2100, 370)]),
-    ("5.3", 3, "gauss", "weak", 4, 5, [(32, 4.0, 0.14), (64, 27, 1.2), (128, 220, 9.2), (256, 1800, 74)]),
-    ("5.4", 3, "inv_r", "strong", 4, 5, [(32, 48, 2.1), (64, 540, 23), (128, 5100, 210)]),
+    ("5.1", 2, "gauss", "weak", 8, 16, [(256, 1.5, 0.16, 1.3e-11), (512, 3.8, 0.65, 2.1e-11), (1024, 16, 2.6, 1.5e-10),
+                                        (2048, 68, 10, 2.0e-11), (4096, 280, 41, 1.8e-11)]),
+    ("5.2", 2, "neg_log", "strong", 8, 16, [(256, 7.6, 1.3, 1.1e-7), (512, 30, 5.4, 8.1e-8), (1024, 130, 23, 1.2e-7),
+                                            (2048, 540, 92, 5.3e-8), (4096, 2100, 370, 4.4e-8)]),
+    ("5.3", 3, "gauss", "weak", 4, 5, [(32, 4.0, 0.14, 2.3e-5), (64, 27, 1.2, 7.4e-6), (128, 220, 9.2, 8.6e-6),
+                                       (256, 1800, 74, 1.2e-5)]),
+    ("5.4", 3, "inv_r", "strong", 4, 5, [(32, 48, 2.1, 1.9e-4), (64, 540, 23, 2.6e-4), (128, 5100, 210, 3.1e-4)]),
 ]
 
 
@@ -259,7 +356,7 @@ def paper_tables_block(H, torch, np):
     H.htlr_build(None, "gauss", 2, 64, 8, 16, a=np.zeros(64 * 64), admissibility="weak").free()   # warm-up
     rows = []
     for table, d, kern, adm, p, leaf, sizes in PAPER_SHAPES:
-        for n, tc_paper, mh_paper in sizes:
+        for n, tc_paper, mh_paper, e_paper in sizes:
             N = n ** d
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -268,8 +365,13 @@ def paper_tables_block(H, torch, np):
             torch.cuda.synchronize()
             tc = time.perf_counter() - t0
             info = M.info()
-            u = torch.randn(N, dtype=torch.float64, device="cuda", generator=None)
+            # e_apply;rand (Sec. 5): relative 2-norm error of the product
+            # against the exact A u on 1000 random rows, u ~ N(0, 1)
+            u = torch.tensor(np.random.default_rng([d, n]).standard_normal(N), device="cuda")
+            rows = np.sort(np.random.default_rng([d, n, 1]).choice(N, size=min(1000, N), replace=False))
             f = M.matvec(u, prec="fp64")
+            ex = M.exact_rows(u, torch.tensor(rows, device="cuda"))
+            e_apply = float(torch.linalg.norm(f[torch.tensor(rows, device="cuda")] - ex) / torch.linalg.norm(ex))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             reps = 3
@@ -280,9 +382,10 @@ def paper_tables_block(H, torch, np):
             rows.append({"table": table, "d": d, "kernel": KERNEL_LABEL[kern], "admissibility": adm, "p": p,
                          "leaf": leaf, "n": n, "N": N, "t_c_s": round(tc, 4),
                          "m_h_GB": round(info["device_bytes"] / 1e9, 4), "matvec_ms": round(ms, 3),
-                         "paper_t_c_s": tc_paper, "paper_m_h_GB": mh_paper})
+                         "e_apply_rand": float(f"{e_apply:.3g}"),
+                         "paper_t_c_s": tc_paper, "paper_m_h_GB": mh_paper, "paper_e_apply_rand": e_paper})
             print(f"[bench]   table {table} n={n}: t_c {tc:.3f} s, {info['device_bytes'] / 1e9:.3f} GB, "
-                  f"matvec {ms:.2f} ms", file=sys.stderr, flush=True)
+                  f"matvec {ms:.2f} ms, e_apply;rand {e_apply:.2e} (paper {e_paper:g})", file=sys.stderr, flush=True)
             M.free()
             del u, f
             torch.cuda.empty_cache()
@@ -449,7 +552,7 @@ def orth_block(H, torch, np, W, steps=10):
     return out
 
 
-def serve_block(H, np, W, count):
+def serve_block(H, np, W, count, rates=(0.5,)):
     """Serving: Poisson arrivals of mixed solve requests (d, n, kernel, p drawn
     per request, f ~ N(0,1), a = 1 + x_1/2, relative residual 1e-8)."""
     A = {}
@@ -515,9 +618,14 @@ def serve_block(H, np, W, count):
         cap = run(S, reqs, fs, [0.0] * count)
         res = {"structures": len(seen), "warm_build_s": round(warm, 2), "capacity": cap}
         if inner == "fp32":
-            rate = 0.5 * cap["solves_per_s"]
-            times = [r.arrival / rate for r in reqs]       # request_stream uses unit rate
-            res["poisson_half_capacity"] = dict(run(S, reqs, fs, times), rate_per_s=round(rate, 3))
+            res["rates"] = []
+            for x in rates:
+                rate = x * cap["solves_per_s"]
+                times = [r.arrival / rate for r in reqs]       # request_stream uses unit rate
+                res["rates"].append(dict(run(S, reqs, fs, times), x_capacity=x, rate_per_s=round(rate, 3)))
+                print(f"[bench]   {x:g} x capacity: {res['rates'][-1]['solves_per_s']} solves/s, "
+                      f"p50 {res['rates'][-1]['p50_latency_s']} s, p99 {res['rates'][-1]['p99_latency_s']} s",
+                      file=sys.stderr, flush=True)
         st = S.stats()
         res["server"] = {k: st[k] for k in ("ticks", "fused_products", "graph_launches", "resident_structures",
                                             "resident_bytes")}
@@ -547,6 +655,29 @@ def summarize_profile(d, command, workload, prec):
     for r in st[:14]:
         lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
                      f"{float(r['TotalDurationNs'])/1e6:.2f} | {float(r['Percentage']):.1f} |")
+    # per launch by position in the product: a serially issued product runs
+    # the levels in ascending order, so the k-th launch of a kernel within
+    # each product is the same level every time (products are counted by the
+    # near-field launches, one per product)
+    tr = rows("stats", "*kernel_trace.csv")
+    skip = ("build", "downcast", "diag", "core_mode", "rocclr")
+    seq = [r for r in sorted(tr, key=lambda r: int(r["Dispatch_Id"]))
+           if "htlr" in r["Kernel_Name"] and not any(x in r["Kernel_Name"] for x in skip)]
+    nprod = sum(1 for r in seq if "k_near" in r["Kernel_Name"] and "reduce" not in r["Kernel_Name"])
+    if nprod:
+        per = {}
+        for r in seq:
+            per.setdefault(short(r["Kernel_Name"]), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines += ["", f"Per launch by position in the product ({nprod} products; levels issued in ascending order):", "",
+                  "| kernel | launch in product | launches | avg us |", "|---|---|---|---|"]
+        for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+            c = len(v) // nprod if len(v) % nprod == 0 else 0
+            if c == 0:
+                lines.append(f"| {k} | all | {len(v)} | {sum(v) / len(v):.1f} |")
+                continue
+            for pos in range(c):
+                w = v[pos::c]
+                lines.append(f"| {k} | {pos + 1} of {c} | {len(w)} | {sum(w) / len(w):.1f} |")
     traffic = {}
     for sub, name in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
         cc = rows(sub, "*counter_collection.csv")
@@ -610,8 +741,15 @@ def summarize_counters(d, command, workload, prec):
     return "\n".join(lines) + "\n"
 
 
+def _short(block, keys):
+    return {k: block[k] for k in keys if k in block}
+
+
 def main():
     args = parse()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker, args.cpu_pick, args.cpu_out)
+        return
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters, args.profile_command, args.workload, args.prec or ""))
         return
@@ -634,19 +772,28 @@ def main():
     import paper_2508_05958_amd as H
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if not os.environ.get("HTLR_TUNE_CACHE") and args.tune_cache and os.path.exists(args.tune_cache):
-        os.environ["HTLR_TUNE_CACHE"] = args.tune_cache
     w = W.WORKLOADS[args.workload]
-    prec = args.prec or ("fp64" if w.nrhs == 1 else "bf16")
+    prec = args.prec
+    # the headline runs the built-in kernel choices unless --tune; the n = 64
+    # block reads the committed tuner cache
+    saved_cache = os.environ.pop("HTLR_TUNE_CACHE", None)
     print(f"[bench] {w.name} {prec}: build + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
-    M, info, f, u, nrhs, ms, prof, build_s = run_workload(H, torch, w, prec, args.steps, args.warmup,
-                                                          tune=not args.no_tune, serial=args.serial)
+    t0 = time.time()
+    M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=w.a())
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    u_host = w.rhs()
+    u64 = to_device(torch, u_host, torch.float64)
+    uh = u64 if prec == "fp64" else u64.float().t().contiguous().t() if u64.dim() == 2 else u64.float()
+    M, info, f, nrhs, ms, prof, _ = run_workload(H, torch, w, prec, args.steps, args.warmup, args.prof_steps,
+                                                 tune=args.tune, serial=args.serial, M=M, ut=uh)
     value = w.N * nrhs / (ms * 1e-3) / 1e9
-    roof, per = roofline(info, w, prec, nrhs, prof, w.name)
-    f_host = f.detach().cpu().numpy()
-    if f_host.ndim == 2:
-        f_host = np.asfortranarray(f_host)
+    roof, per = roofline(info, w, prec, nrhs, prof, ms, w.name)
+    f_ref = f.double() if prec != "fp64" else f
+    f_host = f_ref.detach().cpu().numpy()
+    detail = {"headline": {"workload": w.name, "prec": prec, "ms_per_step": ms, "kernels": per, "roofline": roof,
+                           "build_s": build_s, "device_bytes": info["device_bytes"]}}
     out = {
         "metric": METRIC, "value": round(value, 6), "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
@@ -654,14 +801,37 @@ def main():
         "data": "synthetic (seeded uniform grid, random u)",
         "config": {"workload": w.name, "d": w.d, "n": w.n, "N": w.N, "kernel": KERNEL_LABEL.get(w.kernel, w.kernel),
                    "p": w.p, "leaf": w.leaf, "nrhs": nrhs, "precision": prec, "admissibility": "strong, eta=1",
-                   "parallelism": "1 GPU", "autotuned": not args.no_tune},
-        "build_s": round(build_s, 3), "device_bytes": info["device_bytes"],
-        "tune_cache": os.path.relpath(os.environ["HTLR_TUNE_CACHE"], ROOT) if os.environ.get("HTLR_TUNE_CACHE") else None,
-        "roofline": roof, "kernels": per,
+                   "parallelism": "1 GPU", "autotuned": bool(args.tune)},
+        "build_s": round(build_s, 3),
+        "roofline": roof,
     }
+    if not args.no_extra:
+        # the same products in the other precisions, on the same matrix and u
+        variants = {}
+        u32 = u64.float().t().contiguous().t() if u64.dim() == 2 else u64.float()
+        for pr in ("fp64", "fp32", "bf16"):
+            if pr == prec:
+                continue
+            print(f"[bench] {w.name} {pr}: 5 timed steps", file=sys.stderr, flush=True)
+            _, info3, f3, nr3, ms3, prof3, _ = run_workload(H, torch, w, pr, 5, 1, 2, M=M,
+                                                            ut=u64 if pr == "fp64" else u32)
+            f3d = f3.double()
+            fr = f_ref if prec == "fp64" else f3d
+            err = float(torch.linalg.norm(f3d - fr) / torch.linalg.norm(fr))
+            r3, per3 = roofline(info3, w, pr, nr3, prof3, ms3, w.name)
+            variants[pr] = {"Gpt_s": round(w.N * nr3 / (ms3 * 1e-3) / 1e9, 5), "ms": round(ms3, 3),
+                            "err_vs_fp64": float(f"{err:.3g}"), "kernel": r3["kernel"], "frac": r3["frac"],
+                            "product_frac": r3["product_frac"]}
+            detail[f"headline_{pr}"] = {"ms_per_step": ms3, "kernels": per3, "roofline": r3, "err_vs_fp64": err}
+            del f3, f3d
+        out["variants"] = variants
     M.free()
-    del f
+    del f, f_ref, uh, u64
     torch.cuda.empty_cache()
+    if saved_cache is not None:
+        os.environ["HTLR_TUNE_CACHE"] = saved_cache
+    elif args.tune_cache and os.path.exists(args.tune_cache):
+        os.environ["HTLR_TUNE_CACHE"] = args.tune_cache
     if args.copy_probe_mib:
         # a plain device-to-device copy of known size (the HIP runtime's copy
         # kernel), used to calibrate the FETCH_SIZE / WRITE_SIZE counters
@@ -676,53 +846,68 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nbytes
         del x, y
-    if not args.no_extra:
-        x3 = W.WORKLOADS["w3d_invr_n128_r16"]
-        block = {}
-        print(f"[bench] {x3.name}: fp32 and bf16, 5 timed steps each", file=sys.stderr, flush=True)
-        ref = None
-        for pr in ("fp64", "fp32", "bf16"):
-            M3, info3, f3, u3, nr3, ms3, prof3, b3 = run_workload(H, torch, x3, pr, 2 if pr == "fp64" else 5, 1)
-            fh = f3.detach().double().cpu().numpy()
-            if ref is None:
-                ref = fh
-            err = float(np.linalg.norm(fh - ref) / np.linalg.norm(ref))
-            r3, per3 = roofline(info3, x3, pr, nr3, prof3, x3.name)
-            block[pr] = {"Gpt_s": round(x3.N * nr3 / (ms3 * 1e-3) / 1e9, 5), "ms_per_step": round(ms3, 3),
-                         "rel_err_vs_gpu_fp64": err, "build_s": round(b3, 3), "roofline": r3,
-                         "kernels": {k: round(v["ms"], 3) for k, v in per3.items()}}
-            M3.free()
-            del f3
-            torch.cuda.empty_cache()
-        out["w3d_invr_n128_r16"] = block
+    if not args.no_small:
+        ws = W.WORKLOADS["w3d_invr_n64"]
+        print(f"[bench] {ws.name} fp64 (tuner cache)", file=sys.stderr, flush=True)
+        M2, info2, f2, nr2, ms2, prof2, b2 = run_workload(H, torch, ws, "fp64", 20, 5, 5, tune=True)
+        r2, per2 = roofline(info2, ws, "fp64", nr2, prof2, ms2, ws.name)
+        out[ws.name] = {"Gpt_s": round(ws.N / (ms2 * 1e-3) / 1e9, 5), "ms": round(ms2, 4), "kernel": r2["kernel"],
+                        "frac": r2["frac"], "product_frac": r2["product_frac"]}
+        detail[ws.name] = {"ms_per_step": ms2, "kernels": per2, "roofline": r2}
+        M2.free()
+        del f2
+        torch.cuda.empty_cache()
     if not args.no_tables:
         print("[bench] construction at the paper's table shapes", file=sys.stderr, flush=True)
-        out["paper_tables"] = paper_tables_block(H, torch, np)
+        tb = paper_tables_block(H, torch, np)
+        detail["paper_tables"] = tb
+        out["paper_tables"] = {"rows": len(tb["rows"]),
+                               "t_c_s_max": max(r["t_c_s"] for r in tb["rows"]),
+                               "matvec_ms_max": max(r["matvec_ms"] for r in tb["rows"]),
+                               "e_apply_rand_over_paper_max": round(max(r["e_apply_rand"] / r["paper_e_apply_rand"]
+                                                                        for r in tb["rows"]), 2)}
         torch.cuda.empty_cache()
     if not args.no_orth:
         print("[bench] orthonormal and QRCP-truncated forms (Alg. 4.1 QR step)", file=sys.stderr, flush=True)
-        out["w3d_invr_n64_orth"] = orth_block(H, torch, np, W)
+        ob = orth_block(H, torch, np, W)
+        detail["w3d_invr_n64_orth"] = ob
+        out["orth"] = {k: {"rank": v["rank"], "ms": v["ms_per_product"]} for k, v in ob["forms"].items()}
         torch.cuda.empty_cache()
     if not args.no_quasi:
         print("[bench] quasi-uniform grid through a uniform one (T Ahat S)", file=sys.stderr, flush=True)
-        out["wq2d_log_n512_m1024"] = quasi_block(H, torch, np, W)
+        qb = quasi_block(H, torch, np, W)
+        detail["wq2d_log_n512_m1024"] = qb
+        out["quasi"] = {"fp64_ms": qb["fp64"]["ms_per_product"], "fp32_ms": qb["fp32"]["ms_per_product"],
+                        "Gpt_s_fp64": qb["fp64"]["Gpt_s"], "direct_ms": qb["direct_tensor_grid_ms"]}
         torch.cuda.empty_cache()
     if not args.no_solve:
         print("[bench] warped-grid solve (FP32-IR and FP64 GMRES)", file=sys.stderr, flush=True)
-        out["w3d_exp_warp_n96_solve"] = solve_block(H, torch, np, W)
+        sb = solve_block(H, torch, np, W)
+        detail["w3d_exp_warp_n96_solve"] = sb
+        out["solve"] = {"fp32_ir_s": sb["inner_fp32"]["seconds"], "fp64_s": sb["inner_fp64"]["seconds"],
+                        "solves_per_s": sb["inner_fp32"]["solves_per_s"],
+                        "res": float(f"{sb['inner_fp32']['rel_residual_fp64']:.3g}"),
+                        "err_ustar": float(f"{sb['inner_fp32']['rel_err_vs_ustar']:.3g}")}
         torch.cuda.empty_cache()
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_requests} mixed requests", file=sys.stderr, flush=True)
-        out["serving"] = serve_block(H, np, W, args.serve_requests)
+        vb = serve_block(H, np, W, args.serve_requests, [float(x) for x in args.serve_rates.split(",") if x])
+        detail["serving"] = vb
+        cap = vb["inner_fp32"]["capacity"]
+        out["serving"] = {"requests": vb["requests"], "solves_per_s": cap["solves_per_s"],
+                          "p50_s": cap["p50_latency_s"], "p99_s": cap["p99_latency_s"],
+                          "rates": [_short(r, ("x_capacity", "solves_per_s", "p50_latency_s", "p99_latency_s"))
+                                    for r in vb["inner_fp32"].get("rates", [])]}
         torch.cuda.empty_cache()
     if not args.no_cpu:
-        print(f"[bench] cpu_baseline: oracle on {args.cpu_leaves} leaves", file=sys.stderr, flush=True)
-        cb, err = cpu_baseline(w, args.cpu_leaves, f_host)
+        print(f"[bench] cpu_baseline: oracle on {args.cpu_leaves} leaves of {w.name}", file=sys.stderr, flush=True)
+        cb, err = cpu_baseline(w, args.cpu_leaves, args.cpu_procs, f_host)
         out["cpu_baseline"] = cb
-        out["rel_err_vs_oracle_sampled"] = err
+        out["err_vs_oracle_sampled"] = float(f"{err:.3g}")
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out))
+    print("[bench-detail] " + json.dumps(detail), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -45,6 +45,17 @@ def smooth_u(points: np.ndarray) -> np.ndarray:
     return 1.0 + 0.5 * np.exp(-(x1 - 0.3) ** 2 - (x2 - 0.6) ** 2) + np.sin(5.0 * x1 * x2)
 
 
+def split_edges(nodes: np.ndarray, t: float) -> np.ndarray:
+    """Cell edges 0, x_0 + t (x_1 - x_0), ..., x_{n-2} + t (x_{n-1} - x_{n-2}), 1:
+    each interior edge splits the gap between neighbouring nodes at fraction
+    t (t = 1/2 gives the Voronoi cells)."""
+    x = np.asarray(nodes, dtype=np.float64)
+    e = np.empty(len(x) + 1)
+    e[0], e[-1] = 0.0, 1.0
+    e[1:-1] = x[:-1] + t * (x[1:] - x[:-1])
+    return e
+
+
 def grid_points(nodes_per_dim) -> np.ndarray:
     """All tensor-grid points, shape (N, d), natural order (first index fastest)."""
     d = len(nodes_per_dim)

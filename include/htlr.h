@@ -109,6 +109,20 @@ typedef struct {
                                with admissible leaves)                          */
   double rank_tol;       /* orthonormalize = 2: keep pivots with
                             |R_kk| > rank_tol |R_00|; <= 0 selects 1e-13       */
+  const double* edges;   /* host, d*(n+1) cell edges per dimension, dimension-
+                            major (edges[l*(n+1) + k] = e_{l;k}), or NULL.  The
+                            cells Omega_i of eq. 1.3 are their products: the
+                            quadrature weights |Omega_i|, the diagonal integrals
+                            of eq. 1.4 and the boxes Omega_tau of the cluster
+                            tree (Sec. 2.2, Def. 3.5) follow them.  Each
+                            dimension's edges increase strictly within [0, 1]
+                            and node k lies in [e_{l;k}, e_{l;k+1}], otherwise
+                            HTLR_ERR_INVALID.  NULL: the 1D Voronoi cells
+                            (midpoints between neighbouring nodes, 0 and 1 at
+                            the ends).  The grid takes the uniform path only if
+                            nodes and edges both equal the uniform ones.  Copied
+                            at build; htlr_build_quasi applies them to the
+                            quasi-uniform cells (S and T)                     */
 } htlr_build_opts;
 
 /* Builds the HTLR matrix of the Nystrom operator above (Alg. 4.1).
@@ -116,8 +130,9 @@ typedef struct {
  * points : host, d*n doubles, or NULL.  Node coordinates per dimension,
  *          dimension-major: points[l*n + k] = x_{l;k}, strictly increasing
  *          inside (0, 1).  The grid is their tensor product; cells Omega_i
- *          are the products of the 1D Voronoi cells (midpoints between
- *          neighbouring nodes, 0 and 1 at the ends; Sec. 2.2).  NULL means
+ *          are the products of opts->edges or, by default, of the 1D Voronoi
+ *          cells (midpoints between neighbouring nodes, 0 and 1 at the ends;
+ *          Sec. 2.2).  NULL means
  *          the uniform cell-centred grid x_{l;k} = (k + 1/2)/n (Example 2.2).
  *          A grid whose nodes equal the uniform ones to 1e-14 is treated as
  *          uniform (translation-invariant cores, exact integer geometry).
@@ -190,6 +205,23 @@ htlr_status htlr_workspace_bytes(htlr_matrix A, int nrhs, htlr_precision prec, s
  * issued on one stream at a time. */
 htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_precision prec,
                         htlr_vec_dtype vec_dtype, void* stream);
+
+/* Rows of the uncompressed Nystrom product (eq. 1.3-1.4):
+ *     out_i = (a_i + D_i) u_i + sum_{j != i} k(x_i, x_j) |Omega_j| u_j,
+ * evaluated directly over all N source points in FP64, for measuring the
+ * HTLR approximation error as Sec. 5 does (e_apply;rand, the relative
+ * 2-norm error against the exact A u on randomly chosen rows).
+ *
+ * u      : device, N x nrhs column-major doubles.
+ * rows   : device, nrows int64 row indices in natural order; an index
+ *          outside [0, N) gives NaN in its output rows.
+ * out    : device, nrows x nrhs column-major doubles (out[q + r*nrows] is
+ *          row rows[q] of right-hand side r).
+ * nrhs   : 1..8.
+ * Cost O(nrows N); deterministic.  Transfer-form handles return
+ * HTLR_ERR_UNSUPPORTED. */
+htlr_status htlr_exact_rows(htlr_matrix A, const double* u, const int64_t* rows, int nrows, double* out, int nrhs,
+                            void* stream);
 
 /* Solver options (the paper has no solver: solving A u = f is the
  * "backward evaluation" of Sec. 1).  Restarted GMRES(restart) with x0 = 0 and
@@ -283,8 +315,9 @@ const char* htlr_last_error(void);
 
 /* Host-only planner, for inspection and tests; touches no GPU.
  * Counts the leaves of the block cluster tree (Def. 2.4) for the given grid
- * (points as in htlr_build, may be NULL), per level. */
-htlr_status htlr_plan_counts(const double* points, int d, int n, int leaf, double eta2,
+ * (points and cell edges as in htlr_build and htlr_build_opts.edges, each
+ * may be NULL), per level. */
+htlr_status htlr_plan_counts(const double* points, const double* edges, int d, int n, int leaf, double eta2,
                              int admissibility, int* levels, int64_t* adm_per_level /*[16]*/,
                              int64_t* near_pairs);
 
@@ -293,7 +326,7 @@ htlr_status htlr_plan_counts(const double* points, int d, int n, int leaf, doubl
  * (box multi-index b, linear index b_1 + B b_2 + B^2 b_3, B boxes per
  * dimension).  Writes up to cap pairs into tau[] and sigma[] (host), sorted
  * by (tau, sigma), and the total into *count. */
-htlr_status htlr_plan_pairs(const double* points, int d, int n, int leaf, double eta2,
+htlr_status htlr_plan_pairs(const double* points, const double* edges, int d, int n, int leaf, double eta2,
                             int admissibility, int level, int32_t* tau, int32_t* sigma,
                             int64_t cap, int64_t* count);
 

@@ -32,7 +32,7 @@ from . import kernels
 class Grid:
     """A tensor grid in [0,1]^d with per-dimension nodes and cell edges."""
 
-    def __init__(self, nodes, uniform: bool):
+    def __init__(self, nodes, uniform: bool, edges=None):
         self.d = len(nodes)
         self.nodes = [np.asarray(x, dtype=np.float64) for x in nodes]
         self.n = [len(x) for x in self.nodes]
@@ -42,6 +42,14 @@ class Grid:
             # exact edges k/n, represented as integers k with denominator n
             self.int_edges = [np.arange(m + 1) for m in self.n]
             self.edges = [np.arange(m + 1) / m for m in self.n]
+        elif edges is not None:
+            # cells given by the caller: Omega_i is the product of the 1D
+            # intervals [e_{l;k}, e_{l;k+1}] that hold the nodes (eq. 1.3)
+            self.int_edges = None
+            self.edges = [np.asarray(e, dtype=np.float64) for e in edges]
+            for x, e in zip(self.nodes, self.edges):
+                assert len(e) == len(x) + 1 and np.all(np.diff(e) > 0)
+                assert np.all(e[:-1] <= x) and np.all(x <= e[1:])
         else:
             self.int_edges = None
             self.edges = []
@@ -89,8 +97,11 @@ def uniform_grid(d: int, n: int) -> Grid:
     return Grid([x] * d, uniform=True)
 
 
-def tensor_grid(nodes) -> Grid:
-    return Grid(nodes, uniform=False)
+def tensor_grid(nodes, edges=None) -> Grid:
+    """Tensor grid of the given nodes; cells from ``edges`` (one array of
+    n_l + 1 increasing values per dimension) or, by default, the 1D Voronoi
+    cells (midpoints between neighbouring nodes, 0 and 1 at the ends)."""
+    return Grid(nodes, uniform=False, edges=edges)
 
 
 def default_gl_order(d: int) -> int:

@@ -37,7 +37,8 @@ class HTLRError(RuntimeError):
 class _BuildOpts(ctypes.Structure):
     _fields_ = [("eta2", ctypes.c_double), ("admissibility", ctypes.c_int), ("gl_order", ctypes.c_int),
                 ("a", ctypes.POINTER(ctypes.c_double)), ("precisions", ctypes.c_int),
-                ("orthonormalize", ctypes.c_int), ("rank_tol", ctypes.c_double)]
+                ("orthonormalize", ctypes.c_int), ("rank_tol", ctypes.c_double),
+                ("edges", ctypes.POINTER(ctypes.c_double))]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -91,18 +92,20 @@ def lib() -> ctypes.CDLL:
         L.htlr_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(_SolveOpts),
                                  ctypes.POINTER(_SolveInfo), _vp]
         L.htlr_info.argtypes = [_vp, ctypes.POINTER(_Info)]
+        L.htlr_exact_rows.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp]
         L.htlr_free.argtypes = [_vp]
         L.htlr_free.restype = None
-        L.htlr_plan_counts.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+        L.htlr_plan_counts.argtypes = [_c_dp, _c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64)]
-        L.htlr_plan_pairs.argtypes = [_c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+        L.htlr_plan_pairs.argtypes = [_c_dp, _c_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.htlr_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_TuneResult)]
         L.htlr_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.htlr_profile_read.argtypes = [_vp, ctypes.POINTER(_ProfEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-        for name in ("htlr_build", "htlr_build_quasi", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec", "htlr_solve",
+        for name in ("htlr_build", "htlr_build_quasi", "htlr_footprint", "htlr_workspace_bytes", "htlr_matvec",
+                     "htlr_solve", "htlr_exact_rows",
                      "htlr_info", "htlr_plan_counts", "htlr_plan_pairs", "htlr_profile_enable",
                      "htlr_profile_read", "htlr_autotune"):
             getattr(L, name).restype = ctypes.c_int
@@ -125,7 +128,18 @@ def _points_arg(points, d, n):
 ORTH = {"none": 0, "qr": 1, "qrcp": 2}
 
 
-def _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize=0, rank_tol=0.0):
+def _edges_arg(edges, d, n):
+    if edges is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+    if arr.size != d * (n + 1):
+        raise HTLRError(-1, f"edges must hold d*(n+1) = {d * (n + 1)} values")
+    arr = arr.reshape(d * (n + 1))
+    return arr, arr.ctypes.data_as(_c_dp)
+
+
+def _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize=0, rank_tol=0.0, edges=None):
+    """Build options; returns (options, arrays the options point into)."""
     o = _BuildOpts()
     o.orthonormalize = ORTH[orthonormalize] if isinstance(orthonormalize, str) else int(orthonormalize)
     o.rank_tol = float(rank_tol)
@@ -139,7 +153,11 @@ def _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize=0, rank_t
     if isinstance(precisions, (list, tuple)):
         precisions = sum(1 << PRECISIONS[p] for p in precisions)
     o.precisions = int(precisions)
-    return o, keep
+    keep_e = None
+    if edges is not None:
+        keep_e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64).reshape(-1))
+        o.edges = keep_e.ctypes.data_as(_c_dp)
+    return o, (keep, keep_e)
 
 
 def _stream_ptr(stream):
@@ -164,12 +182,16 @@ class HTLRMatrix:
     diag(a) + T Ahat S, Ahat on the uniform grid of m cells per dimension."""
 
     def __init__(self, points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
-                 a=None, precisions=0, m=None, orthonormalize=0, rank_tol=0.0):
+                 a=None, precisions=0, m=None, orthonormalize=0, rank_tol=0.0, edges=None):
         self.d, self.n, self.p, self.leaf, self.m = d, n, p, leaf, m
         self.N = n ** d
         self.kernel = kernel
+        if a is not None and np.asarray(a).size != self.N:
+            raise HTLRError(-1, f"a must hold {self.N} values (one per grid point)")
         keep_pts, pts = _points_arg(points, d, n)
-        o, keep_a = _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize, rank_tol)
+        if edges is not None:
+            _edges_arg(edges, d, n)
+        o, keep_a = _opts(eta2, admissibility, gl_order, a, precisions, orthonormalize, rank_tol, edges)
         h = _vp()
         kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         if m is None:
@@ -179,20 +201,37 @@ class HTLRMatrix:
         self._h = h
         del keep_pts, keep_a
 
+    def _check_vec(self, x, name, dt, nrhs=None):
+        """x must be a CUDA tensor of dtype dt holding N x nrhs values in the
+        library's layout: (N,) contiguous, or (N, nrhs) column-major."""
+        if not hasattr(x, "is_cuda") or not x.is_cuda or x.dtype != dt:
+            raise HTLRError(-1, f"{name} must be a {dt} CUDA tensor")
+        if x.dim() == 1:
+            ok = x.shape[0] == self.N and x.is_contiguous()
+        elif x.dim() == 2:
+            ok = x.shape[0] == self.N and x.stride(0) == 1 and (x.shape[1] == 1 or x.stride(1) == self.N)
+        else:
+            ok = False
+        if not ok:
+            raise HTLRError(-1, f"{name} must hold {self.N} rows, contiguous (one right-hand side) or column-major "
+                                f"(each right-hand side contiguous)")
+        cols = 1 if x.dim() == 1 else x.shape[1]
+        if nrhs is not None and cols != nrhs:
+            raise HTLRError(-1, f"{name} has {cols} right-hand sides, expected {nrhs}")
+        return cols
+
     def matvec(self, u, f=None, prec="fp64", stream=None):
         """f = A u for device tensors u (N,) or (N, nrhs), column-major for nrhs > 1."""
         import torch
         pr = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
         dt = torch.float64 if pr == 0 else torch.float32
-        if u.dtype != dt or not u.is_cuda:
-            raise HTLRError(-1, f"u must be a {dt} CUDA tensor")
-        nrhs = 1 if u.dim() == 1 else u.shape[1]
-        if u.dim() == 2 and not (u.stride(0) == 1 and u.stride(1) == self.N):
-            raise HTLRError(-1, "u must be column-major (each right-hand side contiguous)")
-        if u.dim() == 1 and not u.is_contiguous():
-            raise HTLRError(-1, "u must be contiguous")
+        nrhs = self._check_vec(u, "u", dt)
         if f is None:
             f = torch.empty_like(u)
+        else:
+            self._check_vec(f, "f", dt, nrhs)
+            if f.data_ptr() == u.data_ptr():
+                raise HTLRError(-1, "f and u must not overlap")
         _check(lib().htlr_matvec(self._h, u.data_ptr(), f.data_ptr(), nrhs, pr,
                                  VEC_F64 if pr == 0 else VEC_F32, _stream_ptr(stream)))
         return f
@@ -200,8 +239,13 @@ class HTLRMatrix:
     def solve(self, f, u=None, tol=1e-10, restart=30, max_outer=20, max_inner=300, inner_prec="fp32",
               inner_tol=0.0, stream=None, check=True):
         import torch
+        self._check_vec(f, "f", torch.float64, 1)
         if u is None:
             u = torch.zeros_like(f)
+        else:
+            self._check_vec(u, "u", torch.float64, 1)
+            if u.data_ptr() == f.data_ptr():
+                raise HTLRError(-1, "f and u must not overlap")
         o = _SolveOpts(tol, restart, max_outer, max_inner,
                        PRECISIONS[inner_prec] if isinstance(inner_prec, str) else int(inner_prec), inner_tol)
         info = _SolveInfo()
@@ -212,6 +256,18 @@ class HTLRMatrix:
         if check:
             _check(st)
         return u, res, st
+
+    def exact_rows(self, u, rows, stream=None):
+        """Rows ``rows`` (int64 CUDA tensor) of the uncompressed Nystrom
+        product A u (eq. 1.3-1.4), FP64; u is (N,) or (N, nrhs) column-major."""
+        import torch
+        nrhs = self._check_vec(u, "u", torch.float64)
+        if not rows.is_cuda or rows.dtype != torch.int64 or rows.dim() != 1 or not rows.is_contiguous():
+            raise HTLRError(-1, "rows must be a contiguous 1-D int64 CUDA tensor")
+        out = torch.empty((nrhs, rows.numel()), dtype=torch.float64, device=u.device).t()
+        _check(lib().htlr_exact_rows(self._h, u.data_ptr(), rows.data_ptr(), rows.numel(), out.data_ptr(), nrhs,
+                                     _stream_ptr(stream)))
+        return out if u.dim() == 2 else out[:, 0]
 
     def info(self) -> dict:
         i = _Info()
@@ -387,33 +443,37 @@ def htlr_build_quasi(points, kernel, d, n, m, p, leaf, **kw) -> HTLRMatrix:
 
 
 def htlr_footprint(points, kernel, d, n, p, leaf, eta2=1.0, admissibility="strong", gl_order=0,
-                   precisions=0, orthonormalize=0, rank_tol=0.0) -> int:
+                   precisions=0, orthonormalize=0, rank_tol=0.0, edges=None) -> int:
     keep_pts, pts = _points_arg(points, d, n)
-    o, _ = _opts(eta2, admissibility, gl_order, None, precisions, orthonormalize, rank_tol)
+    if edges is not None:
+        _edges_arg(edges, d, n)
+    o, keep = _opts(eta2, admissibility, gl_order, None, precisions, orthonormalize, rank_tol, edges)
     b = ctypes.c_size_t()
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     _check(lib().htlr_footprint(pts, kid, d, n, p, leaf, ctypes.byref(o), ctypes.byref(b)))
     return b.value
 
 
-def htlr_plan_counts(points, d, n, leaf, eta2=1.0, admissibility="strong"):
+def htlr_plan_counts(points, d, n, leaf, eta2=1.0, admissibility="strong", edges=None):
     keep, pts = _points_arg(points, d, n)
+    keep_e, e = _edges_arg(edges, d, n)
     L = ctypes.c_int()
     adm = (ctypes.c_int64 * 16)()
     near = ctypes.c_int64()
-    _check(lib().htlr_plan_counts(pts, d, n, leaf, float(eta2), ADM[admissibility], ctypes.byref(L), adm,
+    _check(lib().htlr_plan_counts(pts, e, d, n, leaf, float(eta2), ADM[admissibility], ctypes.byref(L), adm,
                                   ctypes.byref(near)))
     return L.value, list(adm[: L.value + 1]), near.value
 
 
-def htlr_plan_pairs(points, d, n, leaf, level, eta2=1.0, admissibility="strong"):
+def htlr_plan_pairs(points, d, n, leaf, level, eta2=1.0, admissibility="strong", edges=None):
     keep, pts = _points_arg(points, d, n)
+    keep_e, e = _edges_arg(edges, d, n)
     cnt = ctypes.c_int64()
-    _check(lib().htlr_plan_pairs(pts, d, n, leaf, float(eta2), ADM[admissibility], level, None, None, 0,
+    _check(lib().htlr_plan_pairs(pts, e, d, n, leaf, float(eta2), ADM[admissibility], level, None, None, 0,
                                  ctypes.byref(cnt)))
     tau = np.empty(cnt.value, dtype=np.int32)
     sig = np.empty(cnt.value, dtype=np.int32)
-    _check(lib().htlr_plan_pairs(pts, d, n, leaf, float(eta2), ADM[admissibility], level,
+    _check(lib().htlr_plan_pairs(pts, e, d, n, leaf, float(eta2), ADM[admissibility], level,
                                  tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                  sig.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cnt.value, ctypes.byref(cnt)))
     return tau, sig

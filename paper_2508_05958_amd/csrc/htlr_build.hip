@@ -527,7 +527,7 @@ static void init_handle(htlr_matrix_impl& A, const double* points, int kernel, i
                         int leaf, const htlr_build_opts* opts) {
   if (!kernel_known(kernel)) fail(HTLR_ERR_INVALID, "unknown kernel");
   if (p < 1 || p > kMaxP) fail(HTLR_ERR_INVALID, "p out of range (1..12)");
-  A.grid = make_grid(points, d, n);
+  A.grid = make_grid(points, d, n, opts ? opts->edges : nullptr);
   A.d = d;
   A.n = n;
   A.p = p;
@@ -630,11 +630,11 @@ void htlr_free(htlr_matrix A) {
   delete A;
 }
 
-htlr_status htlr_plan_counts(const double* points, int d, int n, int leaf, double eta2, int admissibility,
-                             int* levels, int64_t* adm_per_level, int64_t* near_pairs) {
+htlr_status htlr_plan_counts(const double* points, const double* edges, int d, int n, int leaf, double eta2,
+                             int admissibility, int* levels, int64_t* adm_per_level, int64_t* near_pairs) {
   if (!levels || !adm_per_level || !near_pairs) { g_last_error = "null argument"; return HTLR_ERR_INVALID; }
   return guarded([&] {
-    Grid g = make_grid(points, d, n);
+    Grid g = make_grid(points, d, n, edges);
     Plan pl = make_plan(g, leaf, eta2, admissibility);
     *levels = pl.L;
     for (int l = 0; l < 16; ++l) adm_per_level[l] = l <= pl.L ? pl.adm[l].nnz() : 0;
@@ -642,11 +642,11 @@ htlr_status htlr_plan_counts(const double* points, int d, int n, int leaf, doubl
   });
 }
 
-htlr_status htlr_plan_pairs(const double* points, int d, int n, int leaf, double eta2, int admissibility,
-                            int level, int32_t* tau, int32_t* sigma, int64_t cap, int64_t* count) {
+htlr_status htlr_plan_pairs(const double* points, const double* edges, int d, int n, int leaf, double eta2,
+                            int admissibility, int level, int32_t* tau, int32_t* sigma, int64_t cap, int64_t* count) {
   if (!count) { g_last_error = "null argument"; return HTLR_ERR_INVALID; }
   return guarded([&] {
-    Grid g = make_grid(points, d, n);
+    Grid g = make_grid(points, d, n, edges);
     Plan pl = make_plan(g, leaf, eta2, admissibility);
     if (level > pl.L) fail(HTLR_ERR_INVALID, "level beyond the tree depth");
     const Csr& c = level >= 0 ? pl.adm[level] : pl.near;

@@ -354,6 +354,20 @@ bool core_mfma_ok(const htlr_matrix_impl& A, int prec) {
 }
 
 // Work lists for tiles of nb boxes of one parity class, built on first use.
+//
+// A tile computes every offset of the union of its members' lists; a member
+// for which an offset leaves the domain contributes a zero column there.
+// Near the domain boundary the lists differ (at level 4 of a 16^3 grid only
+// 27 of a class's 512 boxes have the full list), so the members of a tile
+// are chosen in two passes.  Boxes with identical lists fill whole tiles in
+// Morton order (no padding); the remaining boxes are grouped greedily: seed
+// with the unassigned box with the longest list, then repeatedly add the box
+// that adds the fewest offsets to the union (ties: longer list first, then
+// Morton order).  On the 128^3 level-4 lists this cuts the padded work from
+// 1.19x to 1.10x the useful work at 8 boxes per tile, and from 1.33x to
+// 1.17x at 16 (level 3, where every box is near the boundary, stays at 1.48x
+// at 8).  Tiles are then ordered by their first box's Morton code, so that
+// consecutive tiles are spatial neighbours.
 static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
   for (auto& t : lv.tiles)
     if (t.nb == nb) return t;
@@ -366,32 +380,98 @@ static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
   std::map<std::array<int, 3>, int> cid;
   for (int c = 0; c < lv.ncore; ++c)
     cid[{lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]}] = c;
+  const int words = (lv.ncore + 63) / 64;
   const int ncls = 1 << d;
   std::vector<int64_t> class_start{0};
   int64_t maxlist = 0;
   for (int cls = 0; cls < ncls; ++cls) {
-    std::vector<std::pair<uint64_t, int32_t>> boxes;
+    // boxes of the class, each with its offsets as a bit set over core ids
+    std::vector<int32_t> boxes;
     for (int64_t t = 0; t < lv.nbox; ++t) {
       int x = (int)(t % B), y = (int)((t / B) % B), z = (int)(t / ((int64_t)B * B));
       int c = (x & 1) | ((y & 1) << 1) | (d == 3 ? ((z & 1) << 2) : 0);
-      if (c != cls) continue;
-      boxes.push_back({morton3(x >> 1, y >> 1, z >> 1), (int32_t)t});
+      if (c == cls) boxes.push_back((int32_t)t);
     }
-    std::sort(boxes.begin(), boxes.end());
-    for (size_t s = 0; s < boxes.size(); s += nb) {
-      std::set<std::array<int, 3>> offs;
-      std::vector<int32_t> members;
-      for (size_t q = s; q < std::min(boxes.size(), s + (size_t)nb); ++q) {
-        int64_t t = boxes[q].second;
-        members.push_back((int32_t)t);
-        int tx = (int)(t % B), ty = (int)((t / B) % B), tz = (int)(t / ((int64_t)B * B));
-        for (int64_t e = cs.ptr[t]; e < cs.ptr[t + 1]; ++e) {
-          int64_t sg = cs.src[e];
-          offs.insert({(int)(sg % B) - tx, (int)((sg / B) % B) - ty, (int)(sg / ((int64_t)B * B)) - tz});
-        }
+    const size_t nbx = boxes.size();
+    std::vector<uint64_t> bits(nbx * words, 0);
+    std::vector<int> len(nbx, 0);
+    std::vector<uint64_t> mort(nbx);
+    for (size_t q = 0; q < nbx; ++q) {
+      const int64_t t = boxes[q];
+      const int tx = (int)(t % B), ty = (int)((t / B) % B), tz = (int)(t / ((int64_t)B * B));
+      mort[q] = morton3(tx >> 1, ty >> 1, tz >> 1);
+      for (int64_t e = cs.ptr[t]; e < cs.ptr[t + 1]; ++e) {
+        const int64_t sg = cs.src[e];
+        const int c = cid.at({(int)(sg % B) - tx, (int)((sg / B) % B) - ty, (int)(sg / ((int64_t)B * B)) - tz});
+        bits[q * words + c / 64] |= (uint64_t)1 << (c % 64);
       }
+      len[q] = (int)(cs.ptr[t + 1] - cs.ptr[t]);
+    }
+    // boxes with identical lists first: full tiles in Morton order, no padding
+    std::vector<size_t> order(nbx);
+    for (size_t q = 0; q < nbx; ++q) order[q] = q;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      for (int w = 0; w < words; ++w)
+        if (bits[a * words + w] != bits[b * words + w]) return bits[a * words + w] < bits[b * words + w];
+      return mort[a] < mort[b];
+    });
+    std::vector<std::pair<uint64_t, std::vector<size_t>>> groups;
+    std::vector<char> used(nbx, 0);
+    size_t done = 0;
+    for (size_t i = 0; i < nbx;) {
+      size_t j = i + 1;
+      while (j < nbx && std::equal(&bits[order[i] * words], &bits[order[i] * words] + words, &bits[order[j] * words]))
+        ++j;
+      for (size_t k = i; k + nb <= j; k += nb) {
+        std::vector<size_t> g(order.begin() + k, order.begin() + k + nb);
+        for (size_t q : g) used[q] = 1;
+        done += nb;
+        groups.push_back({mort[g[0]], g});
+      }
+      i = j;
+    }
+    // the rest greedily
+    std::vector<uint64_t> uni(words);
+    while (done < nbx) {
+      size_t seed = nbx;
+      for (size_t q = 0; q < nbx; ++q)
+        if (!used[q] && (seed == nbx || len[q] > len[seed] || (len[q] == len[seed] && mort[q] < mort[seed]))) seed = q;
+      std::vector<size_t> g{seed};
+      used[seed] = 1;
+      ++done;
+      for (int w = 0; w < words; ++w) uni[w] = bits[seed * words + w];
+      while ((int)g.size() < nb && done < nbx) {
+        size_t best = nbx;
+        int best_add = 0;
+        for (size_t q = 0; q < nbx; ++q) {
+          if (used[q]) continue;
+          int add = 0;
+          for (int w = 0; w < words; ++w) add += __builtin_popcountll(bits[q * words + w] & ~uni[w]);
+          if (best == nbx || add < best_add || (add == best_add && (len[q] > len[best] ||
+                                                                      (len[q] == len[best] && mort[q] < mort[best])))) {
+            best = q;
+            best_add = add;
+          }
+        }
+        g.push_back(best);
+        used[best] = 1;
+        ++done;
+        for (int w = 0; w < words; ++w) uni[w] |= bits[best * words + w];
+      }
+      groups.push_back({mort[seed], g});
+    }
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (auto& gr : groups) {
+      std::vector<uint64_t> u(words, 0);
+      for (size_t q : gr.second)
+        for (int w = 0; w < words; ++w) u[w] |= bits[q * words + w];
+      std::set<std::array<int, 3>> offs;
+      for (int c = 0; c < lv.ncore; ++c)
+        if (u[c / 64] >> (c % 64) & 1) offs.insert({lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]});
       // every member's own list must equal the tile list restricted to the domain
-      for (int32_t t : members) {
+      for (size_t q : gr.second) {
+        const int32_t t = boxes[q];
         int tx = t % B, ty = (t / B) % B, tz = t / (B * B);
         int64_t inside = 0;
         for (auto& o : offs) {
@@ -401,7 +481,7 @@ static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
         if (inside != cs.ptr[t + 1] - cs.ptr[t])
           fail(HTLR_ERR_UNSUPPORTED, "admissible offsets differ inside a parity class");
       }
-      for (int q = 0; q < nb; ++q) tau.push_back(q < (int)members.size() ? members[q] : -1);
+      for (int q = 0; q < nb; ++q) tau.push_back(q < (int)gr.second.size() ? boxes[gr.second[q]] : -1);
       for (auto& o : offs) off.push_back(make_int4(cid.at(o), o[0], o[1], o[2]));
       ptr.push_back((int64_t)off.size());
       maxlist = std::max<int64_t>(maxlist, (int64_t)offs.size());
@@ -481,18 +561,25 @@ static int pick_ksplit(int64_t base_wgs, int64_t max_list, int target) {
   return ks;
 }
 
-static LevelData::Tiles::Items& items_for(LevelData::Tiles& T, int ks, int nmb, bool frozen) {
-  const int key = ks + 64 * nmb;
+static LevelData::Tiles::Items& items_for(LevelData::Tiles& T, int ks, int nmb, int order, bool frozen) {
+  const int key = ks + 64 * nmb + 4096 * order;
   auto it = T.items.find(key);
   if (it != T.items.end()) return it->second;
   if (frozen) fail(HTLR_ERR_INVALID, "matrix-core work list not reserved");
-  // work items ordered (class, row block, split, tile)
+  // work items ordered (class, row block, split, tile) or (class, tile, row block, split)
   std::vector<int32_t> items;
-  for (size_t cl = 0; cl + 1 < T.class_start.size(); ++cl)
-    for (int mb = 0; mb < nmb; ++mb)
-      for (int s = 0; s < ks; ++s)
-        for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
-          items.push_back((int32_t)((t << 12) | (mb << 6) | s));
+  for (size_t cl = 0; cl + 1 < T.class_start.size(); ++cl) {
+    if (order == 1) {
+      for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
+        for (int mb = 0; mb < nmb; ++mb)
+          for (int s = 0; s < ks; ++s) items.push_back((int32_t)((t << 12) | (mb << 6) | s));
+    } else {
+      for (int mb = 0; mb < nmb; ++mb)
+        for (int s = 0; s < ks; ++s)
+          for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
+            items.push_back((int32_t)((t << 12) | (mb << 6) | s));
+    }
+  }
   LevelData::Tiles::Items& I = T.items[key];
   I.buf.alloc(items.size() * sizeof(int32_t));
   HTLR_HIP(hipMemcpy(I.buf.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -698,7 +785,7 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   const int nmb = (A.P + bmt - 1) / bmt;
   const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
   if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
-  LevelData::Tiles::Items& I = items_for(T, ks, nmb, A.ws.frozen);
+  LevelData::Tiles::Items& I = items_for(T, ks, nmb, A.cur.order, A.ws.frozen);
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
   const int64_t helems = lv.nbox * (int64_t)nrhs * A.P;
   void* Hout = H;
@@ -781,7 +868,7 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
         if (T.ntile == 0) continue;
         const int nmb = (A.P + bmt - 1) / bmt;
         const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
-        items_for(T, ks, nmb, false);
+        items_for(T, ks, nmb, A.cur.order, false);
         if (ks > 1) parts_need[l] = std::max(parts_need[l], (size_t)lv.nbox * c * A.P * ks * esz);
       }
     }

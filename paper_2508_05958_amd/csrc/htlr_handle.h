@@ -141,6 +141,9 @@ struct TuneParams {
                                      // 4 224x64 (FP64), 5 256x256 (BF16), 6 64x128, 7 64x64
   int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
   int serial = 0;                    // 1: every launch on the caller's stream (no level concurrency)
+  int order = 0;                     // matrix-core work items: 0 (class, row block, split, tile),
+                                     // 1 (class, tile, row block, split): the row blocks of a tile
+                                     // run side by side and share its gathered source tensors in L2
 };
 
 // Groups of target leaves for the leaf-column near kernel: lpc leaves per
@@ -209,7 +212,8 @@ struct ProfScope {
   hipStream_t st;
   bool on;
   Profiler::Rec rec;
-  ProfScope(htlr_matrix_impl& A, const char* name, int level, hipStream_t s) : p(A.prof), st(s), on(A.prof.on) {
+  ProfScope(htlr_matrix_impl& A, const char* name, int level, hipStream_t s, bool enable = true)
+      : p(A.prof), st(s), on(A.prof.on && enable) {
     if (!on) return;
     rec.name = level >= 0 ? std::string(name) + "_l" + std::to_string(level) : std::string(name);
     rec.a = p.get();

@@ -31,7 +31,11 @@ struct Grid {
   std::vector<double> w;          // d*n cell lengths, w[l*n + k]
 };
 
-Grid make_grid(const double* points, int d, int n);
+// The tensor grid of the nodes (NULL: uniform cell centres) and its cells:
+// the caller's edges (d*(n+1), dimension-major) or, with NULL, the 1D Voronoi
+// cells (midpoints, 0 and 1 at the ends).  Uniform when nodes and cells equal
+// the uniform ones to 1e-14.
+Grid make_grid(const double* points, int d, int n, const double* edges = nullptr);
 
 // Per-level block lists in CSR form over target boxes: the leaves of the
 // block cluster tree (Def. 2.4) at one level of the cluster tree.

@@ -1167,11 +1167,28 @@ TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
   return best;
 }
 
+// Work buffers of one product: per level the source tensors W, the core
+// apply's outputs H and the partial up contractions UP, plus the zero source
+// tensor of the matrix-core kernel.  noalloc: the buffers live in the
+// library's static scratch array, and the product takes only kernels that
+// need no lazily built work lists, side streams or profiler events (the CSR
+// core apply, near-field kernels without K-split partial sums), with the
+// built-in choices and every launch on the caller's stream.
+struct WorkView {
+  void* W[kMaxLevels] = {};
+  void* H[kMaxLevels] = {};
+  void* UP[kMaxLevels] = {};
+  const void* zero = nullptr;
+  bool noalloc = false;
+};
+
 template <typename T>
-static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st) {
+static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st,
+                       const WorkView& wv) {
   // p: Tucker rank of the stored factors; pm1: degree of the polynomial test kernel
   const int d = A.d, p = A.rank, P = A.P, n = A.n, pm1 = A.p - 1;
-  A.cur = find_tune(A, nrhs, prec);
+  A.cur = wv.noalloc ? TuneParams{} : find_tune(A, nrhs, prec);
+  const bool prof = !wv.noalloc;
   const bool f64 = std::is_same<T, double>::value;
   const Plan& pl = A.plan;
   const int m = pl.m[A.L], B = pl.B[A.L];
@@ -1189,7 +1206,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   for (LevelData& lv : A.levels)
     if (lv.npairs > 0) act.push_back(&lv);
   // (serial while profiling: each recorded duration is then one launch's alone)
-  const bool fork = A.cur.serial == 0 && !A.prof.on && !act.empty();
+  const bool fork = !wv.noalloc && A.cur.serial == 0 && !A.prof.on && !act.empty();
   const std::vector<hipStream_t>* side = fork ? &side_streams(A) : nullptr;
   if (fork) {
     HTLR_HIP(hipEventRecord(A.ev_fork, st));
@@ -1202,7 +1219,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     const int l = lv.level, lm = lv.m, lB = lv.B;
     const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
     const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
-    T* H = A.ws.H[l].as<T>();
+    T* H = (T*)wv.H[l];
     // 3D: rows of a slice staged at a time, as many as the LDS budget allows
     const int up_rows = d == 3 ? (int)std::max<int64_t>(1, std::min<int64_t>(lm, ((int64_t)(kLdsBudget / sizeof(T)) -
                                                          (int64_t)p * lm - (int64_t)p * p) / lm)) : 0;
@@ -1210,7 +1227,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
                                  : (size_t)lm + (size_t)kThreads + (size_t)p) * sizeof(T);
     if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
     const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
-    T* upart = nch > 1 ? A.ws.UP[l].as<T>() : nullptr;
+    T* upart = nch > 1 ? (T*)wv.UP[l] : nullptr;
     // 2D boxes up to 64 points per side: one block contracts the whole box
     // (larger boxes keep the row kernel, which spreads each row's dots over
     // the whole block)
@@ -1238,8 +1255,8 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
       if constexpr (!std::is_same<T, double>::value) {
         if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
         if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
-        uint16_t* W16 = A.ws.W[l].as<uint16_t>();
-        { ProfScope ps(A, "up", l, ls);
+        uint16_t* W16 = (uint16_t*)wv.W[l];
+        { ProfScope ps(A, "up", l, ls, prof);
         if (small3d)
           hipLaunchKernelGGL((k_up3d_small<float, uint16_t>), dim3(g3, nrhs), dim3(kThreads), sh3, ls, u, W16, V, 1, n,
                              lm, lB, p, nrhs, nb3, (int64_t)lv.nbox);
@@ -1256,9 +1273,9 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
           hipLaunchKernelGGL((k_up_reduce<float, uint16_t>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)),
                              dim3(256), 0, ls, (const float*)upart, W16, wcount, nch);
         HTLR_HIP(hipGetLastError()); }
-        ProfScope ps(A, "core", l, ls);
-        if (core_mfma_ok(A, prec)) {
-          launch_core_mfma(A, lv, prec, W16, H, A.ws.zero.ptr, nrhs, ls);
+        ProfScope ps(A, "core", l, ls, prof);
+        if (!wv.noalloc && core_mfma_ok(A, prec)) {
+          launch_core_mfma(A, lv, prec, W16, H, wv.zero, nrhs, ls);
         } else {
         const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
         const int nchunk = (nrhs + rc - 1) / rc;
@@ -1271,8 +1288,8 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
         }
       }
     } else {
-    T* W = A.ws.W[l].as<T>();
-    { ProfScope ps(A, "up", l, ls);
+    T* W = (T*)wv.W[l];
+    { ProfScope ps(A, "up", l, ls, prof);
     if (small3d)
       hipLaunchKernelGGL((k_up3d_small<T, T>), dim3(g3, nrhs), dim3(kThreads), sh3, ls, u, W, V, A.uniform ? 1 : 0,
                          n, lm, lB, p, nrhs, nb3, (int64_t)lv.nbox);
@@ -1289,9 +1306,9 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
       hipLaunchKernelGGL((k_up_reduce<T, T>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)), dim3(256), 0,
                          ls, (const T*)upart, W, wcount, nch);
     HTLR_HIP(hipGetLastError()); }
-    ProfScope ps(A, "core", l, ls);
-    if (A.uniform && core_mfma_ok(A, prec)) {
-      launch_core_mfma(A, lv, prec, W, H, A.ws.zero.ptr, nrhs, ls);
+    ProfScope ps(A, "core", l, ls, prof);
+    if (A.uniform && !wv.noalloc && core_mfma_ok(A, prec)) {
+      launch_core_mfma(A, lv, prec, W, H, wv.zero, nrhs, ls);
     } else if (A.uniform) {
       const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
       if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
@@ -1317,10 +1334,10 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
 
   // near field + diagonal (overwrites f)
   {
-  ProfScope ps(A, "near", -1, st);
+  ProfScope ps(A, "near", -1, st, prof);
   const bool mfma_ok = A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST &&
                        (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T) <= kLdsBudget;
-  const bool near_leaves = use_near_leaves(A, nrhs, prec, A.ws.frozen);
+  const bool near_leaves = !wv.noalloc && use_near_leaves(A, nrhs, prec, A.ws.frozen);
   const bool near_mfma = !near_leaves && mfma_ok &&
                          (A.cur.near_kind == 1 || A.cur.near_kind == 2 || (A.cur.near_kind < 0 && nrhs >= 8));
   if (near_leaves) {
@@ -1420,12 +1437,12 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
     LevelData& lv = *act[li];
     const int l = lv.level, lm = lv.m, lB = lv.B;
     const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
-    T* H = A.ws.H[l].as<T>();
+    T* H = (T*)wv.H[l];
     if (fork) HTLR_HIP(hipStreamWaitEvent(st, A.ev_level[li], 0));
     const size_t sh_dn = ((size_t)P + (d == 3 ? (size_t)p * p + (size_t)lm * p : (size_t)p)) * sizeof(T);
     if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
     const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
-    ProfScope ps(A, "down", l, st);
+    ProfScope ps(A, "down", l, st, prof);
     // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
     // 256 points (measured faster than the row kernel there), the row kernel
     // for larger boxes
@@ -1456,9 +1473,18 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
 
 void product(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st) {
   ensure_workspace(A, nrhs, prec);
-  if (prec == HTLR_FP64) run_matvec<double>(A, (const double*)u, (double*)f, nrhs, prec, st);
-  else run_matvec<float>(A, (const float*)u, (float*)f, nrhs, prec, st);
+  WorkView wv;
+  for (const LevelData& lv : A.levels) {
+    if (lv.npairs == 0) continue;
+    wv.W[lv.level] = A.ws.W[lv.level].ptr;
+    wv.H[lv.level] = A.ws.H[lv.level].ptr;
+    wv.UP[lv.level] = A.ws.UP[lv.level].ptr;
+  }
+  wv.zero = A.ws.zero.ptr;
+  if (prec == HTLR_FP64) run_matvec<double>(A, (const double*)u, (double*)f, nrhs, prec, st, wv);
+  else run_matvec<float>(A, (const float*)u, (float*)f, nrhs, prec, st, wv);
 }
+
 
 }  // namespace htlr
 
@@ -1533,15 +1559,18 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         double md = 0, mb = 0;
         bool found = false;
         // key ks_target near_kind near_nw tile core_mode near_ks near_tpw near_ct serial ms_default ms_best
-        while (std::fgets(line, sizeof(line), fp))
-          if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %lf %lf", k2, &t.ks_target, &t.near_kind,
-                          &t.near_nw, &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw, &t.near_ct, &t.serial, &md,
-                          &mb) == 12 &&
-              std::strcmp(k2, key) == 0) {
+        // [order] (lines without the last field take order 0)
+        while (std::fgets(line, sizeof(line), fp)) {
+          t.order = 0;
+          const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %lf %lf %d", k2, &t.ks_target,
+                                      &t.near_kind, &t.near_nw, &t.tile, &t.core_mode, &t.near_ks, &t.near_tpw,
+                                      &t.near_ct, &t.serial, &md, &mb, &t.order);
+          if ((got == 12 || got == 13) && std::strcmp(k2, key) == 0) {
             A->tune[{nrhs, (int)prec}] = t;
             res = htlr_tune_result{t.ks_target, t.near_kind, t.near_nw, 0, md, mb};
             found = true;
           }
+        }
         std::fclose(fp);
         if (found) {
           if (out) *out = res;
@@ -1575,10 +1604,7 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
       A->tune[{nrhs, (int)prec}] = t;
       std::lock_guard<std::mutex> lk(A->ws_mu);
       ensure_workspace(*A, nrhs, prec);
-      auto once = [&]() {
-        if (prec == HTLR_FP64) run_matvec<double>(*A, u.as<double>(), f.as<double>(), nrhs, prec, st);
-        else run_matvec<float>(*A, u.as<float>(), f.as<float>(), nrhs, prec, st);
-      };
+      auto once = [&]() { product(*A, u.ptr, f.ptr, nrhs, prec, st); };
       once();   // warm-up (work lists, buffers)
       float best = 1e30f;
       for (int r = 0; r < 3; ++r) {
@@ -1612,6 +1638,12 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
       for (int target : {512, 1024, 4096, 8192}) {
         TuneParams t = best;
         t.ks_target = target;
+        const double ms = time_with(t);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+      }
+      {
+        TuneParams t = best;
+        t.order = 1;
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
@@ -1671,9 +1703,9 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "a");
       if (fp) {
-        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d %.6f %.6f\n", key, best.ks_target, best.near_kind,
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d %.6f %.6f %d\n", key, best.ks_target, best.near_kind,
                      best.near_nw, best.tile, best.core_mode, best.near_ks, best.near_tpw, best.near_ct, best.serial,
-                     res.ms_default, best_ms);
+                     res.ms_default, best_ms, best.order);
         std::fclose(fp);
       }
     }

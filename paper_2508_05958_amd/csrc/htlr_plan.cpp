@@ -22,7 +22,7 @@
 
 namespace htlr {
 
-Grid make_grid(const double* points, int d, int n) {
+Grid make_grid(const double* points, int d, int n, const double* edges) {
   if (d != 2 && d != 3) fail(HTLR_ERR_UNSUPPORTED, "d must be 2 or 3");
   if (n < 1 || n > (1 << 15)) fail(HTLR_ERR_INVALID, "n out of range");
   Grid g;
@@ -42,6 +42,21 @@ Grid make_grid(const double* points, int d, int n) {
       g.x[(size_t)l * n + k] = v;
     }
   }
+  if (edges) {
+    // caller's cells: every node inside its cell, cells increasing within [0, 1]
+    for (int l = 0; l < d; ++l) {
+      const double* e = edges + (size_t)l * (n + 1);
+      for (int k = 0; k <= n; ++k) {
+        if (!std::isfinite(e[k]) || e[k] < 0.0 || e[k] > 1.0) fail(HTLR_ERR_INVALID, "cell edge outside [0,1]");
+        if (k > 0 && !(e[k] > e[k - 1])) fail(HTLR_ERR_INVALID, "cell edges not increasing");
+        if (std::fabs(e[k] - (double)k / n) > 1e-14) uniform = false;
+      }
+      for (int k = 0; k < n; ++k) {
+        const double x = g.x[(size_t)l * n + k];
+        if (x < e[k] || x > e[k + 1]) fail(HTLR_ERR_INVALID, "node outside its cell");
+      }
+    }
+  }
   g.uniform = uniform;
   for (int l = 0; l < d; ++l) {
     double* e = &g.e[(size_t)l * (n + 1)];
@@ -49,6 +64,8 @@ Grid make_grid(const double* points, int d, int n) {
     if (uniform) {
       for (int k = 0; k <= n; ++k) e[k] = (double)k / n;
       for (int k = 0; k < n; ++k) g.x[(size_t)l * n + k] = (k + 0.5) / n;
+    } else if (edges) {
+      for (int k = 0; k <= n; ++k) e[k] = edges[(size_t)l * (n + 1) + k];
     } else {
       e[0] = 0.0;
       e[n] = 1.0;

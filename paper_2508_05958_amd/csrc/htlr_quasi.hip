@@ -232,7 +232,7 @@ htlr_status htlr_build_quasi(const double* points, htlr_kernel kernel, int d, in
   htlr_matrix_s* A = nullptr;
   try {
     g_last_error.clear();
-    const Grid g = make_grid(points, d, n);
+    const Grid g = make_grid(points, d, n, opts ? opts->edges : nullptr);
     if (m < 1 || m > (1 << 15)) fail(HTLR_ERR_INVALID, "m out of range");
     auto Q = std::make_shared<QuasiData>();
     Q->m = m;
@@ -242,6 +242,7 @@ htlr_status htlr_build_quasi(const double* points, htlr_kernel kernel, int d, in
     htlr_build_opts io{};
     if (opts) io = *opts;
     io.a = nullptr;
+    io.edges = nullptr;    // Ahat lives on the uniform grid of m cells
     const htlr_status bs = htlr_build(nullptr, kernel, d, m, p, leaf, &io, &Q->inner);
     if (bs != HTLR_OK) fail(bs, "uniform grid of the transfer: " + g_last_error);
     const htlr_matrix_impl& I = *Q->inner;

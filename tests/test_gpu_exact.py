@@ -1,0 +1,74 @@
+"""GPU rows of the uncompressed Nystrom product (htlr_exact_rows) against
+the dense oracle O1 (eq. 1.3-1.4) on sampled rows: the reference the
+benchmark's e_apply;rand (Sec. 5) is measured against."""
+import sys
+
+import numpy as np
+import pytest
+
+import htlr_workloads as W
+from oracle import dense, geometry
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+CASES = [
+    # d, n, p, kernel, grid, nrhs, edges split (0 = Voronoi)
+    (2, 64, 6, "neg_log", "uniform", 1, 0),
+    (3, 32, 6, "inv_r", "uniform", 3, 0),
+    (2, 48, 5, "exp", "warped", 2, 0),
+    (3, 20, 4, "gauss", "warped", 8, 0),
+    (2, 24, 4, "poly_test", "warped", 1, 0),
+    (3, 16, 4, "inv_r", "warped", 5, 0.3),
+]
+
+
+@pytest.mark.parametrize("d,n,p,kernel,grid,nrhs,t", CASES)
+def test_exact_rows_match_dense_oracle(torch, d, n, p, kernel, grid, nrhs, t):
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] exact rows d={d} n={n} {kernel} {grid} nrhs={nrhs} edges={t}")
+    x = W.uniform_nodes(n) if grid == "uniform" else W.warped_nodes(n)
+    edges = [W.split_edges(x, t)] * d if t else None
+    g = geometry.uniform_grid(d, n) if grid == "uniform" else geometry.tensor_grid([x] * d, edges=edges)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    rng = np.random.default_rng(d * 10 + n)
+    u = rng.standard_normal((g.N, nrhs))
+    rows = np.sort(rng.choice(g.N, size=37, replace=False))
+    M = H.htlr_build(None if grid == "uniform" else np.concatenate([x] * d), kernel, d, n, p, 4, a=a,
+                     edges=None if edges is None else np.concatenate(edges))
+    ut = torch.tensor(u.T.copy(), device="cuda").t()
+    got = M.exact_rows(ut, torch.tensor(rows, device="cuda")).cpu().numpy()
+    want = dense.matvec(g, kernel, p, a, u, rows=rows)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _say(f"[gpu]   rel diff {rel:.2e}")
+    assert rel <= 1e-12
+    M.free()
+
+
+def test_exact_rows_single_rhs_and_bad_rows(torch):
+    import paper_2508_05958_amd as H
+    _say("[gpu] exact rows: one rhs, a row out of range")
+    g = geometry.uniform_grid(2, 32)
+    a = np.ones(g.N)
+    u = np.random.default_rng(3).standard_normal(g.N)
+    M = H.htlr_build(None, "inv_r", 2, 32, 5, 4, a=a)
+    rows = np.array([0, 5, 1023, g.N, -1, 17], dtype=np.int64)
+    got = M.exact_rows(torch.tensor(u, device="cuda"), torch.tensor(rows, device="cuda")).cpu().numpy()
+    assert got.shape == (6,)
+    ok = np.array([True, True, True, False, False, True])
+    assert np.isnan(got[~ok]).all()
+    want = dense.matvec(g, "inv_r", 5, a, u, rows=rows[ok])
+    assert np.linalg.norm(got[ok] - want) / np.linalg.norm(want) <= 1e-12
+    M.free()

@@ -89,6 +89,29 @@ def test_fp64_matches_htlr_oracle(torch, d, n, leaf, p, kernel, grid, nrhs):
         assert _rel(fg, dense.matvec(g, kernel, p, a, u)) <= FP64_TOL
 
 
+@pytest.mark.parametrize("d,n,leaf,p,kernel,grid,t", [(2, 32, 4, 5, "neg_log", "uniform", 0.3),
+                                                     (3, 12, 3, 3, "inv_r", "warped", 0.7),
+                                                     (2, 24, 3, 4, "poly_test", "warped", 0.35)])
+def test_caller_cells_match_htlr_oracle(torch, d, n, leaf, p, kernel, grid, t):
+    """Cells given by the caller (htlr_build_opts.edges): weights, diagonal
+    integrals and boxes follow them; uniform nodes with other cells take the
+    tensor-grid path."""
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] caller cells d={d} n={n} {kernel} {grid} t={t}")
+    x = W.uniform_nodes(n) if grid == "uniform" else W.warped_nodes(n)
+    e = W.split_edges(x, t)
+    g = geometry.tensor_grid([x] * d, edges=[e] * d)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    u = np.random.default_rng(d * 100 + n).standard_normal(g.N)
+    M = _build(H, None if grid == "uniform" else np.concatenate([x] * d), kernel, d, n, p, leaf, a,
+               edges=np.concatenate([e] * d))
+    assert not M.info()["uniform"]
+    fg = _gpu_matvec(torch, M, u)
+    assert _rel(fg, htlr.HTLR(g, kernel, p, leaf, a).matvec(u)) <= FP64_TOL
+    if kernel == "poly_test":
+        assert _rel(fg, dense.matvec(g, kernel, p, a, u)) <= FP64_TOL
+
+
 def test_nothing_admissible_equals_dense(torch):
     import paper_2508_05958_amd as H
     _say("[gpu] nothing admissible, 3D n=8 leaf 4")

@@ -87,6 +87,24 @@ def test_fp64_matches_oracle(torch, d, n, m, leaf, p, kernel, adm, eta2, nodes, 
     assert _rel(_gpu_matvec(torch, M, u), ref) <= FP64_TOL
 
 
+def test_caller_cells_match_oracle(torch):
+    """Quasi-uniform cells given by the caller (htlr_build_opts.edges): S and
+    T follow them (cell-overlap matrices of Sec. 3.3)."""
+    import paper_2508_05958_amd as H
+    _say("[gpu] quasi with caller cells")
+    d, n, m, leaf, p = 2, 24, 32, 4, 5
+    nd = _nodes(d, n, "skewed")
+    ed = [W.split_edges(x, 0.3 if l == 0 else 0.65) for l, x in enumerate(nd)]
+    gq = geometry.tensor_grid(nd, edges=ed)
+    a = 1.0 + 0.5 * gq.points()[:, 0]
+    u = _u(gq, 2, 13)
+    M = H.htlr_build_quasi(np.concatenate(nd), "neg_log", d, n, m, p, leaf, a=a, edges=np.concatenate(ed))
+    ref = quasi.matvec(gq, m, "neg_log", p, leaf, a, u, khat="htlr")
+    assert _rel(_gpu_matvec(torch, M, u), ref) <= FP64_TOL
+    ref0 = quasi.matvec(geometry.tensor_grid(nd), m, "neg_log", p, leaf, a, u, khat="htlr")
+    assert _rel(ref, ref0) > 1e-6          # the cells matter
+
+
 def test_coincident_grid_equals_uniform_product(torch):
     """n = m on the uniform grid: S = T = I, the transfer form equals the
     uniform handle's product."""

@@ -67,19 +67,20 @@ def test_server_with_autotune(torch):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
-@pytest.mark.parametrize("mode", [1, 2])
-def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mode):
+@pytest.mark.parametrize("mode,order", [(1, 0), (1, 1), (2, 0)])
+def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mode, order):
     """Force each matrix-core tile shape (128x128, 128x64, 256x128, 224x64, 256x256, 64x128, 64x64) through
-    the tuner's cache file and compare with the oracle (FP64) or with the
-    GPU FP64 product (FP32, BF16)."""
+    the tuner's cache file, in class-tile mode with both work-item orders and
+    in offset-major mode, and compare with the oracle (FP64) or with the GPU
+    FP64 product (FP32, BF16)."""
     import paper_2508_05958_amd as H
     from oracle import geometry, htlr
-    _say(f"[gpu] forced tile {tile} mode {mode} {prec}")
+    _say(f"[gpu] forced tile {tile} mode {mode} order {order} {prec}")
     n, p, leaf, nrhs = 32, 6, 8, 3
     pid = {"fp64": 0, "fp32": 1, "bf16": 2}[prec]
     cache = tmp_path / "tune.txt"
     key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
-    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 0 0 1.0 1.0\n")
+    cache.write_text(f"{key} 2048 -1 0 {tile} {mode} 0 0 0 0 1.0 1.0 {order}\n")
     monkeypatch.setenv("HTLR_TUNE_CACHE", str(cache))
     g = geometry.uniform_grid(3, n)
     a = 1.0 + 0.5 * g.points()[:, 0]

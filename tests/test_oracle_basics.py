@@ -190,3 +190,35 @@ def test_diagonal_singular_converges(golden):
         assert all(b < a for a, b in zip(errs, errs[1:])), errs
     assert 5e-3 < errs3[1] < 3e-2          # the configured 8^3 rule
     assert errs2[2] < 1e-2                 # the configured 16^2 rule
+
+
+def test_caller_cells():
+    """Cells given as edges: Voronoi edges written out reproduce the default
+    grid; the uniform edges with uniform nodes give weights h^d; any edges
+    spanning [0, 1] give weights summing to 1; k = 1 gives |Omega_i| on every
+    skewed cell; a polynomial integrand over skewed cells matches its
+    antiderivative on those cells (and differs from the Voronoi cells' value)."""
+    import htlr_workloads as W
+    x = W.warped_nodes(10)
+    g0 = geometry.tensor_grid([x, x])
+    g1 = geometry.tensor_grid([x, x], edges=[W.split_edges(x, 0.5)] * 2)
+    assert np.allclose(g0.weights(), g1.weights(), rtol=1e-13, atol=0)
+    u = W.uniform_nodes(8)
+    gu = geometry.tensor_grid([u, u, u], edges=[np.arange(9) / 8.0] * 3)
+    assert np.allclose(gu.weights(), 8.0 ** -3, rtol=1e-15, atol=0)
+    e1, e2 = W.split_edges(x, 0.3), W.split_edges(x, 0.8)
+    gs = geometry.tensor_grid([x, x], edges=[e1, e2])
+    assert abs(gs.weights().sum() - 1.0) < 1e-14
+    assert not np.allclose(gs.weights(), g0.weights())
+    assert np.allclose(geometry.diagonal(gs, "poly_test", 1), gs.weights(), rtol=1e-14, atol=0)
+    lin = np.arange(gs.N)
+    D = geometry.diagonal(gs, "poly_test", 3, lin=lin)
+    P = gs.points(lin)
+    idx = gs.multi_index(lin)
+    exact = np.ones(len(lin))
+    for l, e in enumerate((e1, e2)):
+        A = kernels.POLY_A[l]
+        F = lambda y: -(1 + A * (P[:, l] - y)) ** 3 / (3 * A)
+        exact *= F(e[idx[l] + 1]) - F(e[idx[l]])
+    assert np.allclose(D, exact, rtol=1e-13)
+    assert not np.allclose(D, geometry.diagonal(g0, "poly_test", 3, lin=lin), rtol=1e-3)

@@ -60,6 +60,71 @@ def test_planner_pairs_equal_oracle_tree(d, n, leaf, eta2, kind, grid):
         assert mine == _oracle_pairs(g, leaf, eta2, kind, level), level
 
 
+@pytest.mark.parametrize("d,n,leaf,grid,t", [(2, 32, 4, "uniform", 0.3), (3, 16, 2, "uniform", 0.7),
+                                            (2, 24, 3, "warped", 0.7), (3, 12, 3, "warped", 0.35)])
+def test_planner_with_cell_edges_equals_oracle_tree(d, n, leaf, grid, t):
+    """Cells given by the caller (htlr_build_opts.edges): the boxes Omega_tau
+    are unions of those cells, so the block cluster tree follows them.  Each
+    case's pairs differ from those of the default (Voronoi) cells, so an
+    ignored edges argument fails."""
+    x = W.uniform_nodes(n) if grid == "uniform" else W.warped_nodes(n)
+    e = W.split_edges(x, t)
+    g = geometry.tensor_grid([x] * d, edges=[e] * d)
+    pts = None if grid == "uniform" else np.concatenate([x] * d)
+    edges = np.concatenate([e] * d)
+    L, adm, near = H.htlr_plan_counts(pts, d, n, leaf, 1.0, "strong", edges=edges)
+    differs = False
+    for level in list(range(L + 1)) + [-1]:
+        tau, sig = H.htlr_plan_pairs(pts, d, n, leaf, level, 1.0, "strong", edges=edges)
+        mine = sorted(zip(tau.tolist(), sig.tolist()))
+        assert mine == _oracle_pairs(g, leaf, 1.0, "strong", level), level
+        t0, s0 = H.htlr_plan_pairs(pts, d, n, leaf, level, 1.0, "strong")
+        differs |= mine != sorted(zip(t0.tolist(), s0.tolist()))
+    assert differs
+
+
+def test_cell_edges_are_checked():
+    x = W.uniform_nodes(8)
+    e = W.split_edges(x, 0.5)
+    with pytest.raises(H.HTLRError) as ex:
+        H.htlr_plan_counts(None, 2, 8, 2, edges=np.concatenate([e, e[::-1]]))     # not increasing
+    assert ex.value.status == -1
+    bad = e.copy()
+    bad[3] = x[3] + 1e-3                                                        # node 3 left of its cell
+    with pytest.raises(H.HTLRError) as ex:
+        H.htlr_plan_counts(None, 2, 8, 2, edges=np.concatenate([e, bad]))
+    assert ex.value.status == -1
+    with pytest.raises(H.HTLRError) as ex:
+        H.htlr_plan_counts(None, 2, 8, 2, edges=np.concatenate([e, e[:-1]]))    # wrong count
+    assert ex.value.status == -1
+    # the uniform edges k/n on the uniform nodes are the uniform grid
+    u = np.arange(9) / 8.0
+    assert H.htlr_plan_counts(None, 2, 8, 2, edges=np.concatenate([u, u])) == H.htlr_plan_counts(None, 2, 8, 2)
+
+
+@pytest.mark.slow
+def test_planner_equals_oracle_tree_on_warped_96():
+    """The warped 96^3 grid of the solve workload, pair for pair against the
+    oracle's block cluster tree (counts 1352 / 136312 / 2110448 admissible
+    leaves at levels 2-4 and 405008 near pairs)."""
+    x = W.warped_nodes(96)
+    g = geometry.tensor_grid([x] * 3)
+    pts = np.concatenate([x] * 3)
+    t = ClusterTree(g, 8)
+    adm = Admissibility(t, "strong", 1.0)
+    want = {}
+    for k, tau, sigma in block_leaves(t, adm):
+        m = tau.hi[0] - tau.lo[0]
+        B = 96 // m
+        lin = lambda nd: sum((nd.lo[l] // m) * B ** l for l in range(3))
+        want.setdefault(tau.level if k == "A" else -1, []).append((lin(tau), lin(sigma)))
+    L, cnt, near = H.htlr_plan_counts(pts, 3, 96, 8)
+    assert cnt[2:] == [1352, 136312, 2110448] and near == 405008
+    for level in (2, 3, 4, -1):
+        tau, sig = H.htlr_plan_pairs(pts, 3, 96, 8, level)
+        assert sorted(zip(tau.tolist(), sig.tolist())) == sorted(want[level]), level
+
+
 def test_planner_counts_match_derived(golden):
     for case in golden["derived_block_counts"]["cases"]:
         L, adm, near = H.htlr_plan_counts(None, case["d"], case["n"], case["leaf"])
