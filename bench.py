@@ -46,14 +46,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 / bfloat16-core variants of the headline")
     ap.add_argument("--no-small", action="store_true", help="skip the n = 64 FP64 block")
-    ap.add_argument("--cpu-leaves", type=int, default=32, help="leaf boxes of the CPU-oracle sample")
+    ap.add_argument("--cpu-leaves", type=int, default=64, help="leaf boxes of the CPU-oracle sample")
     ap.add_argument("--cpu-procs", type=int, default=16, help="worker processes of the CPU-oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the warped-grid solve block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
     ap.add_argument("--no-quasi", action="store_true", help="skip the quasi-uniform transfer block")
     ap.add_argument("--no-orth", action="store_true", help="skip the orthonormal / QRCP forms block")
-    ap.add_argument("--serve-requests", type=int, default=160)
-    ap.add_argument("--serve-rates", default="0.5",
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-rates", default="0.25,0.5,1,2,4",
                     help="Poisson arrival rates as multiples of the measured capacity, comma separated")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the headline product (otherwise its built-in kernel choices, the ones the "
@@ -368,10 +368,11 @@ def paper_tables_block(H, torch, np):
             # e_apply;rand (Sec. 5): relative 2-norm error of the product
             # against the exact A u on 1000 random rows, u ~ N(0, 1)
             u = torch.tensor(np.random.default_rng([d, n]).standard_normal(N), device="cuda")
-            rows = np.sort(np.random.default_rng([d, n, 1]).choice(N, size=min(1000, N), replace=False))
+            pick = torch.tensor(np.sort(np.random.default_rng([d, n, 1]).choice(N, size=min(1000, N), replace=False)),
+                                device="cuda")
             f = M.matvec(u, prec="fp64")
-            ex = M.exact_rows(u, torch.tensor(rows, device="cuda"))
-            e_apply = float(torch.linalg.norm(f[torch.tensor(rows, device="cuda")] - ex) / torch.linalg.norm(ex))
+            ex = M.exact_rows(u, pick)
+            e_apply = float(torch.linalg.norm(f[pick] - ex) / torch.linalg.norm(ex))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             reps = 3
@@ -627,8 +628,8 @@ def serve_block(H, np, W, count, rates=(0.5,)):
                       f"p50 {res['rates'][-1]['p50_latency_s']} s, p99 {res['rates'][-1]['p99_latency_s']} s",
                       file=sys.stderr, flush=True)
         st = S.stats()
-        res["server"] = {k: st[k] for k in ("ticks", "fused_products", "graph_launches", "resident_structures",
-                                            "resident_bytes")}
+        res["server"] = {k: st[k] for k in ("ticks", "fused_products", "graph_launches", "group_products",
+                                            "grouped_launches", "resident_structures", "resident_bytes")}
         S.close()
         out[f"inner_{inner}"] = res
     return out

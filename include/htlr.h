@@ -347,7 +347,14 @@ htlr_status htlr_plan_pairs(const double* points, const double* edges, int d, in
  *    after every GMRES cycle); the products of all requests on one structure
  *    in one tick are fused into a single multi-right-hand-side product,
  *    optionally replayed from a captured hipGraph;
- *  - structures run on separate streams, so their work overlaps.
+ *  - structures that share their factors (the uniform grid of the same d,
+ *    n, p, leaf, eta2 and admissibility; e.g. different kernels) form a
+ *    group: their fused products of one tick run as one grouped product, in
+ *    which the up contraction and the down expansion of each level are one
+ *    launch over the columns of every member (Alg. 4.2's factor steps do not
+ *    depend on the kernel), and the core applies and near fields run per
+ *    structure;
+ *  - structures (or groups) run on separate streams, so their work overlaps.
  * A request's answer does not depend on which other requests share its
  * ticks beyond rounding (each column of a fused product is computed by the
  * same arithmetic as alone).
@@ -363,6 +370,7 @@ typedef struct {
   int inner_prec;       /* htlr_precision of the inner products */
   int use_graphs;       /* 1: replay fused products from captured hipGraphs */
   int autotune;         /* 1: time kernel variants per (structure, batch width, precision) */
+  int no_group_fusion;  /* 1: never fuse the products of different structures */
 } htlr_server_opts;
 
 typedef struct {
@@ -388,6 +396,8 @@ typedef struct {
   int64_t ticks, fused_products, graph_launches, structures_built, evictions;
   int resident_structures, active, queued;
   size_t resident_bytes;
+  int64_t group_products;     /* fused products that spanned several structures */
+  int64_t grouped_launches;   /* up / down launches shared by several structures */
 } htlr_server_stats_t;
 
 htlr_status htlr_server_create(const htlr_server_opts* opts, htlr_server* out);

@@ -222,6 +222,9 @@ class HTLRMatrix:
 
     def matvec(self, u, f=None, prec="fp64", stream=None):
         """f = A u for device tensors u (N,) or (N, nrhs), column-major for nrhs > 1."""
+        return self._product(lib().htlr_matvec, u, f, prec, stream)
+
+    def _product(self, fn, u, f, prec, stream):
         import torch
         pr = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
         dt = torch.float64 if pr == 0 else torch.float32
@@ -232,8 +235,8 @@ class HTLRMatrix:
             self._check_vec(f, "f", dt, nrhs)
             if f.data_ptr() == u.data_ptr():
                 raise HTLRError(-1, "f and u must not overlap")
-        _check(lib().htlr_matvec(self._h, u.data_ptr(), f.data_ptr(), nrhs, pr,
-                                 VEC_F64 if pr == 0 else VEC_F32, _stream_ptr(stream)))
+        _check(fn(self._h, u.data_ptr(), f.data_ptr(), nrhs, pr, VEC_F64 if pr == 0 else VEC_F32,
+                  _stream_ptr(stream)))
         return f
 
     def solve(self, f, u=None, tol=1e-10, restart=30, max_outer=20, max_inner=300, inner_prec="fp32",
@@ -316,7 +319,7 @@ class HTLRMatrix:
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_size_t), ("max_active", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("restart", ctypes.c_int), ("inner_prec", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("no_group_fusion", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -336,7 +339,8 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("ticks", ctypes.c_int64), ("fused_products", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
                 ("structures_built", ctypes.c_int64), ("evictions", ctypes.c_int64),
                 ("resident_structures", ctypes.c_int), ("active", ctypes.c_int), ("queued", ctypes.c_int),
-                ("resident_bytes", ctypes.c_size_t)]
+                ("resident_bytes", ctypes.c_size_t), ("group_products", ctypes.c_int64),
+                ("grouped_launches", ctypes.c_int64)]
 
 
 def _declare_server(L):
@@ -361,12 +365,12 @@ class Server:
     """Continuous-batching request server (wraps htlr_server)."""
 
     def __init__(self, memory_budget=0, max_active=64, max_batch=16, restart=30, inner_prec="fp32",
-                 use_graphs=True, autotune=False):
+                 use_graphs=True, autotune=False, group_fusion=True):
         L = lib()
         _declare_server(L)
         o = _ServerOpts(int(memory_budget), max_active, max_batch, restart,
                         PRECISIONS[inner_prec] if isinstance(inner_prec, str) else int(inner_prec),
-                        1 if use_graphs else 0, 1 if autotune else 0)
+                        1 if use_graphs else 0, 1 if autotune else 0, 0 if group_fusion else 1)
         h = _vp()
         _check(L.htlr_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -593,8 +593,8 @@ static void launch_variant(const TE* G, const TE* W, const TE* zero, void* H, co
                            int nb, int B, hipStream_t st) {
   using TA = typename AccT<TE>::type;
   const unsigned nwg = (unsigned)(((I.n + 7) / 8) * 8);
-  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(core_threads(BMT)), 0, st, G, W, zero, (TA*)H, tau, ptr, off,
-                     I.buf.as<int32_t>(), I.n, ks, helems, P, nrhs, nb, B, (const int32_t*)nullptr);
+  hipLaunchKernelGGL((k_core_mfma<TE, BMT, BNT>), dim3(nwg), dim3(core_threads(BMT)), 0, st, G, W, zero, (TA*)H, tau,
+                     ptr, off, I.buf.as<int32_t>(), I.n, ks, helems, P, nrhs, nb, B, (const int32_t*)nullptr);
 }
 
 template <typename TE, int BMT, int BNT>

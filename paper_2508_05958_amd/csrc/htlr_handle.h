@@ -195,11 +195,16 @@ struct htlr_matrix_impl {
   TuneParams cur;                    // choices of the product being issued
   hipEvent_t ev_fork = nullptr;      // level concurrency: fork from and join into the caller's stream
   hipEvent_t ev_level[kMaxLevels] = {};
+  std::vector<hipStream_t> side;     // the handle's own side streams for the level chains
   std::shared_ptr<QuasiData> quasi;  // set on quasi-uniform handles: T Ahat S (Sec. 3.3)
   htlr_matrix_impl() = default;
   htlr_matrix_impl(const htlr_matrix_impl&) = delete;
   htlr_matrix_impl& operator=(const htlr_matrix_impl&) = delete;
   ~htlr_matrix_impl() {
+    for (hipStream_t s : side) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (hipEvent_t e : ev_level)
       if (e) (void)hipEventDestroy(e);
@@ -229,8 +234,10 @@ struct ProfScope {
 
 bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
 // Side streams for the concurrent level chains of a product (a few per
-// device, shared by every handle, default priority, kept until the process
-// ends); also creates the handle's fork and level events.
+// handle, default priority, non-blocking, created on first use and
+// destroyed with the handle, so that the far fields of different handles do
+// not queue behind each other); also creates the handle's fork and level
+// events.
 const std::vector<hipStream_t>& side_streams(htlr_matrix_impl& A);
 void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec);
 // Allocates every buffer products with up to nrhs right-hand sides can need
@@ -260,6 +267,55 @@ template <typename T>
 void launch_near_rows3d(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st);
 // Work buffers of a product of this shape (handles from htlr_build).
 size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec);
+// Column table of a grouped up contraction or down expansion over several
+// matrices that share their factors (same d, n, p, leaf on a uniform grid):
+// global column r of the launch belongs to the matrix whose work buffer
+// (W for the up contraction, H for the down expansion) starts at base[r],
+// with ld[r] columns per box, as its column rl[r].  Lives in device memory.
+constexpr int kMaxGroupCols = 64;
+struct ColTab {
+  void* base[kMaxGroupCols];
+  int ld[kMaxGroupCols];
+  int rl[kMaxGroupCols];
+};
+
+// f = A_g u for several matrices with the same factors (uniform grids of
+// the same d, n, leaf and Tucker rank; e.g. different kernels): columns
+// [c0_g, c0_g + cols[g]) of the column-major N x C buffers u and f belong to
+// matrix g, in list order.  The up contraction and down expansion of each
+// level whose kernel is a one-pass box kernel, for every matrix's own
+// product and for the whole group, run as one launch over all C columns
+// (column tables route each column's W and H to its matrix's work buffers);
+// the rest runs per matrix.  Everything is issued on st in the single
+// product's order (up, core, near field, then down expansions in level
+// order), so each column equals its matrix's own product with the same
+// kernel choices.  tab_host (pinned) and tab_dev hold 2 * kMaxLevels tables,
+// which must stay untouched until st reaches this point.  Takes each
+// matrix's work-buffer lock; returns the number of grouped launches.
+int product_group(const std::vector<htlr_matrix_impl*>& As, const std::vector<int>& cols, const void* u, void* f,
+                  int prec, hipStream_t st, ColTab* tab_host, ColTab* tab_dev);
+
+// Work buffers of one product: per level the source tensors W, the core
+// apply's outputs H and the partial up contractions UP, plus the zero source
+// tensor of the matrix-core kernel.  noalloc: the buffers live in memory the
+// caller provides, and the product takes only kernels that need no lazily
+// built work lists, side streams or profiler events (the CSR core apply,
+// near-field kernels without K-split partial sums), with the built-in
+// choices and every launch on the caller's stream.
+struct WorkView {
+  void* W[kMaxLevels] = {};
+  void* H[kMaxLevels] = {};
+  void* UP[kMaxLevels] = {};
+  const void* zero = nullptr;
+  bool noalloc = false;
+};
+// f = A u with the work buffers of wv (the caller holds A.ws_mu).
+void product_view(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st,
+                  const WorkView& wv);
+// Lays the work buffers of a product with nrhs right-hand sides out in one
+// region starting at base (256-byte aligned pieces); returns its size in
+// bytes.  base NULL: size only.
+size_t carve_workview(const htlr_matrix_impl& A, int nrhs, char* base, WorkView* wv);
 // f = A u on a handle from htlr_build (work buffers on demand); the caller
 // holds A.ws_mu.  u, f: f64 for FP64, f32 otherwise.
 void product(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st);

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "htlr_device.h"
 #include "htlr_handle.h"
@@ -614,14 +615,23 @@ __global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ H, T* _
   }
 }
 
+// Source or output tensor of (box, column r): the product's own buffer
+// ([box][nrhs][P]), or with GRP the buffer of the matrix that owns column r
+// in a grouped launch over several matrices that share their factors.
+template <bool GRP, typename TW>
+__device__ __forceinline__ TW* col_slot(TW* W, const ColTab* __restrict__ tab, int64_t box, int r, int nrhs, int P) {
+  if constexpr (GRP) return (TW*)tab->base[r] + (box * tab->ld[r] + tab->rl[r]) * (int64_t)P;
+  else return W + (box * nrhs + r) * (int64_t)P;
+}
+
 // Up contraction of a whole 2D box in one block (boxes of up to 64 x 64
 // points): the box X is staged in LDS, then T1[j1][s0] = sum_j0 V0[j0][s0]
 // X[j1][j0] and W[s1][s0] = sum_j1 V1[j1][s1] T1[j1][s0], two barriers per
 // box instead of a few per row.
-template <typename T, typename TW>
+template <typename T, typename TW, bool GRP = false>
 __global__ __launch_bounds__(kThreads) void k_up2d_box(const T* __restrict__ u, TW* __restrict__ W,
                                                        const T* __restrict__ V, int uniform, int n, int m, int B,
-                                                       int p, int nrhs) {
+                                                       int p, int nrhs, const ColTab* __restrict__ tab) {
   extern __shared__ unsigned char smem_raw[];
   T* X = reinterpret_cast<T*>(smem_raw);   // m*m  [j1][j0]
   T* T1 = X + m * m;                       // m*p  [j1][s0]
@@ -643,7 +653,7 @@ __global__ __launch_bounds__(kThreads) void k_up2d_box(const T* __restrict__ u, 
     T1[idx] = v;
   }
   __syncthreads();
-  TW* Wo = W + ((int64_t)box * nrhs + r) * p * p;
+  TW* Wo = col_slot<GRP>(W, tab, box, r, nrhs, p * p);
   for (int idx = tid; idx < p * p; idx += kThreads) {
     const int s0 = idx % p, s1 = idx / p;
     T v = T(0);
@@ -655,10 +665,10 @@ __global__ __launch_bounds__(kThreads) void k_up2d_box(const T* __restrict__ u, 
 // Down expansion of a whole 2D box in one block (boxes of up to 64 x 64
 // points): Z[i1][t0] = sum_t1 U1[i1][t1] H[t1][t0], then
 // f[i1][i0] += sum_t0 U0[i0][t0] Z[i1][t0] (the sums of k_down, in its order).
-template <typename T>
+template <typename T, bool GRP = false>
 __global__ __launch_bounds__(kThreads) void k_down2d_box(const T* __restrict__ H, T* __restrict__ f,
                                                          const T* __restrict__ U, int uniform, int n, int m, int B,
-                                                         int p, int nrhs) {
+                                                         int p, int nrhs, const ColTab* __restrict__ tab) {
   extern __shared__ unsigned char smem_raw[];
   T* hs = reinterpret_cast<T*>(smem_raw);  // p*p  [t1][t0]
   T* Z = hs + p * p;                       // m*p  [i1][t0]
@@ -667,7 +677,7 @@ __global__ __launch_bounds__(kThreads) void k_down2d_box(const T* __restrict__ H
   const int b0 = box % B, b1 = box / B;
   const T* U0 = uniform ? U : U + (size_t)b0 * m * p;
   const T* U1 = uniform ? U : U + ((size_t)B + b1) * m * p;
-  const T* Hb = H + ((int64_t)box * nrhs + r) * p * p;
+  const T* Hb = col_slot<GRP>(H, tab, box, r, nrhs, p * p);
   for (int t = tid; t < p * p; t += kThreads) hs[t] = Hb[t];
   __syncthreads();
   for (int idx = tid; idx < m * p; idx += kThreads) {
@@ -791,10 +801,11 @@ __global__ __launch_bounds__(kThreads) void k_down2d(const T* __restrict__ H, T*
 //   T2[j2][s1][s0] = sum_j1 V1[j1][s1] T1[j2][j1][s0],
 //   W[s2][s1][s0]  = sum_j2 V2[j2][s2] T2[j2][s1][s0]
 // (the sums of k_up, in its order), three barriers per block.
-template <typename T, typename TW>
+template <typename T, typename TW, bool GRP = false>
 __global__ __launch_bounds__(kThreads) void k_up3d_small(const T* __restrict__ u, TW* __restrict__ W,
                                                          const T* __restrict__ V, int uniform, int n, int m, int B,
-                                                         int p, int nrhs, int nb, int64_t nbox) {
+                                                         int p, int nrhs, int nb, int64_t nbox,
+                                                         const ColTab* __restrict__ tab) {
   extern __shared__ unsigned char smem_raw[];
   const int m2 = m * m, m3 = m2 * m, pp = p * p, P = pp * p;
   const int per = m3 + m2 * p + m * pp;    // LDS values per box
@@ -848,7 +859,7 @@ __global__ __launch_bounds__(kThreads) void k_up3d_small(const T* __restrict__ u
     const T* T2 = sh + bl * per + m3 + m2 * p;
     T v = T(0);
     for (int j2 = 0; j2 < m; ++j2) v += V2[j2 * p + t / pp] * T2[j2 * pp + t % pp];
-    W[(box * nrhs + r) * P + t] = store_cast<TW>(v);
+    col_slot<GRP>(W, tab, box, r, nrhs, P)[t] = store_cast<TW>(v);
   }
 }
 
@@ -857,10 +868,11 @@ __global__ __launch_bounds__(kThreads) void k_up3d_small(const T* __restrict__ u
 //   Z1[i2][i1][t0] = sum_t1 U1[i1][t1] Z2[i2][t1][t0],
 //   f[i2][i1][i0] += sum_t0 U0[i0][t0] Z1[i2][i1][t0]
 // (the sums of k_down, in its order), nb boxes per block.
-template <typename T>
+template <typename T, bool GRP = false>
 __global__ __launch_bounds__(kThreads) void k_down3d_small(const T* __restrict__ H, T* __restrict__ f,
                                                            const T* __restrict__ U, int uniform, int n, int m, int B,
-                                                           int p, int nrhs, int nb, int64_t nbox) {
+                                                           int p, int nrhs, int nb, int64_t nbox,
+                                                           const ColTab* __restrict__ tab) {
   extern __shared__ unsigned char smem_raw[];
   const int m2 = m * m, m3 = m2 * m, pp = p * p, P = pp * p;
   const int per = P + m * pp + m2 * p;     // LDS values per box
@@ -876,7 +888,7 @@ __global__ __launch_bounds__(kThreads) void k_down3d_small(const T* __restrict__
     const int bl = idx / P, t = idx % P;
     const int64_t box = box0 + bl;
     if (box >= nbox) continue;
-    sh[bl * per + t] = H[(box * nrhs + r) * P + t];
+    sh[bl * per + t] = col_slot<GRP>(H, tab, box, r, nrhs, P)[t];
   }
   __syncthreads();
   for (int idx = tid; idx < nb * m * pp; idx += kThreads) {
@@ -1136,22 +1148,18 @@ void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
 
 const std::vector<hipStream_t>& side_streams(htlr_matrix_impl& A) {
   constexpr int kSideStreams = 4;
-  static std::mutex mu;
-  static std::map<int, std::vector<hipStream_t>> pool;
-  std::lock_guard<std::mutex> lk(mu);
-  std::vector<hipStream_t>& v = pool[A.device];
-  if (v.empty()) {
+  if (A.side.empty()) {
     for (int i = 0; i < kSideStreams; ++i) {
       hipStream_t s = nullptr;
       HTLR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-      v.push_back(s);
+      A.side.push_back(s);
     }
   }
   if (!A.ev_fork) {
     HTLR_HIP(hipEventCreateWithFlags(&A.ev_fork, hipEventDisableTiming));
     for (hipEvent_t& e : A.ev_level) HTLR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
-  return v;
+  return A.side;
 }
 
 TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
@@ -1167,177 +1175,155 @@ TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
   return best;
 }
 
-// Work buffers of one product: per level the source tensors W, the core
-// apply's outputs H and the partial up contractions UP, plus the zero source
-// tensor of the matrix-core kernel.  noalloc: the buffers live in the
-// library's static scratch array, and the product takes only kernels that
-// need no lazily built work lists, side streams or profiler events (the CSR
-// core apply, near-field kernels without K-split partial sums), with the
-// built-in choices and every launch on the caller's stream.
-struct WorkView {
-  void* W[kMaxLevels] = {};
-  void* H[kMaxLevels] = {};
-  void* UP[kMaxLevels] = {};
-  const void* zero = nullptr;
-  bool noalloc = false;
-};
+// Kernel of a level's up contraction (and, with the same rule, of its down
+// expansion) for a product with nrhs right-hand sides.
+enum UpKind { kUpGeneric = 0, kUpSmall3d = 1, kUpBox2d = 2, kUpRows2d = 3 };
 
-template <typename T>
-static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st,
-                       const WorkView& wv) {
-  // p: Tucker rank of the stored factors; pm1: degree of the polynomial test kernel
-  const int d = A.d, p = A.rank, P = A.P, n = A.n, pm1 = A.p - 1;
-  A.cur = wv.noalloc ? TuneParams{} : find_tune(A, nrhs, prec);
-  const bool prof = !wv.noalloc;
+static int up_kind(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, size_t tsize) {
+  const int d = A.d, lm = lv.m, p = A.rank;
+  const int nch = level_chunks(lv, nrhs, d);
+  if (d == 2 && nch == 1 && lm <= 64) return kUpBox2d;
+  const size_t per3 = (size_t)lm * lm * lm + (size_t)lm * lm * p + (size_t)lm * p * p;
+  if (d == 3 && nch == 1 && lm <= 16 && per3 * tsize <= kLdsBudget) return kUpSmall3d;
+  if (d == 2 && lm >= 128) return kUpRows2d;
+  return kUpGeneric;
+}
+
+static int down_kind(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, size_t tsize) {
+  const int d = A.d, lm = lv.m, p = A.rank, P = A.P;
+  const int nch = level_chunks(lv, nrhs, d);
+  const size_t per3d = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
+  if (d == 3 && nch == 1 && lm <= 16 && per3d * tsize <= kLdsBudget) return kUpSmall3d;
+  if (d == 2 && nch == 1 && lm <= 64) return kUpBox2d;
+  if (d == 2 && lm >= 128 && lm <= 256) return kUpRows2d;
+  return kUpGeneric;
+}
+
+// Whether a level's up contraction and down expansion can run as one launch
+// over several matrices with a column table (the one-pass box kernels).
+static bool groupable_kind(int k) { return k == kUpSmall3d || k == kUpBox2d; }
+
+// Up contraction of one level: W = (|Omega| o u) x_l V_l^T (Alg. 4.2).  With
+// tab (device column table, nrhs = the launch's columns) each column's W goes
+// to the buffer of the matrix that owns it.
+template <typename T, typename TW>
+static void launch_up(htlr_matrix_impl& A, LevelData& lv, const T* u, TW* W, T* upart, int nrhs, hipStream_t ls,
+                      const ColTab* tab) {
+  const int d = A.d, p = A.rank, P = A.P, n = A.n;
+  const int lm = lv.m, lB = lv.B;
   const bool f64 = std::is_same<T, double>::value;
-  const Plan& pl = A.plan;
-  const int m = pl.m[A.L], B = pl.B[A.L];
-  const int M = d == 3 ? m * m * m : m * m;
-  if (M > 4 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "leaf boxes larger than 1024 points");
-  if (P > 8 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "p^d larger than 2048");
-  const T* a = f64 ? (const T*)A.a64.ptr : (const T*)A.a32.ptr;
-  const int64_t nleaf = A.levels[A.L].nbox;
-
-  // far field.  Each level's up and core launches run on a side stream,
-  // concurrently with the near field and with the other levels; the down
-  // expansions then add into f on the caller's stream in level order, so the
-  // summation order is fixed.
-  std::vector<LevelData*> act;
-  for (LevelData& lv : A.levels)
-    if (lv.npairs > 0) act.push_back(&lv);
-  // (serial while profiling: each recorded duration is then one launch's alone)
-  const bool fork = !wv.noalloc && A.cur.serial == 0 && !A.prof.on && !act.empty();
-  const std::vector<hipStream_t>* side = fork ? &side_streams(A) : nullptr;
-  if (fork) {
-    HTLR_HIP(hipEventRecord(A.ev_fork, st));
-    for (size_t i = 0; i < act.size() && i < side->size(); ++i)
-      HTLR_HIP(hipStreamWaitEvent((*side)[i], A.ev_fork, 0));
-  }
-  for (size_t li = 0; li < act.size(); ++li) {
-    LevelData& lv = *act[li];
-    const hipStream_t ls = fork ? (*side)[li % side->size()] : st;
-    const int l = lv.level, lm = lv.m, lB = lv.B;
-    const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
-    const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
-    T* H = (T*)wv.H[l];
-    // 3D: rows of a slice staged at a time, as many as the LDS budget allows
-    const int up_rows = d == 3 ? (int)std::max<int64_t>(1, std::min<int64_t>(lm, ((int64_t)(kLdsBudget / sizeof(T)) -
-                                                         (int64_t)p * lm - (int64_t)p * p) / lm)) : 0;
-    const size_t sh_up = (d == 3 ? (size_t)up_rows * lm + (size_t)p * lm + (size_t)p * p
-                                 : (size_t)lm + (size_t)kThreads + (size_t)p) * sizeof(T);
-    if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
-    const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
-    T* upart = nch > 1 ? (T*)wv.UP[l] : nullptr;
-    // 2D boxes up to 64 points per side: one block contracts the whole box
-    // (larger boxes keep the row kernel, which spreads each row's dots over
-    // the whole block)
-    const bool box2d = d == 2 && nch == 1 && lm <= 64;
-    const size_t sh_box = ((size_t)lm * lm + (size_t)lm * p) * sizeof(T);
-    // 3D boxes up to 16 points per side whose stages fit in LDS: whole boxes,
-    // several per block when small
+  const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
+  const int uni = A.uniform ? 1 : 0;
+  const int kind = up_kind(A, lv, nrhs, sizeof(T));
+  if (tab && !groupable_kind(kind)) fail(HTLR_ERR_INVALID, "grouped up contraction of a level without box kernels");
+  // 3D: rows of a slice staged at a time, as many as the LDS budget allows
+  const int up_rows = d == 3 ? (int)std::max<int64_t>(1, std::min<int64_t>(lm, ((int64_t)(kLdsBudget / sizeof(T)) -
+                                                       (int64_t)p * lm - (int64_t)p * p) / lm)) : 0;
+  const size_t sh_up = (d == 3 ? (size_t)up_rows * lm + (size_t)p * lm + (size_t)p * p
+                               : (size_t)lm + (size_t)kThreads + (size_t)p) * sizeof(T);
+  if (sh_up > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "box too large for the up contraction");
+  const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
+  T* part = nch > 1 ? upart : nullptr;
+  const int64_t wcount = lv.nbox * (int64_t)nrhs * P;
+  if (kind == kUpSmall3d) {
+    // 3D boxes up to 16 points per side whose stages fit in LDS: whole
+    // boxes, several per block when small
     const size_t per3 = (size_t)lm * lm * lm + (size_t)lm * lm * p + (size_t)lm * p * p;
-    const bool small3d = d == 3 && nch == 1 && lm <= 16 && per3 * sizeof(T) <= kLdsBudget;
-    int nb3 = 1;
-    size_t sh3 = 0;
-    if (small3d) {
-      const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, p * p * p));
-      nb3 = std::max(1, kThreads / S);
-      while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
-      sh3 = nb3 * per3 * sizeof(T);
-    }
+    const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, p * p * p));
+    int nb3 = std::max(1, kThreads / S);
+    while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
     const unsigned g3 = (unsigned)((lv.nbox + nb3 - 1) / nb3);
+    if (tab)
+      hipLaunchKernelGGL((k_up3d_small<T, TW, true>), dim3(g3, nrhs), dim3(kThreads), nb3 * per3 * sizeof(T), ls, u, W,
+                         V, uni, n, lm, lB, p, nrhs, nb3, (int64_t)lv.nbox, tab);
+    else
+      hipLaunchKernelGGL((k_up3d_small<T, TW>), dim3(g3, nrhs), dim3(kThreads), nb3 * per3 * sizeof(T), ls, u, W, V,
+                         uni, n, lm, lB, p, nrhs, nb3, (int64_t)lv.nbox, (const ColTab*)nullptr);
+  } else if (kind == kUpBox2d) {
+    // 2D boxes up to 64 points per side: one block contracts the whole box
+    const size_t sh_box = ((size_t)lm * lm + (size_t)lm * p) * sizeof(T);
+    if (tab)
+      hipLaunchKernelGGL((k_up2d_box<T, TW, true>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W, V, uni, n,
+                         lm, lB, p, nrhs, tab);
+    else
+      hipLaunchKernelGGL((k_up2d_box<T, TW>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W, V, uni, n, lm,
+                         lB, p, nrhs, (const ColTab*)nullptr);
+  } else if (kind == kUpRows2d) {
     // larger 2D boxes: staged rows with each dot split over the block
-    const bool rows2d = d == 2 && !box2d && lm >= 128;
     const int Rr = std::max(1, std::min(std::min(rpc, 4096 / lm), kThreads / p));
     const size_t sh_rows = ((size_t)Rr * lm + (size_t)kThreads + (size_t)Rr * p) * sizeof(T);
-    const int64_t wcount = lv.nbox * (int64_t)nrhs * P;
-    if (prec == HTLR_BF16_CORE) {
-      if constexpr (!std::is_same<T, double>::value) {
-        if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
-        if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
-        uint16_t* W16 = (uint16_t*)wv.W[l];
-        { ProfScope ps(A, "up", l, ls, prof);
-        if (small3d)
-          hipLaunchKernelGGL((k_up3d_small<float, uint16_t>), dim3(g3, nrhs), dim3(kThreads), sh3, ls, u, W16, V, 1, n,
-                             lm, lB, p, nrhs, nb3, (int64_t)lv.nbox);
-        else if (box2d)
-          hipLaunchKernelGGL((k_up2d_box<float, uint16_t>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W16, V,
-                             1, n, lm, lB, p, nrhs);
-        else if (rows2d)
-          hipLaunchKernelGGL((k_up2d_rows<float, uint16_t>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_rows, ls, u,
-                             W16, V, 1, n, lm, lB, p, nrhs, rpc, Rr, (float*)upart);
-        else
-        hipLaunchKernelGGL((k_up<float, uint16_t>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W16, V,
-                           1, d, n, lm, lB, p, nrhs, rpc, (float*)upart, up_rows);
-        if (nch > 1)
-          hipLaunchKernelGGL((k_up_reduce<float, uint16_t>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)),
-                             dim3(256), 0, ls, (const float*)upart, W16, wcount, nch);
-        HTLR_HIP(hipGetLastError()); }
-        ProfScope ps(A, "core", l, ls, prof);
-        if (!wv.noalloc && core_mfma_ok(A, prec)) {
-          launch_core_mfma(A, lv, prec, W16, H, wv.zero, nrhs, ls);
-        } else {
+    hipLaunchKernelGGL((k_up2d_rows<T, TW>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_rows, ls, u, W, V, uni, n,
+                       lm, lB, p, nrhs, rpc, Rr, part);
+  } else {
+    hipLaunchKernelGGL((k_up<T, TW>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W, V, uni, d, n, lm, lB,
+                       p, nrhs, rpc, part, up_rows);
+  }
+  if (nch > 1 && kind != kUpSmall3d && kind != kUpBox2d)
+    hipLaunchKernelGGL((k_up_reduce<T, TW>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)), dim3(256), 0,
+                       ls, (const T*)part, W, wcount, nch);
+  HTLR_HIP(hipGetLastError());
+}
+
+// Core apply of one level: H_tau = sum_sigma G_{tau sigma} W_sigma (Alg. 4.2).
+template <typename T>
+static void launch_core(htlr_matrix_impl& A, LevelData& lv, const void* W, T* H, const void* zero, int nrhs, int prec,
+                        hipStream_t ls, bool noalloc) {
+  const int d = A.d, p = A.rank, P = A.P, pm1 = A.p - 1;
+  const int lB = lv.B;
+  const bool f64 = std::is_same<T, double>::value;
+  if (prec == HTLR_BF16_CORE) {
+    if constexpr (!std::is_same<T, double>::value) {
+      if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
+      if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
+      if (!noalloc && core_mfma_ok(A, prec)) {
+        launch_core_mfma(A, lv, prec, W, H, zero, nrhs, ls);
+      } else {
         const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
         const int nchunk = (nrhs + rc - 1) / rc;
         size_t sh = (size_t)rc * P * sizeof(float);
         HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<uint16_t, uint16_t, float, RC, false>),
-                                                dim3(lv.nbox, nchunk), dim3(kThreads), sh, ls, W16, H,
+                                                dim3(lv.nbox, nchunk), dim3(kThreads), sh, ls, (const uint16_t*)W, H,
                                                 lv.Gm16.as<uint16_t>(), lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
                                                 lv.cid.as<int32_t>(), P, nrhs));
-        HTLR_HIP(hipGetLastError());
-        }
       }
-    } else {
-    T* W = (T*)wv.W[l];
-    { ProfScope ps(A, "up", l, ls, prof);
-    if (small3d)
-      hipLaunchKernelGGL((k_up3d_small<T, T>), dim3(g3, nrhs), dim3(kThreads), sh3, ls, u, W, V, A.uniform ? 1 : 0,
-                         n, lm, lB, p, nrhs, nb3, (int64_t)lv.nbox);
-    else if (box2d)
-      hipLaunchKernelGGL((k_up2d_box<T, T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh_box, ls, u, W, V,
-                         A.uniform ? 1 : 0, n, lm, lB, p, nrhs);
-    else if (rows2d)
-      hipLaunchKernelGGL((k_up2d_rows<T, T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_rows, ls, u, W, V,
-                         A.uniform ? 1 : 0, n, lm, lB, p, nrhs, rpc, Rr, upart);
-    else
-    hipLaunchKernelGGL((k_up<T, T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_up, ls, u, W, V, A.uniform ? 1 : 0,
-                       d, n, lm, lB, p, nrhs, rpc, upart, up_rows);
-    if (nch > 1)
-      hipLaunchKernelGGL((k_up_reduce<T, T>), dim3((unsigned)std::min<int64_t>((wcount + 255) / 256, 4096)), dim3(256), 0,
-                         ls, (const T*)upart, W, wcount, nch);
-    HTLR_HIP(hipGetLastError()); }
-    ProfScope ps(A, "core", l, ls, prof);
-    if (A.uniform && !wv.noalloc && core_mfma_ok(A, prec)) {
-      launch_core_mfma(A, lv, prec, W, H, wv.zero, nrhs, ls);
-    } else if (A.uniform) {
-      const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
-      if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
-      const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(T));
-      const int nchunk = (nrhs + rc - 1) / rc;
-      size_t sh = (size_t)rc * P * sizeof(T);
-      HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, false>), dim3(lv.nbox, nchunk), dim3(kThreads),
-                                              sh, ls, W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
-                                              lv.cid.as<int32_t>(), P, nrhs));
-    } else {
-      const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T), (size_t)P * sizeof(T));
-      const int nchunk = (nrhs + rc - 1) / rc;
-      size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T);
-      HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_tensor<KID, T, RC>), dim3(lv.nbox, nchunk),
-                                                                     dim3(kThreads), sh, ls, W, H, lv.cheb64.as<double>(),
-                                                                     lv.ptr.as<int64_t>(), lv.src.as<int32_t>(), d, p, lB,
-                                                                     nrhs, pm1)));
     }
-    HTLR_HIP(hipGetLastError());
-    }
-    if (fork) HTLR_HIP(hipEventRecord(A.ev_level[li], ls));
+  } else if (A.uniform && !noalloc && core_mfma_ok(A, prec)) {
+    launch_core_mfma(A, lv, prec, W, H, zero, nrhs, ls);
+  } else if (A.uniform) {
+    const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
+    if (!G) fail(HTLR_ERR_UNSUPPORTED, "matrix built without cores for this precision");
+    const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(T));
+    const int nchunk = (nrhs + rc - 1) / rc;
+    size_t sh = (size_t)rc * P * sizeof(T);
+    HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_simple<T, T, T, RC, false>), dim3(lv.nbox, nchunk), dim3(kThreads),
+                                            sh, ls, (const T*)W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
+                                            lv.cid.as<int32_t>(), P, nrhs));
+  } else {
+    const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T), (size_t)P * sizeof(T));
+    const int nchunk = (nrhs + rc - 1) / rc;
+    size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T);
+    HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_tensor<KID, T, RC>), dim3(lv.nbox, nchunk),
+                                                                   dim3(kThreads), sh, ls, (const T*)W, H,
+                                                                   lv.cheb64.as<double>(), lv.ptr.as<int64_t>(),
+                                                                   lv.src.as<int32_t>(), d, p, lB, nrhs, pm1)));
   }
+  HTLR_HIP(hipGetLastError());
+}
 
-  // near field + diagonal (overwrites f)
-  {
-  ProfScope ps(A, "near", -1, st, prof);
+// Near field and diagonal term (overwrites f): inadmissible leaves evaluated
+// on the fly (eq. 4.1).
+template <typename T>
+static void launch_near(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st, bool noalloc) {
+  const int d = A.d, n = A.n, pm1 = A.p - 1;
+  const bool f64 = std::is_same<T, double>::value;
+  const Plan& pl = A.plan;
+  const int m = pl.m[A.L], B = pl.B[A.L];
+  const int M = d == 3 ? m * m * m : m * m;
+  const T* a = f64 ? (const T*)A.a64.ptr : (const T*)A.a32.ptr;
+  const int64_t nleaf = A.levels[A.L].nbox;
   const bool mfma_ok = A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST &&
                        (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T) <= kLdsBudget;
-  const bool near_leaves = !wv.noalloc && use_near_leaves(A, nrhs, prec, A.ws.frozen);
+  const bool near_leaves = !noalloc && use_near_leaves(A, nrhs, prec, A.ws.frozen);
   const bool near_mfma = !near_leaves && mfma_ok &&
                          (A.cur.near_kind == 1 || A.cur.near_kind == 2 || (A.cur.near_kind < 0 && nrhs >= 8));
   if (near_leaves) {
@@ -1430,45 +1416,123 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
                                                                    A.x64.as<double>(), wd, d, n, m, B, nrhs, pm1)));
   }
   HTLR_HIP(hipGetLastError());
+}
+
+// Down expansion of one level: f_tau += H_tau x_l U_l (Alg. 4.2).  With tab
+// (device column table) each column's H comes from the buffer of the matrix
+// that owns it.
+template <typename T>
+static void launch_down(htlr_matrix_impl& A, LevelData& lv, const T* H, T* f, int nrhs, hipStream_t st,
+                        const ColTab* tab) {
+  const int d = A.d, p = A.rank, P = A.P, n = A.n;
+  const int lm = lv.m, lB = lv.B;
+  const bool f64 = std::is_same<T, double>::value;
+  const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
+  const int uni = A.uniform ? 1 : 0;
+  const size_t sh_dn = ((size_t)P + (d == 3 ? (size_t)p * p + (size_t)lm * p : (size_t)p)) * sizeof(T);
+  if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
+  const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
+  const int kind = down_kind(A, lv, nrhs, sizeof(T));
+  if (tab && !groupable_kind(kind)) fail(HTLR_ERR_INVALID, "grouped down expansion of a level without box kernels");
+  // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
+  // 256 points (measured faster than the row kernel there), the row kernel
+  // for larger boxes
+  if (kind == kUpSmall3d) {
+    const size_t per3 = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
+    const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, P));
+    int nb3 = std::max(1, kThreads / S);
+    while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
+    const dim3 grid((unsigned)((lv.nbox + nb3 - 1) / nb3), nrhs);
+    if (tab)
+      hipLaunchKernelGGL((k_down3d_small<T, true>), grid, dim3(kThreads), nb3 * per3 * sizeof(T), st, H, f, U, uni, n,
+                         lm, lB, p, nrhs, nb3, (int64_t)lv.nbox, tab);
+    else
+      hipLaunchKernelGGL((k_down3d_small<T>), grid, dim3(kThreads), nb3 * per3 * sizeof(T), st, H, f, U, uni, n, lm,
+                         lB, p, nrhs, nb3, (int64_t)lv.nbox, (const ColTab*)nullptr);
+  } else if (kind == kUpBox2d) {
+    const size_t sh = ((size_t)p * p + (size_t)lm * p) * sizeof(T);
+    if (tab)
+      hipLaunchKernelGGL((k_down2d_box<T, true>), dim3(lv.nbox, nrhs), dim3(kThreads), sh, st, H, f, U, uni, n, lm, lB,
+                         p, nrhs, tab);
+    else
+      hipLaunchKernelGGL((k_down2d_box<T>), dim3(lv.nbox, nrhs), dim3(kThreads), sh, st, H, f, U, uni, n, lm, lB, p,
+                         nrhs, (const ColTab*)nullptr);
+  } else if (kind == kUpRows2d) {
+    const int R2 = std::max(1, std::min(rpc, 4096 / lm));
+    hipLaunchKernelGGL((k_down2d<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads),
+                       ((size_t)p * p + (size_t)R2 * p) * sizeof(T), st, H, f, U, uni, n, lm, lB, p, nrhs, rpc, R2);
+  } else {
+    hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_dn, st, H, f, U, uni, d, n, lm, lB, p,
+                       nrhs, rpc);
   }
+  HTLR_HIP(hipGetLastError());
+}
 
+template <typename T>
+static void check_shape(const htlr_matrix_impl& A) {
+  const int d = A.d, m = A.plan.m[A.L];
+  const int M = d == 3 ? m * m * m : m * m;
+  if (M > 4 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "leaf boxes larger than 1024 points");
+  if (A.P > 8 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "p^d larger than 2048");
+}
 
+template <typename T>
+static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st,
+                       const WorkView& wv) {
+  A.cur = wv.noalloc ? TuneParams{} : find_tune(A, nrhs, prec);
+  const bool prof = !wv.noalloc;
+  check_shape<T>(A);
+  // far field.  Each level's up and core launches run on a side stream,
+  // concurrently with the near field and with the other levels; the down
+  // expansions then add into f on the caller's stream in level order, so the
+  // summation order is fixed.
+  std::vector<LevelData*> act;
+  for (LevelData& lv : A.levels)
+    if (lv.npairs > 0) act.push_back(&lv);
+  // (serial while profiling: each recorded duration is then one launch's alone)
+  const bool fork = !wv.noalloc && A.cur.serial == 0 && !A.prof.on && !act.empty();
+  const std::vector<hipStream_t>* side = fork ? &side_streams(A) : nullptr;
+  if (fork) {
+    HTLR_HIP(hipEventRecord(A.ev_fork, st));
+    for (size_t i = 0; i < act.size() && i < side->size(); ++i)
+      HTLR_HIP(hipStreamWaitEvent((*side)[i], A.ev_fork, 0));
+  }
   for (size_t li = 0; li < act.size(); ++li) {
     LevelData& lv = *act[li];
-    const int l = lv.level, lm = lv.m, lB = lv.B;
-    const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
+    const hipStream_t ls = fork ? (*side)[li % side->size()] : st;
+    const int l = lv.level;
     T* H = (T*)wv.H[l];
-    if (fork) HTLR_HIP(hipStreamWaitEvent(st, A.ev_level[li], 0));
-    const size_t sh_dn = ((size_t)P + (d == 3 ? (size_t)p * p + (size_t)lm * p : (size_t)p)) * sizeof(T);
-    if (sh_dn > kLdsBudget) fail(HTLR_ERR_UNSUPPORTED, "core too large for the down expansion");
-    const int nch = level_chunks(lv, nrhs, d), rpc = (lm + nch - 1) / nch;
-    ProfScope ps(A, "down", l, st, prof);
-    // 2D: whole boxes up to 64 points per side, staged row chunks at 128 and
-    // 256 points (measured faster than the row kernel there), the row kernel
-    // for larger boxes
-    const size_t per3d = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
-    if (d == 3 && nch == 1 && lm <= 16 && per3d * sizeof(T) <= kLdsBudget) {
-      const int S = std::max(std::max(lm * lm * lm, lm * lm * p), std::max(lm * p * p, P));
-      const size_t per3 = per3d;
-      int nb3 = std::max(1, kThreads / S);
-      while (nb3 > 1 && nb3 * per3 * sizeof(T) > kLdsBudget) --nb3;
-      hipLaunchKernelGGL((k_down3d_small<T>), dim3((unsigned)((lv.nbox + nb3 - 1) / nb3), nrhs), dim3(kThreads),
-                         nb3 * per3 * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p, nrhs, nb3,
-                         (int64_t)lv.nbox);
-    } else if (d == 2 && nch == 1 && lm <= 64) {
-      hipLaunchKernelGGL((k_down2d_box<T>), dim3(lv.nbox, nrhs), dim3(kThreads),
-                         ((size_t)p * p + (size_t)lm * p) * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p,
-                         nrhs);
-    } else if (d == 2 && lm >= 128 && lm <= 256) {
-      const int R2 = std::max(1, std::min(rpc, 4096 / lm));
-      hipLaunchKernelGGL((k_down2d<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads),
-                         ((size_t)p * p + (size_t)R2 * p) * sizeof(T), st, H, f, U, A.uniform ? 1 : 0, n, lm, lB, p,
-                         nrhs, rpc, R2);
-    } else
-    hipLaunchKernelGGL((k_down<T>), dim3(lv.nbox, nrhs, nch), dim3(kThreads), sh_dn, st, H, f, U, A.uniform ? 1 : 0, d,
-                       n, lm, lB, p, nrhs, rpc);
-    HTLR_HIP(hipGetLastError());
+    {
+      ProfScope ps(A, "up", l, ls, prof);
+      if (prec == HTLR_BF16_CORE) {
+        if constexpr (!std::is_same<T, double>::value)
+          launch_up<float, uint16_t>(A, lv, u, (uint16_t*)wv.W[l], (float*)wv.UP[l], nrhs, ls, nullptr);
+      } else {
+        launch_up<T, T>(A, lv, u, (T*)wv.W[l], (T*)wv.UP[l], nrhs, ls, nullptr);
+      }
+    }
+    {
+      ProfScope ps(A, "core", l, ls, prof);
+      launch_core<T>(A, lv, wv.W[l], H, wv.zero, nrhs, prec, ls, wv.noalloc);
+    }
+    if (fork) HTLR_HIP(hipEventRecord(A.ev_level[li], ls));
   }
+  {
+    ProfScope ps(A, "near", -1, st, prof);
+    launch_near<T>(A, u, f, nrhs, prec, st, wv.noalloc);
+  }
+  for (size_t li = 0; li < act.size(); ++li) {
+    LevelData& lv = *act[li];
+    if (fork) HTLR_HIP(hipStreamWaitEvent(st, A.ev_level[li], 0));
+    ProfScope ps(A, "down", lv.level, st, prof);
+    launch_down<T>(A, lv, (const T*)wv.H[lv.level], f, nrhs, st, nullptr);
+  }
+}
+
+void product_view(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st,
+                  const WorkView& wv) {
+  if (prec == HTLR_FP64) run_matvec<double>(A, (const double*)u, (double*)f, nrhs, prec, st, wv);
+  else run_matvec<float>(A, (const float*)u, (float*)f, nrhs, prec, st, wv);
 }
 
 void product(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hipStream_t st) {
@@ -1481,8 +1545,150 @@ void product(htlr_matrix_impl& A, const void* u, void* f, int nrhs, int prec, hi
     wv.UP[lv.level] = A.ws.UP[lv.level].ptr;
   }
   wv.zero = A.ws.zero.ptr;
-  if (prec == HTLR_FP64) run_matvec<double>(A, (const double*)u, (double*)f, nrhs, prec, st, wv);
-  else run_matvec<float>(A, (const float*)u, (float*)f, nrhs, prec, st, wv);
+  product_view(A, u, f, nrhs, prec, st, wv);
+}
+
+// Grouped product over matrices that share their factors (see
+// product_group in htlr_handle.h).
+template <typename T>
+static int run_group(const std::vector<htlr_matrix_impl*>& As, const std::vector<int>& cols, const T* u, T* f,
+                      int prec, hipStream_t st, ColTab* th, ColTab* td) {
+  const size_t G = As.size();
+  htlr_matrix_impl& A0 = *As[0];
+  std::vector<int> c0(G);
+  int C = 0;
+  for (size_t g = 0; g < G; ++g) {
+    c0[g] = C;
+    C += cols[g];
+  }
+  if (C < 1 || C > kMaxGroupCols) fail(HTLR_ERR_INVALID, "grouped product: columns out of range");
+  const int64_t N = A0.N;
+  for (size_t g = 0; g < G; ++g) {
+    const htlr_matrix_impl& A = *As[g];
+    if (A.d != A0.d || A.n != A0.n || A.leaf != A0.leaf || A.rank != A0.rank || A.orth != A0.orth || !A.uniform ||
+        A.quasi || A.levels.size() != A0.levels.size())
+      fail(HTLR_ERR_INVALID, "grouped product: matrices do not share their factors");
+    for (size_t l = 0; l < A.levels.size(); ++l)
+      if ((A.levels[l].npairs > 0) != (A0.levels[l].npairs > 0))
+        fail(HTLR_ERR_INVALID, "grouped product: matrices differ in their levels");
+    check_shape<T>(A);
+    ensure_workspace(*As[g], cols[g], prec);
+  }
+  using TW = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+  const bool bf = prec == HTLR_BF16_CORE;
+  const size_t tsz = sizeof(T);
+  std::vector<int> lev;
+  for (const LevelData& lv : A0.levels)
+    if (lv.npairs > 0) lev.push_back(lv.level);
+  // a level runs as one launch when every matrix's own product, and the
+  // grouped launch, take the same one-pass box kernel
+  int nt = 0;
+  std::vector<int> up_tab(A0.levels.size(), -1), dn_tab(A0.levels.size(), -1);
+  for (int l : lev) {
+    const int ku = up_kind(A0, A0.levels[l], C, tsz), kd = down_kind(A0, A0.levels[l], C, tsz);
+    bool fu = groupable_kind(ku) && G > 1, fd = groupable_kind(kd) && G > 1;
+    for (size_t g = 0; g < G; ++g) {
+      fu = fu && up_kind(*As[g], As[g]->levels[l], cols[g], tsz) == ku;
+      fd = fd && down_kind(*As[g], As[g]->levels[l], cols[g], tsz) == kd;
+    }
+    auto fill = [&](ColTab& t, bool out_w) {
+      for (size_t g = 0; g < G; ++g)
+        for (int r = 0; r < cols[g]; ++r) {
+          t.base[c0[g] + r] = out_w ? As[g]->ws.W[l].ptr : As[g]->ws.H[l].ptr;
+          t.ld[c0[g] + r] = cols[g];
+          t.rl[c0[g] + r] = r;
+        }
+    };
+    if (fu) { up_tab[l] = nt; fill(th[nt++], true); }
+    if (fd) { dn_tab[l] = nt; fill(th[nt++], false); }
+  }
+  if (nt > 2 * kMaxLevels) fail(HTLR_ERR_INVALID, "grouped product: too many column tables");
+  if (nt) HTLR_HIP(hipMemcpyAsync(td, th, nt * sizeof(ColTab), hipMemcpyHostToDevice, st));
+  // up contractions
+  for (int l : lev) {
+    if (up_tab[l] >= 0) {
+      if (bf) {
+        if constexpr (!std::is_same<T, double>::value)
+          launch_up<float, uint16_t>(A0, A0.levels[l], u, (uint16_t*)nullptr, nullptr, C, st, td + up_tab[l]);
+      } else {
+        launch_up<T, TW>(A0, A0.levels[l], u, (TW*)nullptr, nullptr, C, st, td + up_tab[l]);
+      }
+      continue;
+    }
+    for (size_t g = 0; g < G; ++g) {
+      htlr_matrix_impl& A = *As[g];
+      const T* ug = u + (int64_t)c0[g] * N;
+      if (bf) {
+        if constexpr (!std::is_same<T, double>::value)
+          launch_up<float, uint16_t>(A, A.levels[l], ug, (uint16_t*)A.ws.W[l].ptr, (float*)A.ws.UP[l].ptr, cols[g],
+                                     st, nullptr);
+      } else {
+        launch_up<T, TW>(A, A.levels[l], ug, (TW*)A.ws.W[l].ptr, (T*)A.ws.UP[l].ptr, cols[g], st, nullptr);
+      }
+    }
+  }
+  // core applies and near fields, per matrix
+  for (size_t g = 0; g < G; ++g) {
+    htlr_matrix_impl& A = *As[g];
+    A.cur = find_tune(A, cols[g], prec);
+    for (int l : lev) launch_core<T>(A, A.levels[l], A.ws.W[l].ptr, (T*)A.ws.H[l].ptr, A.ws.zero.ptr, cols[g], prec, st,
+                                     false);
+    launch_near<T>(A, u + (int64_t)c0[g] * N, f + (int64_t)c0[g] * N, cols[g], prec, st, false);
+  }
+  // down expansions in level order
+  for (int l : lev) {
+    if (dn_tab[l] >= 0) {
+      launch_down<T>(A0, A0.levels[l], nullptr, f, C, st, td + dn_tab[l]);
+      continue;
+    }
+    for (size_t g = 0; g < G; ++g) {
+      htlr_matrix_impl& A = *As[g];
+      launch_down<T>(A, A.levels[l], (const T*)A.ws.H[l].ptr, f + (int64_t)c0[g] * N, cols[g], st, nullptr);
+    }
+  }
+  return nt;
+}
+
+int product_group(const std::vector<htlr_matrix_impl*>& As, const std::vector<int>& cols, const void* u, void* f,
+                  int prec, hipStream_t st, ColTab* tab_host, ColTab* tab_dev) {
+  if (As.empty() || As.size() != cols.size()) fail(HTLR_ERR_INVALID, "grouped product: bad member list");
+  std::vector<htlr_matrix_impl*> order(As.begin(), As.end());
+  std::sort(order.begin(), order.end());
+  if (std::adjacent_find(order.begin(), order.end()) != order.end())
+    fail(HTLR_ERR_INVALID, "grouped product: a matrix appears twice");
+  std::vector<std::unique_lock<std::mutex>> locks;
+  for (htlr_matrix_impl* A : order) locks.emplace_back(A->ws_mu);
+  if (prec == HTLR_FP64) return run_group<double>(As, cols, (const double*)u, (double*)f, prec, st, tab_host, tab_dev);
+  return run_group<float>(As, cols, (const float*)u, (float*)f, prec, st, tab_host, tab_dev);
+}
+
+// Carves the work buffers of a product with nrhs right-hand sides out of
+// one region (each 256-byte aligned, in level order: W, H, UP, then the
+// zero tensor); returns the bytes used.  With base NULL only the size is
+// computed.
+size_t carve_workview(const htlr_matrix_impl& A, int nrhs, char* base, WorkView* wv) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* q = base ? (void*)(base + off) : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return q;
+  };
+  for (const LevelData& lv : A.levels) {
+    if (lv.npairs == 0) continue;
+    const size_t cnt = (size_t)lv.nbox * nrhs * A.P;
+    void* W = take(cnt * sizeof(double));
+    void* H = take(cnt * sizeof(double));
+    const size_t up = up_part_elems(lv, nrhs, A.P, A.d) * sizeof(double);
+    void* UP = up ? take(up) : nullptr;
+    if (wv) {
+      wv->W[lv.level] = W;
+      wv->H[lv.level] = H;
+      wv->UP[lv.level] = UP;
+    }
+  }
+  const void* z = take((size_t)A.P * sizeof(double));
+  if (wv) wv->zero = z;
+  return off;
 }
 
 

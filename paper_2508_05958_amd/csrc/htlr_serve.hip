@@ -95,6 +95,9 @@ struct Req {
 
 struct Structure {
   std::string key;
+  std::string gkey;                // structures with equal gkey share their factors
+  std::vector<double> points, a;   // build inputs, compared on a key hit
+  hipEvent_t ev = nullptr;         // orders a group's work after this structure's stream
   htlr_matrix A = nullptr;
   int64_t N = 0;
   size_t bytes = 0;
@@ -111,9 +114,32 @@ struct Structure {
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (A) htlr_free(A);
+    if (ev) (void)hipEventDestroy(ev);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
+
+// Batch buffers of the fused products of a group of structures that share
+// their factors (uniform grids of the same d, n, p, leaf, eta2 and
+// admissibility; the kernel and a(x) may differ): the products of all their
+// requests in one tick run as one grouped product (product_group), whose up
+// contractions and down expansions cover every member's columns in one
+// launch per level.
+struct Group {
+  hipStream_t stream = nullptr;
+  int cols = 0;                    // columns of the batch buffers
+  DevBuf U64, F64, U32, F32, ptrs, partial, tabs;
+  PinnedBuf hptrs, htabs;
+  size_t bytes = 0;
+  ~Group() {
+    if (stream) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipStreamDestroy(stream);
+    }
+  }
+};
+
+constexpr int kTabSlots = 2 * kMaxLevels;   // column tables per grouped product
 
 constexpr int kRedB = 512;
 
@@ -134,9 +160,15 @@ struct ServerImpl {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 
+  // Structure key: the build arguments, eta2 by its exact bit pattern, and a
+  // hash of the points and a(x); a hit is confirmed by comparing points and
+  // a in full (same_inputs), so a hash collision never reuses a structure.
   static std::string make_key(const Req& q) {
     std::ostringstream os;
-    os << q.kernel << '|' << q.d << '|' << q.n << '|' << q.p << '|' << q.leaf << '|' << q.eta2 << '|' << q.adm << '|';
+    uint64_t eb;
+    std::memcpy(&eb, &q.eta2, 8);
+    os << q.kernel << '|' << q.d << '|' << q.n << '|' << q.p << '|' << q.leaf << '|' << std::hex << eb << std::dec
+       << '|' << q.adm << '|';
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](const std::vector<double>& v) {
       for (double x : v) {
@@ -188,10 +220,31 @@ struct ServerImpl {
     }
   }
 
+  static bool same_inputs(const Structure& S, const Req& q) { return S.points == q.points && S.a == q.a; }
+
+  // Structures on the uniform cell-centred grid with the same (d, n, p,
+  // leaf, eta2, admissibility) have the same cluster and block trees and the
+  // same factors at every level; only the kernel (cores, near field) and
+  // a(x) differ.  Other structures form groups of one.
+  static std::string group_key(const Req& q) {
+    if (!q.points.empty()) return "solo|" + q.key;
+    uint64_t eb;
+    std::memcpy(&eb, &q.eta2, 8);
+    std::ostringstream os;
+    os << "uniform|" << q.d << '|' << q.n << '|' << q.p << '|' << q.leaf << '|' << std::hex << eb << std::dec << '|'
+       << q.adm;
+    return os.str();
+  }
+
+  std::map<std::string, std::unique_ptr<Group>> groups;
+
   Structure* build(Req& q) {
     auto S = std::make_unique<Structure>();
     S->key = q.key;
     S->N = q.N;
+    S->points = q.points;
+    S->a = q.a;
+    S->gkey = group_key(q);
     htlr_build_opts bo{};
     bo.eta2 = q.eta2;
     bo.admissibility = q.adm;
@@ -200,6 +253,7 @@ struct ServerImpl {
     HTLR_CHECK_ST(htlr_build(q.points.empty() ? nullptr : q.points.data(), (htlr_kernel)q.kernel, q.d, q.n, q.p,
                              q.leaf, &bo, &S->A));
     HTLR_HIP(hipStreamCreate(&S->stream));
+    HTLR_HIP(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
     S->cap = o.max_batch;
     S->U64.alloc((size_t)S->N * S->cap * sizeof(double));
     S->F64.alloc((size_t)S->N * S->cap * sizeof(double));
@@ -240,6 +294,12 @@ struct ServerImpl {
     while (!queue.empty() && active < o.max_active) {
       Req& q = *reqs.at(queue.front());
       auto it = structs.find(q.key);
+      // a key whose structure was built for other points or a(x) (a hash
+      // collision) is made distinct until it names a free or matching slot
+      while (it != structs.end() && !same_inputs(*it->second, q)) {
+        q.key += '#';
+        it = structs.find(q.key);
+      }
       Structure* S = it == structs.end() ? nullptr : it->second.get();
       const size_t sb = state_bytes(q.N);
       size_t need = sb + (S ? 0 : structure_bytes(q));
@@ -350,17 +410,48 @@ struct ServerImpl {
     ++st.graph_launches;
   }
 
-  // device: out[c] = <Vb[:, c], x> into dst (device), c < ncols
-  void dots(Structure* S, const double* Vb, int ncols, const double* x, double* dst) {
-    hipLaunchKernelGGL(k_dots_partial, dim3(kRedB), dim3(kRB), 0, S->stream, Vb, S->N, ncols, x, S->N,
-                       S->partial.as<double>());
-    hipLaunchKernelGGL(k_dots_final, dim3((ncols + 63) / 64), dim3(64), 0, S->stream, S->partial.as<double>(), kRedB,
-                       ncols, dst);
+  // device: out[c] = <Vb[:, c], x> into dst (device), c < ncols, on stream st
+  // with the partial-sum buffer part (kRedB x ncols doubles)
+  void dots(hipStream_t st, double* part, int64_t N, const double* Vb, int ncols, const double* x, double* dst) {
+    hipLaunchKernelGGL(k_dots_partial, dim3(kRedB), dim3(kRB), 0, st, Vb, N, ncols, x, N, part);
+    hipLaunchKernelGGL(k_dots_final, dim3((ncols + 63) / 64), dim3(64), 0, st, part, kRedB, ncols, dst);
+  }
+
+  // refinement residual r = f - A x from column col of an FP64 product,
+  // its norm (and ||f|| the first time) copied to the host
+  void post_residual(Req* q, const double* col, hipStream_t st, double* part) {
+    const int m = o.restart;
+    const int64_t N = q->N;
+    hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, st, q->df, col, q->dr, N);
+    double* hd = q->hdev.as<double>();
+    dots(st, part, N, q->dr, 1, q->dr, hd + 2 * (m + 1));
+    if (q->fn < 0) dots(st, part, N, q->df, 1, q->df, hd + 2 * (m + 1) + 1);
+    HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+
+  // Arnoldi step: w = A V_k from column col64 (FP64 product) or col32 (inner
+  // precision product), classical Gram-Schmidt twice, norm to the host
+  void post_arnoldi(Req* q, const double* col64, const float* col32, hipStream_t st, double* part) {
+    const int m = o.restart;
+    const int64_t N = q->N;
+    double* w = q->V + (int64_t)(q->k + 1) * N;
+    if (col64)
+      HTLR_HIP(hipMemcpyAsync(w, col64, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+      hipLaunchKernelGGL(k_f2d, dim3(vblocks(N)), dim3(256), 0, st, col32, w, N);
+    double* hd = q->hdev.as<double>();
+    for (int pass = 0; pass < 2; ++pass) {
+      double* hp = hd + pass * (m + 1);
+      dots(st, part, N, q->V, q->k + 1, w, hp);
+      hipLaunchKernelGGL(k_sub_vh, dim3(vblocks(N)), dim3(256), 0, st, q->V, N, q->k + 1, hp, w, N);
+    }
+    dots(st, part, N, w, 1, w, hd + 2 * (m + 1));
+    HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, st));
   }
 
   void issue(Structure* S, std::vector<Req*>& members) {
-    const int m = o.restart;
     const int64_t N = S->N;
+    double* part = S->partial.as<double>();
     std::vector<Req*> R, K;
     for (Req* q : members) (q->arnoldi ? K : R).push_back(q);
     // refinement residuals: r = f - A x (FP64)
@@ -369,15 +460,8 @@ struct ServerImpl {
       std::vector<const double*> src;
       for (size_t i = s; i < e; ++i) src.push_back(R[i]->dx);
       fused_product(S, HTLR_FP64, src);
-      for (size_t i = s; i < e; ++i) {
-        Req* q = R[i];
-        const double* col = S->F64.as<double>() + (int64_t)(i - s) * N;
-        hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, S->stream, q->df, col, q->dr, N);
-        double* hd = q->hdev.as<double>();
-        dots(S, q->dr, 1, q->dr, hd + 2 * (m + 1));
-        if (q->fn < 0) dots(S, q->df, 1, q->df, hd + 2 * (m + 1) + 1);
-        HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, S->stream));
-      }
+      for (size_t i = s; i < e; ++i)
+        post_residual(R[i], S->F64.as<double>() + (int64_t)(i - s) * N, S->stream, part);
     }
     // Arnoldi steps: w = A V_k (inner precision), CGS2, norm
     const int ip = o.inner_prec;
@@ -387,22 +471,126 @@ struct ServerImpl {
       for (size_t i = s; i < e; ++i) src.push_back(K[i]->V + (int64_t)K[i]->k * N);
       fused_product(S, ip, src);
       for (size_t i = s; i < e; ++i) {
-        Req* q = K[i];
-        double* w = q->V + (int64_t)(q->k + 1) * N;
         if (ip == HTLR_FP64)
-          HTLR_HIP(hipMemcpyAsync(w, S->F64.as<double>() + (int64_t)(i - s) * N, N * sizeof(double),
-                                  hipMemcpyDeviceToDevice, S->stream));
+          post_arnoldi(K[i], S->F64.as<double>() + (int64_t)(i - s) * N, nullptr, S->stream, part);
         else
-          hipLaunchKernelGGL(k_f2d, dim3(vblocks(N)), dim3(256), 0, S->stream, S->F32.as<float>() + (int64_t)(i - s) * N,
-                             w, N);
-        double* hd = q->hdev.as<double>();
-        for (int pass = 0; pass < 2; ++pass) {
-          double* hp = hd + pass * (m + 1);
-          dots(S, q->V, q->k + 1, w, hp);
-          hipLaunchKernelGGL(k_sub_vh, dim3(vblocks(N)), dim3(256), 0, S->stream, q->V, N, q->k + 1, hp, w, N);
+          post_arnoldi(K[i], nullptr, S->F32.as<float>() + (int64_t)(i - s) * N, S->stream, part);
+      }
+    }
+    HTLR_HIP(hipGetLastError());
+  }
+
+  // The group of structures Ss (same gkey, each with active requests) ready
+  // for one grouped product per precision this tick, or null when they do not
+  // fit one (a structure with more than max_batch requests in one phase, more
+  // than kMaxGroupCols columns, or no memory for the batch buffers).
+  Group* group_for(const std::string& gk, const std::vector<Structure*>& Ss,
+                   std::map<Structure*, std::vector<Req*>>& by) {
+    int nr = 0, nk = 0;
+    for (Structure* S : Ss) {
+      int r = 0, k = 0;
+      for (Req* q : by[S]) (q->arnoldi ? k : r)++;
+      if (r > o.max_batch || k > o.max_batch) return nullptr;
+      nr += r;
+      nk += k;
+    }
+    const int need = std::max(nr, nk);
+    if (need > kMaxGroupCols) return nullptr;
+    auto& slot = groups[gk];
+    if (!slot) {
+      slot = std::make_unique<Group>();
+      HTLR_HIP(hipStreamCreate(&slot->stream));
+      slot->ptrs.alloc((size_t)2 * kMaxGroupCols * sizeof(double*));
+      slot->hptrs.alloc((size_t)2 * kMaxGroupCols);
+      slot->partial.alloc((size_t)kRedB * (o.restart + 2) * sizeof(double));
+      slot->tabs.alloc((size_t)2 * kTabSlots * sizeof(ColTab));
+      slot->htabs.alloc((size_t)2 * kTabSlots * sizeof(ColTab) / sizeof(double));
+      slot->bytes = slot->ptrs.bytes + slot->partial.bytes + slot->tabs.bytes;
+      used += slot->bytes;
+    }
+    Group* G = slot.get();
+    if (G->cols < need) {
+      const int64_t N = Ss[0]->N;
+      const int cols = std::min(kMaxGroupCols, std::max(need, 2 * o.max_batch));
+      const size_t per = (size_t)N * cols * (sizeof(double) * 2 + (o.inner_prec != HTLR_FP64 ? sizeof(float) * 2 : 0));
+      const size_t old = (size_t)N * G->cols * (sizeof(double) * 2 + (o.inner_prec != HTLR_FP64 ? sizeof(float) * 2 : 0));
+      if (used - old + per > budget) return nullptr;
+      HTLR_HIP(hipStreamSynchronize(G->stream));
+      G->U64.alloc((size_t)N * cols * sizeof(double));
+      G->F64.alloc((size_t)N * cols * sizeof(double));
+      if (o.inner_prec != HTLR_FP64) {
+        G->U32.alloc((size_t)N * cols * sizeof(float));
+        G->F32.alloc((size_t)N * cols * sizeof(float));
+      }
+      used = used - old + per;
+      G->bytes += per - old;
+      G->cols = cols;
+    }
+    return G;
+  }
+
+  // One grouped product of the given precision over the requests in Q (in
+  // structure order), reading column src[i] of request Q[i].
+  void group_product(Group* G, int prec, int slot, const std::vector<Structure*>& Ss,
+                     const std::vector<int>& cols, const std::vector<const double*>& src) {
+    const int C = (int)src.size();
+    const int64_t N = Ss[0]->N;
+    const double** hp = reinterpret_cast<const double**>(G->hptrs.p) + (size_t)slot * kMaxGroupCols;
+    for (int j = 0; j < C; ++j) hp[j] = src[j];
+    const double** dp = G->ptrs.as<const double*>() + (size_t)slot * kMaxGroupCols;
+    HTLR_HIP(hipMemcpyAsync(dp, hp, C * sizeof(double*), hipMemcpyHostToDevice, G->stream));
+    std::vector<htlr_matrix_impl*> As;
+    for (Structure* S : Ss) As.push_back(S->A);
+    ColTab* th = reinterpret_cast<ColTab*>(G->htabs.p) + (size_t)slot * kTabSlots;
+    ColTab* td = G->tabs.as<ColTab>() + (size_t)slot * kTabSlots;
+    if (prec == HTLR_FP64) {
+      hipLaunchKernelGGL(k_gather_f64, dim3(vblocks(N)), dim3(256), 0, G->stream, dp, G->U64.as<double>(), N, C);
+      st.grouped_launches += product_group(As, cols, G->U64.ptr, G->F64.ptr, prec, G->stream, th, td);
+    } else {
+      hipLaunchKernelGGL(k_gather_f32, dim3(vblocks(N)), dim3(256), 0, G->stream, dp, G->U32.as<float>(), N, C);
+      st.grouped_launches += product_group(As, cols, G->U32.ptr, G->F32.ptr, prec, G->stream, th, td);
+    }
+    ++st.fused_products;
+    ++st.group_products;
+  }
+
+  void issue_group(Group* G, const std::vector<Structure*>& Ss, std::map<Structure*, std::vector<Req*>>& by) {
+    // after each member's earlier work (refinement updates issued on its stream)
+    for (Structure* S : Ss) {
+      HTLR_HIP(hipEventRecord(S->ev, S->stream));
+      HTLR_HIP(hipStreamWaitEvent(G->stream, S->ev, 0));
+    }
+    const int64_t N = Ss[0]->N;
+    double* part = G->partial.as<double>();
+    for (int phase = 0; phase < 2; ++phase) {
+      // phase 0: refinement residuals (FP64); phase 1: Arnoldi steps (inner precision)
+      std::vector<Structure*> mem;
+      std::vector<int> cols;
+      std::vector<Req*> Q;
+      std::vector<const double*> src;
+      for (Structure* S : Ss) {
+        int c = 0;
+        for (Req* q : by[S])
+          if (q->arnoldi == (phase == 1)) {
+            Q.push_back(q);
+            src.push_back(phase == 0 ? q->dx : q->V + (int64_t)q->k * N);
+            ++c;
+          }
+        if (c) {
+          mem.push_back(S);
+          cols.push_back(c);
         }
-        dots(S, w, 1, w, hd + 2 * (m + 1));
-        HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+      }
+      if (Q.empty()) continue;
+      const int prec = phase == 0 ? HTLR_FP64 : o.inner_prec;
+      group_product(G, prec, phase, mem, cols, src);
+      for (size_t i = 0; i < Q.size(); ++i) {
+        if (phase == 0)
+          post_residual(Q[i], G->F64.as<double>() + (int64_t)i * N, G->stream, part);
+        else if (prec == HTLR_FP64)
+          post_arnoldi(Q[i], G->F64.as<double>() + (int64_t)i * N, nullptr, G->stream, part);
+        else
+          post_arnoldi(Q[i], nullptr, G->F32.as<float>() + (int64_t)i * N, G->stream, part);
       }
     }
     HTLR_HIP(hipGetLastError());
@@ -503,19 +691,43 @@ struct ServerImpl {
   void step(int* active, int* queued) {
     ++st.ticks;
     admit();
-    std::map<Structure*, std::vector<Req*>> groups;
+    std::map<Structure*, std::vector<Req*>> by;
     for (auto& kv : reqs)
-      if (kv.second->state == 1) groups[kv.second->S].push_back(kv.second.get());
-    for (auto& g : groups) {
-      g.first->ptr_slot = 0;   // the previous tick ended with a synchronisation
-      issue(g.first, g.second);
+      if (kv.second->state == 1) by[kv.second->S].push_back(kv.second.get());
+    std::map<std::string, std::vector<Structure*>> bygroup;
+    for (auto& g : by) bygroup[g.first->gkey].push_back(g.first);
+    std::vector<Group*> ran;
+    for (auto& kv : bygroup) {
+      Group* G = (!o.no_group_fusion && kv.second.size() >= 2) ? group_for(kv.first, kv.second, by) : nullptr;
+      if (G) {
+        issue_group(G, kv.second, by);
+        ran.push_back(G);
+        continue;
+      }
+      for (Structure* S : kv.second) {
+        S->ptr_slot = 0;   // the previous tick ended with a synchronisation
+        issue(S, by[S]);
+      }
     }
-    for (auto& g : groups) HTLR_HIP(hipStreamSynchronize(g.first->stream));
-    for (auto& g : groups)
+    for (auto& g : by) HTLR_HIP(hipStreamSynchronize(g.first->stream));
+    for (Group* G : ran) HTLR_HIP(hipStreamSynchronize(G->stream));
+    for (auto& g : by)
       for (Req* q : g.second) {
         finish_one(*q);
         if (q->state >= 2) retire(*q);
       }
+    // batch buffers of groups with fewer than two resident structures go
+    for (auto it = groups.begin(); it != groups.end();) {
+      int resident = 0;
+      for (auto& kv : structs)
+        if (kv.second->gkey == it->first) ++resident;
+      if (resident < 2) {
+        used -= it->second->bytes;
+        it = groups.erase(it);
+      } else {
+        ++it;
+      }
+    }
     int a = 0;
     for (auto& kv : reqs)
       if (kv.second->state == 1) ++a;

@@ -29,7 +29,7 @@ CASES = [
     (2, 64, 6, "neg_log", "uniform", 1, 0),
     (3, 32, 6, "inv_r", "uniform", 3, 0),
     (2, 48, 5, "exp", "warped", 2, 0),
-    (3, 20, 4, "gauss", "warped", 8, 0),
+    (3, 24, 4, "gauss", "warped", 8, 0),
     (2, 24, 4, "poly_test", "warped", 1, 0),
     (3, 16, 4, "inv_r", "warped", 5, 0.3),
 ]

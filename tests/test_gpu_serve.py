@@ -108,6 +108,49 @@ def test_alone_equals_mixed(torch):
         assert _residual(reqs[k], u_m) <= 2 * TOL
 
 
+# structures that share their factors (same d, n, p, leaf; different kernels)
+GROUPED = [("inv_r", 2, 64, 6, 8), ("neg_log", 2, 64, 6, 8), ("exp", 2, 64, 6, 8),
+           ("inv_r", 3, 16, 4, 4), ("exp", 3, 16, 4, 4)]
+
+
+def _grouped_requests(count=10):
+    out = []
+    for rid in range(count):
+        kern, d, n, p, leaf = GROUPED[rid % len(GROUPED)]
+        a = 1.0 + 0.5 * W.grid_points([W.uniform_nodes(n)] * d)[:, 0]
+        f = np.random.default_rng([4, 100 + rid]).standard_normal(n ** d)
+        out.append(dict(f=f, kernel=kern, d=d, n=n, p=p, leaf=leaf, a=a, tol=TOL))
+    return out
+
+
+def test_cross_structure_fusion(torch):
+    """Requests on structures that differ only in the kernel: with fusion
+    their products of a tick run as one grouped product whose up
+    contractions and down expansions cover all of them in one launch per
+    level.  The answers equal those without fusion bit for bit (each column
+    takes the same kernels either way), and they solve the oracle's system."""
+    import paper_2508_05958_amd as H
+    _say("[gpu] server: cross-structure fusion on vs off")
+    reqs = _grouped_requests(10)
+    outs, stats = [], []
+    for fuse in (False, True):
+        S = H.Server(max_batch=4, inner_prec="fp32", use_graphs=True, group_fusion=fuse)
+        ids = [S.submit(**r) for r in reqs]
+        res = _drain(S, list(ids))
+        stats.append(S.stats())
+        outs.append([res[i] for i in ids])
+        S.close()
+    _say(f"[gpu]   fused: {stats[1]['group_products']} grouped products, {stats[1]['grouped_launches']} shared "
+         f"launches; unfused: {stats[0]['fused_products']} products")
+    assert stats[0]["group_products"] == 0
+    assert stats[1]["group_products"] > 0 and stats[1]["grouped_launches"] > 0
+    for (u0, i0), (u1, i1) in zip(*outs):
+        assert i0["status"] == 0 and i1["status"] == 0
+        assert np.array_equal(u0, u1)
+    for k in (0, 1, 3):
+        assert _residual(reqs[k], outs[1][k][0]) <= 2 * TOL
+
+
 def test_served_answer_equals_direct_solve(torch):
     """The smallest structure (2D n = 32, N = 1024): served answers against
     numpy.linalg.solve on the densely assembled O2 operator, within
