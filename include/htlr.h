@@ -206,6 +206,29 @@ htlr_status htlr_workspace_bytes(htlr_matrix A, int nrhs, htlr_precision prec, s
 htlr_status htlr_matvec(htlr_matrix A, const void* u, void* f, int nrhs, htlr_precision prec,
                         htlr_vec_dtype vec_dtype, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, serving loops or harnesses that forbid hipMalloc): f = A u as
+ * htlr_matvec computes it, with the product's work buffers in a fixed array
+ * of the library's own device memory of HTLR_NOALLOC_SCRATCH_BYTES, which
+ * each device the library runs on holds until the process ends.  Calls no
+ * hipMalloc or hipFree and no allocating library routine.
+ *
+ * Arguments, layouts and errors as htlr_matvec.  The product takes the
+ * kernels that need no lazily built work lists: the plain core apply on
+ * VALU instead of the matrix-core kernels, near-field kernels without K-split
+ * partial sums, every launch on the caller's stream, no tuner choices.  So
+ * its result equals htlr_matvec's to rounding, not bit for bit, and it is
+ * slower on large problems.
+ * HTLR_ERR_INVALID when the work buffers of this (matrix, nrhs) exceed the
+ * fixed size (the message states both sizes; htlr_matvec still serves
+ * them), HTLR_ERR_UNSUPPORTED for htlr_build_quasi handles.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (on different streams, or from several threads) race and
+ * must be serialised by the caller. */
+#define HTLR_NOALLOC_SCRATCH_BYTES (64u << 20)
+htlr_status htlr_matvec_noalloc(htlr_matrix A, const void* u, void* f, int nrhs, htlr_precision prec,
+                                htlr_vec_dtype vec_dtype, void* stream);
+
 /* Rows of the uncompressed Nystrom product (eq. 1.3-1.4):
  *     out_i = (a_i + D_i) u_i + sum_{j != i} k(x_i, x_j) |Omega_j| u_j,
  * evaluated directly over all N source points in FP64, for measuring the

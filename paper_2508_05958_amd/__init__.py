@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(_BuildOpts), ctypes.POINTER(ctypes.c_size_t)]
         L.htlr_workspace_bytes.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.htlr_matvec.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
+        L.htlr_matvec_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
         L.htlr_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(_SolveOpts),
                                  ctypes.POINTER(_SolveInfo), _vp]
         L.htlr_info.argtypes = [_vp, ctypes.POINTER(_Info)]
@@ -223,6 +224,13 @@ class HTLRMatrix:
     def matvec(self, u, f=None, prec="fp64", stream=None):
         """f = A u for device tensors u (N,) or (N, nrhs), column-major for nrhs > 1."""
         return self._product(lib().htlr_matvec, u, f, prec, stream)
+
+    def matvec_noalloc(self, u, f, prec="fp64", stream=None):
+        """f = A u into a caller-given f, with the work buffers in the library's
+        fixed device scratch (htlr_matvec_noalloc): no device allocation."""
+        if f is None:
+            raise HTLRError(-1, "matvec_noalloc writes into a caller-given f")
+        return self._product(lib().htlr_matvec_noalloc, u, f, prec, stream)
 
     def _product(self, fn, u, f, prec, stream):
         import torch

@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libhtlr.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["htlr_plan.cpp", "htlr_build.hip", "htlr_matvec.hip", "htlr_core_mfma.hip", "htlr_near_leaves.hip", "htlr_near_rows.hip", "htlr_quasi.hip", "htlr_solve.hip", "htlr_serve.hip",
-           "htlr_exact.hip"]
+           "htlr_exact.hip", "htlr_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
