@@ -353,6 +353,14 @@ bool core_mfma_ok(const htlr_matrix_impl& A, int prec) {
   return A.P % E == 0;
 }
 
+// Measured at 128^3 x 16 right-hand sides (level 4): tile-major items make
+// the 64- and 32-bit core applies 4-5% faster (the row blocks of a tile read
+// the same gathered sources together); the bfloat16 one is 3% slower.
+int core_item_order(const htlr_matrix_impl& A, int prec) {
+  if (A.cur.order >= 0) return A.cur.order;
+  return prec == HTLR_BF16_CORE ? 0 : 1;
+}
+
 // Work lists for tiles of nb boxes of one parity class, built on first use.
 //
 // A tile computes every offset of the union of its members' lists; a member
@@ -785,7 +793,7 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   const int nmb = (A.P + bmt - 1) / bmt;
   const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
   if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
-  LevelData::Tiles::Items& I = items_for(T, ks, nmb, A.cur.order, A.ws.frozen);
+  LevelData::Tiles::Items& I = items_for(T, ks, nmb, core_item_order(A, prec), A.ws.frozen);
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
   const int64_t helems = lv.nbox * (int64_t)nrhs * A.P;
   void* Hout = H;
@@ -868,7 +876,7 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
         if (T.ntile == 0) continue;
         const int nmb = (A.P + bmt - 1) / bmt;
         const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
-        items_for(T, ks, nmb, A.cur.order, false);
+        items_for(T, ks, nmb, core_item_order(A, prec), false);
         if (ks > 1) parts_need[l] = std::max(parts_need[l], (size_t)lv.nbox * c * A.P * ks * esz);
       }
     }

@@ -20,12 +20,19 @@ __device__ __forceinline__ double kr2(double r2, int d) {
   else return exp(-r2 / (2.0 * d));
 }
 
+// Single precision: the hardware reciprocal square root, square root, 2^x
+// and log2 instructions (about 1 ulp each), with exp(x) = 2^(x log2 e) and
+// log(x) = ln 2 log2(x); far inside the accuracy of a single-precision
+// product.  The arguments stay in the instructions' normal range: r^2 > 0,
+// and the exponents are negative and of modest size on [0, 1]^d.
 template <int KID>
 __device__ __forceinline__ float kr2(float r2, int d) {
-  if constexpr (KID == HTLR_K_INV_R) return rsqrtf(r2);
-  else if constexpr (KID == HTLR_K_NEG_LOG) return -0.5f * logf(r2);
-  else if constexpr (KID == HTLR_K_EXP) return expf(-sqrtf(r2));
-  else return expf(-r2 / (2.0f * d));
+  constexpr float kLog2e = 1.44269504088896341f;      // log2(e)
+  constexpr float kHalfLn2 = 0.346573590279972655f;   // ln(2) / 2
+  if constexpr (KID == HTLR_K_INV_R) return __builtin_amdgcn_rsqf(r2);
+  else if constexpr (KID == HTLR_K_NEG_LOG) return -kHalfLn2 * __builtin_amdgcn_logf(r2);
+  else if constexpr (KID == HTLR_K_EXP) return __builtin_amdgcn_exp2f(-kLog2e * __builtin_amdgcn_sqrtf(r2));
+  else return __builtin_amdgcn_exp2f(r2 * (-kLog2e / (2.0f * d)));
 }
 
 template <typename T>
@@ -46,6 +53,14 @@ __device__ __forceinline__ T kvec(T dx0, T dx1, T dx2, int d, int pm1) {
     T r2 = dx0 * dx0 + dx1 * dx1 + dx2 * dx2;
     return kr2<KID>(r2, d);
   }
+}
+
+// k at (dx0, dx1, dx2) given c12 = dx1^2 + dx2^2 (formed once per source
+// row by the caller): r^2 = dx0^2 + c12 for the radial kernels.
+template <int KID, typename T>
+__device__ __forceinline__ T kvec_c12(T dx0, T dx1, T dx2, T c12, int d, int pm1) {
+  if constexpr (KID == HTLR_K_POLY_TEST) return kvec<KID, T>(dx0, dx1, dx2, d, pm1);
+  else return kr2<KID>(fma(dx0, dx0, c12), d);
 }
 
 // bfloat16 stored as uint16_t; round to nearest even.

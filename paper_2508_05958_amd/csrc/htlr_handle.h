@@ -141,9 +141,10 @@ struct TuneParams {
                                      // 4 224x64 (FP64), 5 256x256 (BF16), 6 64x128, 7 64x64
   int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
   int serial = 0;                    // 1: every launch on the caller's stream (no level concurrency)
-  int order = 0;                     // matrix-core work items: 0 (class, row block, split, tile),
+  int order = -1;                    // matrix-core work items: 0 (class, row block, split, tile),
                                      // 1 (class, tile, row block, split): the row blocks of a tile
-                                     // run side by side and share its gathered source tensors in L2
+                                     // run side by side and share its gathered source tensors in L2;
+                                     // -1 automatic: 1 for 64- and 32-bit cores, 0 for bfloat16
 };
 
 // Groups of target leaves for the leaf-column near kernel: lpc leaves per
@@ -233,6 +234,9 @@ struct ProfScope {
 };
 
 bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
+// Work-item order of the matrix-core core apply for this precision (the
+// choice in A.cur, or the automatic one).
+int core_item_order(const htlr_matrix_impl& A, int prec);
 // Side streams for the concurrent level chains of a product (a few per
 // handle, default priority, non-blocking, created on first use and
 // destroyed with the handle, so that the far fields of different handles do

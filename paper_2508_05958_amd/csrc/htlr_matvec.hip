@@ -402,10 +402,11 @@ __global__ __launch_bounds__(kThreads) void k_near_tensor(
         T dx2 = (d == 3) ? xi[q][2] - cs[2 * m + j2] : T(0);
         for (int j1 = 0; j1 < m; ++j1) {
           T dx1 = xi[q][1] - cs[m + j1];
+          const T c12 = dx1 * dx1 + dx2 * dx2;
           for (int j0 = 0; j0 < m; ++j0, ++jj) {
             if (self && jj == li[q]) continue;
             T dx0 = xi[q][0] - cs[j0];
-            T kv = kvec<KID, T>(dx0, dx1, dx2, d, pm1);
+            T kv = kvec_c12<KID, T>(dx0, dx1, dx2, c12, d, pm1);
 #pragma unroll
             for (int r = 0; r < RC; ++r) acc[q][r] += kv * us[r * M + jj];
           }
@@ -1030,8 +1031,9 @@ __global__ __launch_bounds__(kThreads) void k_core_tensor(
         T dx2 = (d == 3) ? xt[q][2] - ce[2 * p + s2] : T(0);
         for (int s1 = 0; s1 < p; ++s1) {
           T dx1 = xt[q][1] - ce[p + s1];
+          const T c12 = dx1 * dx1 + dx2 * dx2;
           for (int s0 = 0; s0 < p; ++s0, ++s) {
-            T g = kvec<KID, T>(xt[q][0] - ce[s0], dx1, dx2, d, pm1);
+            T g = kvec_c12<KID, T>(xt[q][0] - ce[s0], dx1, dx2, c12, d, pm1);
 #pragma unroll
             for (int r = 0; r < RC; ++r) acc[q][r] += g * ws[r * P + s];
           }
@@ -1849,7 +1851,8 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
       }
       {
         TuneParams t = best;
-        t.order = 1;
+        const int ord = best.order >= 0 ? best.order : (prec == HTLR_BF16_CORE ? 0 : 1);
+        t.order = 1 - ord;
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
