@@ -86,16 +86,30 @@ def level_shapes(info, w):
     return [(l, 2 ** l, w.n // 2 ** l) for l in range(info["levels"] + 1)]
 
 
+# Kernel evaluations per second a tensor-grid product can reach when it is
+# bound by the vector ALU (cores and near-field blocks made in the product).
+# One evaluation of a radial kernel, per lane: 4 full-rate instructions
+# (difference, r^2, scale, accumulate; 16 lanes per SIMD and cycle) and 2
+# transcendentals (square root or reciprocal square root, and 2^x or log2; a
+# quarter of that rate), i.e. 4/16 + 2/4 = 0.75 SIMD cycles.  1024 SIMDs at
+# 2.4 GHz.  In FP64 the exp and log are software sequences; the same count
+# is used as a lower bound on their cost.
+EVAL_CYCLES = 0.75
+EVAL_PEAK_G = 1024 * 2.4e9 / EVAL_CYCLES / 1e9
+
+
 def algorithmic_cost(info, w, nrhs, prec):
-    """Per launch of each product step: algorithmic flops (no padding) and
+    """Per launch of each product step: algorithmic flops (no padding),
     algorithmic HBM bytes (each operand read once, each result written
-    once)."""
+    once), and, on tensor grids, the kernel evaluations the step makes."""
     P = w.p ** w.d
     M = info["leaf_side"] ** w.d
     ev = 8 if prec == "fp64" else 4                      # vector and work-buffer element
     eg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]         # core and staged source-tensor element
     N = w.N
-    cost = {"near": (2.0 * info["near_pairs"] * M * M * nrhs, 2.0 * N * nrhs * ev)}
+    tensor = w.grid != "uniform"
+    cost = {"near": (2.0 * info["near_pairs"] * M * M * nrhs, 2.0 * N * nrhs * ev,
+                     float(info["near_pairs"] * M * M) if tensor else 0.0)}
     for l, B, m in level_shapes(info, w):
         pairs = info["adm_pairs"][l]
         if not pairs:
@@ -103,11 +117,12 @@ def algorithmic_cost(info, w, nrhs, prec):
         nbox = B ** w.d
         wbytes = nbox * P * nrhs
         cost[f"up_l{l}"] = (2.0 * nbox * nrhs * sum(m ** (w.d - k) * w.p ** (k + 1) for k in range(w.d)),
-                            N * nrhs * ev + wbytes * eg)
+                            N * nrhs * ev + wbytes * eg, 0.0)
         cost[f"core_l{l}"] = (2.0 * pairs * P * P * nrhs,
-                              info["unique_cores"][l] * P * P * eg + wbytes * eg + wbytes * ev)
+                              info["unique_cores"][l] * P * P * eg + wbytes * eg + wbytes * ev,
+                              float(pairs * P * P) if tensor else 0.0)
         cost[f"down_l{l}"] = (2.0 * nbox * nrhs * sum(w.p ** (w.d - k) * m ** (k + 1) for k in range(w.d)),
-                              wbytes * ev + 2.0 * N * nrhs * ev)
+                              wbytes * ev + 2.0 * N * nrhs * ev, 0.0)
     return cost
 
 
@@ -155,11 +170,25 @@ def to_device(torch, u, dt):
     return torch.tensor(u, dtype=dt, device="cuda")
 
 
+def np_mod():
+    import numpy
+    return numpy
+
+
+def build_workload(H, np, w):
+    """The workload's matrix: the uniform grid, or a warped tensor grid from
+    its nodes (cores and near-field blocks then made in the product)."""
+    if w.grid == "uniform":
+        return H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=w.a())
+    return H.htlr_build(np.concatenate(w.nodes()), w.kernel, w.d, w.n, w.p, w.leaf, a=w.a(),
+                        precisions=["fp64", "fp32"])
+
+
 def run_workload(H, torch, w, prec, steps, warmup, prof_steps=3, tune=False, serial=False, M=None, ut=None):
     build_s = 0.0
     if M is None:
         t0 = time.time()
-        M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=w.a())
+        M = build_workload(H, np_mod(), w)
         torch.cuda.synchronize()
         build_s = time.time() - t0
     info = M.info()
@@ -212,10 +241,16 @@ def roofline(info, w, prec, nrhs, prof, ms_meas, workload):
         if step not in cost:
             per[step] = {"ms": round(avg, 4)}
             continue
-        flops, nbytes = cost[step]
+        flops, nbytes, evals = cost[step]
         bound, peak = peak_for(step, prec)
         t_mem = nbytes / (HBM_GBS * 1e9) * 1e3
-        if bound == "hbm":
+        if evals > 0:
+            # tensor grid: cores and near-field blocks evaluated in the product
+            rate = evals / (avg * 1e-3) / 1e9
+            per[step] = {"ms": round(avg, 4), "bound": "alu", "achieved_Geval_s": round(rate, 1),
+                         "peak_Geval_s": round(EVAL_PEAK_G, 1), "frac": round(rate / EVAL_PEAK_G, 4)}
+            t_roof += max(t_mem, evals / (EVAL_PEAK_G * 1e9) * 1e3)
+        elif bound == "hbm":
             gbs = nbytes / (avg * 1e-3) / 1e9
             per[step] = {"ms": round(avg, 4), "bound": "hbm", "achieved_GBs": round(gbs, 1),
                          "frac": round(gbs / HBM_GBS, 4)}
@@ -228,10 +263,16 @@ def roofline(info, w, prec, nrhs, prof, ms_meas, workload):
     mf = [s for s in per if s in cost and per[s]["bound"] != "hbm"]
     dom = max(mf, key=lambda s: per[s]["ms"])
     d = per[dom]
-    roof = {"bound": d["bound"], "achieved": d["achieved_tflops"], "peak": d["peak_tflops"], "unit": "TFLOP/s",
-            "frac": d["frac"], "traffic": traffic_for(workload, prec, dom, prof[dom][0]),
-            "kernel": dom, "flop_per_launch": cost[dom][0], "avg_launch_ms": d["ms"],
-            "product_frac": round(t_roof / ms_meas, 4), "T_roof_ms": round(t_roof, 3)}
+    if d["bound"] == "alu":
+        roof = {"bound": "alu", "achieved": d["achieved_Geval_s"], "peak": d["peak_Geval_s"], "unit": "Geval/s",
+                "frac": d["frac"], "traffic": traffic_for(workload, prec, dom, prof[dom][0]), "kernel": dom,
+                "evals_per_launch": cost[dom][2], "avg_launch_ms": d["ms"],
+                "product_frac": round(t_roof / ms_meas, 4), "T_roof_ms": round(t_roof, 3)}
+    else:
+        roof = {"bound": d["bound"], "achieved": d["achieved_tflops"], "peak": d["peak_tflops"], "unit": "TFLOP/s",
+                "frac": d["frac"], "traffic": traffic_for(workload, prec, dom, prof[dom][0]),
+                "kernel": dom, "flop_per_launch": cost[dom][0], "avg_launch_ms": d["ms"],
+                "product_frac": round(t_roof / ms_meas, 4), "T_roof_ms": round(t_roof, 3)}
     return roof, per
 
 
@@ -245,7 +286,7 @@ def cpu_worker(wname, leaves_csv, out):
     w = W.WORKLOADS[wname]
     g = geometry.uniform_grid(w.d, w.n) if w.grid == "uniform" else geometry.tensor_grid(w.nodes())
     O = htlr.HTLR(g, w.kernel, w.p, w.leaf, w.a())
-    u = w.rhs()
+    u = w.rhs() if w.grid == "uniform" else W.solve_target(w.points())
     leaves = O.tree.leaves()
     pick = [leaves[int(i)] for i in leaves_csv.split(",")]
     print("ready", flush=True)
@@ -408,7 +449,31 @@ def solve_block(H, torch, np, W):
     build_s = time.time() - t0
     us = torch.tensor(W.solve_target(pts), device="cuda")
     f = M.matvec(us, prec="fp64")
-    out = {"workload": w.name, "N": w.N, "tol": 1e-10, "build_s": round(build_s, 3)}
+    out = {"workload": w.name, "N": w.N, "tol": 1e-10, "build_s": round(build_s, 3), "products": {}}
+    # the products the solve is made of, per kernel against the evaluation-rate bound
+    info = M.info()
+    for pr in ("fp32", "fp64"):
+        ut = us if pr == "fp64" else us.float()
+        fp = M.matvec(ut, prec=pr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            M.matvec(ut, fp, prec=pr)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 3 * 1e3
+        M.profile(True)
+        M.matvec(ut, fp, prec=pr)
+        torch.cuda.synchronize()
+        prof = M.profile_read()
+        M.profile(False)
+        roof, per = roofline(info, w, pr, 1, prof, ms, w.name)
+        out["products"][pr] = {"ms": round(ms, 3), "err_vs_fp64": float(torch.linalg.norm(fp.double() - f) /
+                                                                       torch.linalg.norm(f)),
+                               "roofline": roof, "kernels": per}
+        print(f"[bench]   warped {pr} product {ms:.2f} ms: {roof['kernel']} {roof['achieved']} of {roof['peak']} "
+              f"{roof['unit']} ({roof['frac']:.2f}), product {roof['product_frac']:.2f} of T_roof", file=sys.stderr,
+              flush=True)
+        del fp
     for inner in ("fp32", "fp64"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -781,10 +846,10 @@ def main():
     print(f"[bench] {w.name} {prec}: build + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
     t0 = time.time()
-    M = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=w.a())
+    M = build_workload(H, np, w)
     torch.cuda.synchronize()
     build_s = time.time() - t0
-    u_host = w.rhs()
+    u_host = w.rhs() if w.grid == "uniform" else W.solve_target(w.points())
     u64 = to_device(torch, u_host, torch.float64)
     uh = u64 if prec == "fp64" else u64.float().t().contiguous().t() if u64.dim() == 2 else u64.float()
     M, info, f, nrhs, ms, prof, _ = run_workload(H, torch, w, prec, args.steps, args.warmup, args.prof_steps,
@@ -799,7 +864,8 @@ def main():
         "metric": METRIC, "value": round(value, 6), "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-core/f32"}[prec],
-        "data": "synthetic (seeded uniform grid, random u)",
+        "data": ("synthetic (seeded uniform grid, random u)" if w.grid == "uniform"
+                 else "synthetic (warped tensor grid, u = u*(x))"),
         "config": {"workload": w.name, "d": w.d, "n": w.n, "N": w.N, "kernel": KERNEL_LABEL.get(w.kernel, w.kernel),
                    "p": w.p, "leaf": w.leaf, "nrhs": nrhs, "precision": prec, "admissibility": "strong, eta=1",
                    "parallelism": "1 GPU", "autotuned": bool(args.tune)},
@@ -811,7 +877,7 @@ def main():
         variants = {}
         u32 = u64.float().t().contiguous().t() if u64.dim() == 2 else u64.float()
         for pr in ("fp64", "fp32", "bf16"):
-            if pr == prec:
+            if pr == prec or (pr == "bf16" and w.grid != "uniform"):
                 continue
             print(f"[bench] {w.name} {pr}: 5 timed steps", file=sys.stderr, flush=True)
             _, info3, f3, nr3, ms3, prof3, _ = run_workload(H, torch, w, pr, 5, 1, 2, M=M,
@@ -886,6 +952,8 @@ def main():
         sb = solve_block(H, torch, np, W)
         detail["w3d_exp_warp_n96_solve"] = sb
         out["solve"] = {"fp32_ir_s": sb["inner_fp32"]["seconds"], "fp64_s": sb["inner_fp64"]["seconds"],
+                        "fp32_product_ms": sb["products"]["fp32"]["ms"],
+                        "fp32_core_frac": sb["products"]["fp32"]["roofline"]["frac"],
                         "solves_per_s": sb["inner_fp32"]["solves_per_s"],
                         "res": float(f"{sb['inner_fp32']['rel_residual_fp64']:.3g}"),
                         "err_ustar": float(f"{sb['inner_fp32']['rel_err_vs_ustar']:.3g}")}

@@ -470,13 +470,31 @@ static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
     }
     std::stable_sort(groups.begin(), groups.end(),
                      [](const auto& a, const auto& b) { return a.first < b.first; });
+    // popularity of each offset: the number of the class's tiles whose list
+    // holds it.  Every tile walks its offsets from the most to the least
+    // popular, so the workgroups of one XCD, which run the class's tiles side
+    // by side, read the same cores (A operand) at about the same time and
+    // share them in L2; offsets only boundary tiles have come last.
+    std::vector<int> pop(lv.ncore, 0);
+    std::vector<std::vector<uint64_t>> unions;
     for (auto& gr : groups) {
       std::vector<uint64_t> u(words, 0);
       for (size_t q : gr.second)
         for (int w = 0; w < words; ++w) u[w] |= bits[q * words + w];
-      std::set<std::array<int, 3>> offs;
       for (int c = 0; c < lv.ncore; ++c)
-        if (u[c / 64] >> (c % 64) & 1) offs.insert({lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]});
+        if (u[c / 64] >> (c % 64) & 1) ++pop[c];
+      unions.push_back(std::move(u));
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      auto& gr = groups[gi];
+      const std::vector<uint64_t>& u = unions[gi];
+      std::vector<std::pair<int, std::array<int, 3>>> ord;   // (-popularity, offset)
+      for (int c = 0; c < lv.ncore; ++c)
+        if (u[c / 64] >> (c % 64) & 1)
+          ord.push_back({-pop[c], {lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]}});
+      std::sort(ord.begin(), ord.end());
+      std::vector<std::array<int, 3>> offs;
+      for (auto& po : ord) offs.push_back(po.second);
       // every member's own list must equal the tile list restricted to the domain
       for (size_t q : gr.second) {
         const int32_t t = boxes[q];

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import htlr_workloads as W
+from precision_checks import assert_reduced_close
 from oracle import dense, geometry, htlr
 
 pytestmark = pytest.mark.gpu
@@ -183,8 +184,8 @@ def test_reduced_precision_vs_fp64(torch, d, n, leaf, p, kernel, nrhs):
     u = np.random.default_rng(3).standard_normal((g.N, nrhs))
     M = _build(H, None, kernel, d, n, p, leaf, a)
     f64 = _gpu_matvec(torch, M, u, "fp64")
-    assert _rel(_gpu_matvec(torch, M, u, "fp32"), f64) <= FP32_TOL
-    assert _rel(_gpu_matvec(torch, M, u, "bf16"), f64) <= BF16_TOL
+    assert_reduced_close(_gpu_matvec(torch, M, u, "fp32"), f64, FP32_TOL)
+    assert_reduced_close(_gpu_matvec(torch, M, u, "bf16"), f64, BF16_TOL)
 
 
 def test_multi_rhs_equals_single(torch):

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import htlr_workloads as W
+from precision_checks import assert_reduced_close
 from oracle import geometry, htlr, quasi
 
 pytestmark = pytest.mark.gpu
@@ -129,8 +130,8 @@ def test_reduced_precision_vs_fp64(torch, d, n, m, leaf, p, kernel, nrhs):
     u = _u(gq, nrhs, 13)
     M = H.htlr_build_quasi(np.concatenate(nd), kernel, d, n, m, p, leaf, a=np.ones(gq.N))
     f64 = _gpu_matvec(torch, M, u, "fp64")
-    assert _rel(_gpu_matvec(torch, M, u, "fp32"), f64) <= FP32_TOL
-    assert _rel(_gpu_matvec(torch, M, u, "bf16"), f64) <= BF16_TOL
+    assert_reduced_close(_gpu_matvec(torch, M, u, "fp32"), f64, FP32_TOL)
+    assert_reduced_close(_gpu_matvec(torch, M, u, "bf16"), f64, BF16_TOL)
 
 
 def test_full_size_sampled(torch):
