@@ -138,10 +138,17 @@ def peak_for(step, prec):
     return ("mfma", {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16": PEAK["bf16_mfma"]}[prec])
 
 
+# Sources that define the product's kernels and work lists: a committed
+# counter summary is used only while these are unchanged (the solver, server,
+# transfer-form and no-allocation sources do not change a product's kernels).
+PRODUCT_SOURCES = ("htlr_build.hip", "htlr_core_mfma.hip", "htlr_device.h", "htlr_handle.h", "htlr_internal.h",
+                   "htlr_matvec.hip", "htlr_near_leaves.hip", "htlr_near_rows.hip", "htlr_plan.cpp")
+
+
 def source_digest():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2508_05958_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in PRODUCT_SOURCES:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -125,17 +125,41 @@ struct Structure {
 // requests in one tick run as one grouped product (product_group), whose up
 // contractions and down expansions cover every member's columns in one
 // launch per level.
+// A grouped product replayed from a captured hipGraph: one per composition
+// (members, their column counts, precision, tick slot).  The column tables
+// of that composition live in its own pinned and device buffers, which the
+// captured copy reads on every replay.
+struct GroupGraph {
+  hipGraphExec_t exec = nullptr;
+  PinnedBuf ht;
+  DevBuf td;
+  int grouped = 0;                 // grouped launches per replay
+  ~GroupGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+constexpr size_t kMaxGroupGraphs = 64;   // captured compositions kept per group
+
 struct Group {
   hipStream_t stream = nullptr;
   int cols = 0;                    // columns of the batch buffers
   DevBuf U64, F64, U32, F32, ptrs, partial, tabs;
   PinnedBuf hptrs, htabs;
   size_t bytes = 0;
+  std::map<std::string, std::unique_ptr<GroupGraph>> graphs;
+  std::map<std::string, int> uses;
+  // graphs hold the addresses of the batch buffers and of the members' work
+  // buffers: dropped when either may change
+  void drop_graphs() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    graphs.clear();
+    uses.clear();
+  }
   ~Group() {
-    if (stream) {
-      (void)hipStreamSynchronize(stream);
-      (void)hipStreamDestroy(stream);
-    }
+    if (stream) (void)hipStreamSynchronize(stream);
+    graphs.clear();
+    if (stream) (void)hipStreamDestroy(stream);
   }
 };
 
@@ -215,6 +239,8 @@ struct ServerImpl {
         if (kv.second->active == 0 && (!victim || kv.second->last_use < victim->last_use)) victim = kv.second.get();
       if (!victim) return;
       used -= victim->bytes;
+      auto g = groups.find(victim->gkey);
+      if (g != groups.end()) g->second->drop_graphs();
       structs.erase(victim->key);
       ++st.evictions;
     }
@@ -515,7 +541,7 @@ struct ServerImpl {
       const size_t per = (size_t)N * cols * (sizeof(double) * 2 + (o.inner_prec != HTLR_FP64 ? sizeof(float) * 2 : 0));
       const size_t old = (size_t)N * G->cols * (sizeof(double) * 2 + (o.inner_prec != HTLR_FP64 ? sizeof(float) * 2 : 0));
       if (used - old + per > budget) return nullptr;
-      HTLR_HIP(hipStreamSynchronize(G->stream));
+      G->drop_graphs();
       G->U64.alloc((size_t)N * cols * sizeof(double));
       G->F64.alloc((size_t)N * cols * sizeof(double));
       if (o.inner_prec != HTLR_FP64) {
@@ -541,17 +567,57 @@ struct ServerImpl {
     HTLR_HIP(hipMemcpyAsync(dp, hp, C * sizeof(double*), hipMemcpyHostToDevice, G->stream));
     std::vector<htlr_matrix_impl*> As;
     for (Structure* S : Ss) As.push_back(S->A);
-    ColTab* th = reinterpret_cast<ColTab*>(G->htabs.p) + (size_t)slot * kTabSlots;
-    ColTab* td = G->tabs.as<ColTab>() + (size_t)slot * kTabSlots;
-    if (prec == HTLR_FP64) {
-      hipLaunchKernelGGL(k_gather_f64, dim3(vblocks(N)), dim3(256), 0, G->stream, dp, G->U64.as<double>(), N, C);
-      st.grouped_launches += product_group(As, cols, G->U64.ptr, G->F64.ptr, prec, G->stream, th, td);
-    } else {
+    // gather + grouped product with the given column-table buffers
+    auto launch = [&](ColTab* th, ColTab* td) -> int {
+      if (prec == HTLR_FP64) {
+        hipLaunchKernelGGL(k_gather_f64, dim3(vblocks(N)), dim3(256), 0, G->stream, dp, G->U64.as<double>(), N, C);
+        return product_group(As, cols, G->U64.ptr, G->F64.ptr, prec, G->stream, th, td);
+      }
       hipLaunchKernelGGL(k_gather_f32, dim3(vblocks(N)), dim3(256), 0, G->stream, dp, G->U32.as<float>(), N, C);
-      st.grouped_launches += product_group(As, cols, G->U32.ptr, G->F32.ptr, prec, G->stream, th, td);
-    }
+      return product_group(As, cols, G->U32.ptr, G->F32.ptr, prec, G->stream, th, td);
+    };
     ++st.fused_products;
     ++st.group_products;
+    if (o.use_graphs) {
+      std::ostringstream ks;
+      ks << prec << '|' << slot;
+      for (size_t i = 0; i < Ss.size(); ++i) ks << '|' << (const void*)Ss[i] << ':' << cols[i];
+      const std::string key = ks.str();
+      auto it = G->graphs.find(key);
+      if (it != G->graphs.end()) {
+        HTLR_HIP(hipGraphLaunch(it->second->exec, G->stream));
+        st.grouped_launches += it->second->grouped;
+        ++st.graph_launches;
+        return;
+      }
+      // first use runs eagerly (work lists and buffers exist afterwards);
+      // a composition seen again is captured with its own column tables
+      if (G->uses[key]++ > 0 && G->graphs.size() < kMaxGroupGraphs) {
+        auto g = std::make_unique<GroupGraph>();
+        g->ht.alloc((size_t)kTabSlots * sizeof(ColTab) / sizeof(double));
+        g->td.alloc((size_t)kTabSlots * sizeof(ColTab));
+        hipGraph_t graph = nullptr;
+        HTLR_HIP(hipStreamBeginCapture(G->stream, hipStreamCaptureModeRelaxed));
+        try {
+          g->grouped = launch(reinterpret_cast<ColTab*>(g->ht.p), g->td.as<ColTab>());
+        } catch (...) {
+          (void)hipStreamEndCapture(G->stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        HTLR_HIP(hipStreamEndCapture(G->stream, &graph));
+        const hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HTLR_HIP(ie);
+        HTLR_HIP(hipGraphLaunch(g->exec, G->stream));
+        st.grouped_launches += g->grouped;
+        ++st.graph_launches;
+        G->graphs[key] = std::move(g);
+        return;
+      }
+    }
+    st.grouped_launches += launch(reinterpret_cast<ColTab*>(G->htabs.p) + (size_t)slot * kTabSlots,
+                                  G->tabs.as<ColTab>() + (size_t)slot * kTabSlots);
   }
 
   void issue_group(Group* G, const std::vector<Structure*>& Ss, std::map<Structure*, std::vector<Req*>>& by) {

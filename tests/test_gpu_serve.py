@@ -133,20 +133,25 @@ def test_cross_structure_fusion(torch):
     _say("[gpu] server: cross-structure fusion on vs off")
     reqs = _grouped_requests(10)
     outs, stats = [], []
-    for fuse in (False, True):
-        S = H.Server(max_batch=4, inner_prec="fp32", use_graphs=True, group_fusion=fuse)
+    # unfused (graphs), fused eager, fused with grouped products replayed from graphs
+    for fuse, graphs in ((False, True), (True, False), (True, True)):
+        S = H.Server(max_batch=4, inner_prec="fp32", use_graphs=graphs, group_fusion=fuse)
         ids = [S.submit(**r) for r in reqs]
         res = _drain(S, list(ids))
         stats.append(S.stats())
         outs.append([res[i] for i in ids])
         S.close()
-    _say(f"[gpu]   fused: {stats[1]['group_products']} grouped products, {stats[1]['grouped_launches']} shared "
-         f"launches; unfused: {stats[0]['fused_products']} products")
+    _say(f"[gpu]   fused: {stats[2]['group_products']} grouped products, {stats[2]['grouped_launches']} shared "
+         f"launches, {stats[2]['graph_launches']} graph launches; unfused: {stats[0]['fused_products']} products")
     assert stats[0]["group_products"] == 0
     assert stats[1]["group_products"] > 0 and stats[1]["grouped_launches"] > 0
-    for (u0, i0), (u1, i1) in zip(*outs):
-        assert i0["status"] == 0 and i1["status"] == 0
+    assert stats[1]["graph_launches"] == 0
+    assert stats[2]["group_products"] > 0 and stats[2]["graph_launches"] > 0
+    assert stats[2]["grouped_launches"] == stats[1]["grouped_launches"]
+    for (u0, i0), (u1, i1), (u2, i2) in zip(*outs):
+        assert i0["status"] == 0 and i1["status"] == 0 and i2["status"] == 0
         assert np.array_equal(u0, u1)
+        assert np.array_equal(u1, u2)
     for k in (0, 1, 3):
         assert _residual(reqs[k], outs[1][k][0]) <= 2 * TOL
 
