@@ -443,17 +443,24 @@ struct ServerImpl {
     hipLaunchKernelGGL(k_dots_final, dim3((ncols + 63) / 64), dim3(64), 0, st, part, kRedB, ncols, dst);
   }
 
-  // refinement residual r = f - A x from column col of an FP64 product,
-  // its norm (and ||f|| the first time) copied to the host
+  // refinement residual r = f - A x from column col of an FP64 product (col
+  // null: x = 0, the request's first residual, r = f), its norm (and ||f||
+  // the first time) copied to the host
   void post_residual(Req* q, const double* col, hipStream_t st, double* part) {
     const int m = o.restart;
     const int64_t N = q->N;
-    hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, st, q->df, col, q->dr, N);
+    if (col)
+      hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, st, q->df, col, q->dr, N);
+    else
+      HTLR_HIP(hipMemcpyAsync(q->dr, q->df, N * sizeof(double), hipMemcpyDeviceToDevice, st));
     double* hd = q->hdev.as<double>();
     dots(st, part, N, q->dr, 1, q->dr, hd + 2 * (m + 1));
     if (q->fn < 0) dots(st, part, N, q->df, 1, q->df, hd + 2 * (m + 1) + 1);
     HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, st));
   }
+
+  // The first residual of a request (x = 0) needs no product: r = f.
+  static bool first_residual(const Req& q) { return !q.arnoldi && q.fn < 0; }
 
   // Arnoldi step: w = A V_k from column col64 (FP64 product) or col32 (inner
   // precision product), classical Gram-Schmidt twice, norm to the host
@@ -479,7 +486,11 @@ struct ServerImpl {
     const int64_t N = S->N;
     double* part = S->partial.as<double>();
     std::vector<Req*> R, K;
-    for (Req* q : members) (q->arnoldi ? K : R).push_back(q);
+    for (Req* q : members) {
+      if (q->arnoldi) K.push_back(q);
+      else if (first_residual(*q)) post_residual(q, nullptr, S->stream, part);
+      else R.push_back(q);
+    }
     // refinement residuals: r = f - A x (FP64)
     for (size_t s = 0; s < R.size(); s += o.max_batch) {
       const size_t e = std::min(R.size(), s + (size_t)o.max_batch);
@@ -515,7 +526,9 @@ struct ServerImpl {
     int nr = 0, nk = 0;
     for (Structure* S : Ss) {
       int r = 0, k = 0;
-      for (Req* q : by[S]) (q->arnoldi ? k : r)++;
+      for (Req* q : by[S])
+        if (q->arnoldi) ++k;
+        else if (!first_residual(*q)) ++r;
       if (r > o.max_batch || k > o.max_batch) return nullptr;
       nr += r;
       nk += k;
@@ -628,6 +641,9 @@ struct ServerImpl {
     }
     const int64_t N = Ss[0]->N;
     double* part = G->partial.as<double>();
+    for (Structure* S : Ss)
+      for (Req* q : by[S])
+        if (first_residual(*q)) post_residual(q, nullptr, G->stream, part);
     for (int phase = 0; phase < 2; ++phase) {
       // phase 0: refinement residuals (FP64); phase 1: Arnoldi steps (inner precision)
       std::vector<Structure*> mem;
@@ -637,7 +653,7 @@ struct ServerImpl {
       for (Structure* S : Ss) {
         int c = 0;
         for (Req* q : by[S])
-          if (q->arnoldi == (phase == 1)) {
+          if (q->arnoldi == (phase == 1) && !first_residual(*q)) {
             Q.push_back(q);
             src.push_back(phase == 0 ? q->dx : q->V + (int64_t)q->k * N);
             ++c;

@@ -200,10 +200,15 @@ extern "C" htlr_status htlr_solve(htlr_matrix A, const double* f, double* u, int
     }
     double rel = 1.0;
     for (int outer = 0;; ++outer) {
-      // r = f - A u with the FP64 product
-      S.matvec(HTLR_FP64, u, S.w.as<double>());
-      hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, st, f, S.w.as<double>(), S.r.as<double>(), N);
-      const double rn = S.norm(S.r.as<double>());
+      // r = f - A u with the FP64 product; the first time u = 0, so r = f
+      // exactly and the product is skipped
+      if (outer == 0) {
+        HTLR_HIP(hipMemcpyAsync(S.r.ptr, f, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else {
+        S.matvec(HTLR_FP64, u, S.w.as<double>());
+        hipLaunchKernelGGL(k_sub_to, dim3(vblocks(N)), dim3(256), 0, st, f, S.w.as<double>(), S.r.as<double>(), N);
+      }
+      const double rn = outer == 0 ? fn : S.norm(S.r.as<double>());
       if (!std::isfinite(rn)) fail(HTLR_ERR_NUMERIC, "residual is NaN/Inf");
       rel = rn / fn;
       inf.outer_iters = outer;
