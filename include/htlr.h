@@ -321,7 +321,8 @@ htlr_status htlr_profile_read(htlr_matrix A, htlr_profile_entry* out, int cap, i
  * are read from and appended to it, keyed by (d, n, p, leaf, kernel, grid,
  * nrhs, prec).  Allocates scratch vectors; synchronises the device. */
 typedef struct {
-  int ks_target;        /* workgroups the core apply aims for when splitting its reduction */
+  int ks_target;        /* workgroups the core apply aims for when splitting its reduction
+                           (0: automatic, at least 2048 and 4 per unsplit work item) */
   int near_kind;        /* 0: VALU row kernel, 1: matrix-core kernel */
   int near_waves;       /* waves per leaf of the VALU row kernel */
   int candidates;       /* variants timed (0: taken from the cache) */

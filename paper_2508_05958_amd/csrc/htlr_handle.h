@@ -129,7 +129,8 @@ struct Profiler {
 
 // Kernel variant choices for products of one shape (nrhs, precision).
 struct TuneParams {
-  int ks_target = 2048;              // matrix-core core apply: workgroups aimed for when splitting K
+  int ks_target = 0;                 // matrix-core core apply: workgroups aimed for when splitting K
+                                     // (0 automatic: at least 2048, and 4 per unsplit work item)
   int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel with
                                      // right-hand sides as columns, 2 with target leaves as columns,
                                      // 3 the generic uniform-grid kernel (no row reuse)

@@ -1872,7 +1872,7 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         const double ms = time_with(t);
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
-      for (int target : {512, 1024, 4096, 8192}) {
+      for (int target : {512, 1024, 2048, 4096, 8192}) {
         TuneParams t = best;
         t.ks_target = target;
         const double ms = time_with(t);
