@@ -544,7 +544,9 @@ struct ServerImpl {
       slot->partial.alloc((size_t)kRedB * (o.restart + 2) * sizeof(double));
       slot->tabs.alloc((size_t)2 * kTabSlots * sizeof(ColTab));
       slot->htabs.alloc((size_t)2 * kTabSlots * sizeof(ColTab) / sizeof(double));
-      slot->bytes = slot->ptrs.bytes + slot->partial.bytes + slot->tabs.bytes;
+      // (plus the column tables of up to kMaxGroupGraphs captured compositions)
+      slot->bytes = slot->ptrs.bytes + slot->partial.bytes + slot->tabs.bytes +
+                    kMaxGroupGraphs * (size_t)kTabSlots * sizeof(ColTab);
       used += slot->bytes;
     }
     Group* G = slot.get();
