@@ -102,7 +102,6 @@ def algorithmic_cost(info, w, nrhs, prec):
     """Per launch of each product step: algorithmic flops (no padding),
     algorithmic HBM bytes (each operand read once, each result written
     once), and, on tensor grids, the kernel evaluations the step makes."""
-    P = w.p ** w.d
     M = info["leaf_side"] ** w.d
     ev = 8 if prec == "fp64" else 4                      # vector and work-buffer element
     eg = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]         # core and staged source-tensor element
@@ -114,14 +113,16 @@ def algorithmic_cost(info, w, nrhs, prec):
         pairs = info["adm_pairs"][l]
         if not pairs:
             continue
+        r = info["level_rank"][l] or w.p                 # the level's Tucker rank (p unless truncated)
+        P = r ** w.d
         nbox = B ** w.d
         wbytes = nbox * P * nrhs
-        cost[f"up_l{l}"] = (2.0 * nbox * nrhs * sum(m ** (w.d - k) * w.p ** (k + 1) for k in range(w.d)),
+        cost[f"up_l{l}"] = (2.0 * nbox * nrhs * sum(m ** (w.d - k) * r ** (k + 1) for k in range(w.d)),
                             N * nrhs * ev + wbytes * eg, 0.0)
         cost[f"core_l{l}"] = (2.0 * pairs * P * P * nrhs,
                               info["unique_cores"][l] * P * P * eg + wbytes * eg + wbytes * ev,
                               float(pairs * P * P) if tensor else 0.0)
-        cost[f"down_l{l}"] = (2.0 * nbox * nrhs * sum(w.p ** (w.d - k) * m ** (k + 1) for k in range(w.d)),
+        cost[f"down_l{l}"] = (2.0 * nbox * nrhs * sum(r ** (w.d - k) * m ** (k + 1) for k in range(w.d)),
                               wbytes * ev + 2.0 * N * nrhs * ev, 0.0)
     return cost
 
@@ -615,10 +616,11 @@ def orth_block(H, torch, np, W, steps=10):
         if ref is None:
             ref = f.clone()
         info = M.info()
-        out["forms"][label] = {"rank": info["rank"], "build_s": round(build_s, 4), "device_bytes": info["device_bytes"],
+        out["forms"][label] = {"rank": info["rank"], "level_rank": info["level_rank"], "build_s": round(build_s, 4),
+                               "device_bytes": info["device_bytes"],
                                "ms_per_product": round(ms, 4),
                                "rel_diff_vs_interpolation": float(torch.linalg.norm(f - ref) / torch.linalg.norm(ref))}
-        print(f"[bench]   {label}: rank {info['rank']}, build {build_s:.3f} s, {ms:.3f} ms/product",
+        print(f"[bench]   {label}: level ranks {info['level_rank']}, build {build_s:.3f} s, {ms:.3f} ms/product",
               file=sys.stderr, flush=True)
         M.free()
         del f
@@ -898,6 +900,23 @@ def main():
                             "product_frac": r3["product_frac"]}
             detail[f"headline_{pr}"] = {"ms_per_step": ms3, "kernels": per3, "roofline": r3, "err_vs_fp64": err}
             del f3, f3d
+        if w.grid == "uniform":
+            # Alg. 4.1's QR step with QRCP truncation at pivot tolerance 0.1:
+            # each level keeps its own rank (here the finest level drops below p)
+            print(f"[bench] {w.name} fp64, QRCP-truncated factors (rank_tol 0.1): 5 timed steps", file=sys.stderr,
+                  flush=True)
+            Mq = H.htlr_build(None, w.kernel, w.d, w.n, w.p, w.leaf, a=w.a(), precisions=["fp64"],
+                              orthonormalize="qrcp", rank_tol=0.1)
+            _, infq, fq, nrq, msq, profq, _ = run_workload(H, torch, w, "fp64", 5, 1, 2, M=Mq, ut=u64)
+            err = float(torch.linalg.norm(fq - f_ref) / torch.linalg.norm(f_ref))
+            rq, perq = roofline(infq, w, "fp64", nrq, profq, msq, w.name + "_qrcp")
+            variants["fp64_qrcp_0.1"] = {"Gpt_s": round(w.N * nrq / (msq * 1e-3) / 1e9, 5), "ms": round(msq, 3),
+                                         "level_rank": infq["level_rank"], "err_vs_interpolation": float(f"{err:.3g}"),
+                                         "kernel": rq["kernel"], "frac": rq["frac"], "product_frac": rq["product_frac"]}
+            detail["headline_fp64_qrcp_0.1"] = {"ms_per_step": msq, "kernels": perq, "roofline": rq,
+                                                "level_rank": infq["level_rank"], "err_vs_interpolation": err}
+            Mq.free()
+            del fq
         out["variants"] = variants
     M.free()
     del f, f_ref, uh, u64
@@ -945,7 +964,7 @@ def main():
         print("[bench] orthonormal and QRCP-truncated forms (Alg. 4.1 QR step)", file=sys.stderr, flush=True)
         ob = orth_block(H, torch, np, W)
         detail["w3d_invr_n64_orth"] = ob
-        out["orth"] = {k: {"rank": v["rank"], "ms": v["ms_per_product"]} for k, v in ob["forms"].items()}
+        out["orth"] = {k: {"level_rank": v["level_rank"], "ms": v["ms_per_product"]} for k, v in ob["forms"].items()}
         torch.cuda.empty_cache()
     if not args.no_quasi:
         print("[bench] quasi-uniform grid through a uniform one (T Ahat S)", file=sys.stderr, flush=True)

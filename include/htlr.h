@@ -100,13 +100,11 @@ typedef struct {
                                as W, Q with G <- G x_1 R ... x_{d+1} T ...; the
                                same operator up to rounding;
                             2: QR with column pivoting truncated at rank_tol
-                               (Sec. 2.1): a factor of numerical rank r < p
-                               keeps r columns.  One rank serves all levels (the
-                               largest level rank; smaller ones are padded with
-                               zero columns), so cores shrink to r^d x r^d only
-                               when every level's factor has rank <= r (for
-                               example p above the box side at every level
-                               with admissible leaves)                          */
+                               (Sec. 2.1): each level keeps its own rank r_l,
+                               the number of pivots kept for its factor, and
+                               its cores shrink to r_l^d x r_l^d (levels whose
+                               boxes are at least p points wide keep p unless
+                               rank_tol is loose)                              */
   double rank_tol;       /* orthonormalize = 2: keep pivots with
                             |R_kk| > rank_tol |R_00|; <= 0 selects 1e-13       */
   const double* edges;   /* host, d*(n+1) cell edges per dimension, dimension-
@@ -286,8 +284,11 @@ typedef struct {
   size_t device_bytes;                /* what htlr_footprint reports                    */
   double diag0;                       /* D_0 = K_00 |Omega_0| (uniform: every D_i)       */
   int uniform_m;                      /* htlr_build_quasi handles: m; otherwise 0        */
-  int rank;                           /* Tucker rank of the stored factors and cores (p
-                                         unless QRCP truncated it)                       */
+  int rank;                           /* largest level rank of the stored factors and
+                                         cores (p unless the QR step truncated it)        */
+  int level_rank[16];                 /* Tucker rank of each level 0..15 with admissible
+                                         leaves (its cores are level_rank^d squared);
+                                         0 for levels without admissible leaves          */
 } htlr_info_t;
 
 htlr_status htlr_info(htlr_matrix A, htlr_info_t* info);

@@ -56,7 +56,7 @@ class _Info(ctypes.Structure):
                 ("levels", ctypes.c_int), ("uniform", ctypes.c_int), ("adm_pairs", ctypes.c_int64 * 16),
                 ("unique_cores", ctypes.c_int64 * 16), ("near_pairs", ctypes.c_int64),
                 ("device_bytes", ctypes.c_size_t), ("diag0", ctypes.c_double), ("uniform_m", ctypes.c_int),
-                ("rank", ctypes.c_int)]
+                ("rank", ctypes.c_int), ("level_rank", ctypes.c_int * 16)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -286,7 +286,8 @@ class HTLRMatrix:
         return {"d": i.d, "n": i.n, "p": i.p, "leaf_side": i.leaf_side, "levels": i.levels,
                 "uniform": bool(i.uniform), "adm_pairs": list(i.adm_pairs[: i.levels + 1]),
                 "unique_cores": list(i.unique_cores[: i.levels + 1]), "near_pairs": i.near_pairs,
-                "device_bytes": i.device_bytes, "diag0": i.diag0, "uniform_m": i.uniform_m, "rank": i.rank}
+                "device_bytes": i.device_bytes, "diag0": i.diag0, "uniform_m": i.uniform_m, "rank": i.rank,
+                "level_rank": list(i.level_rank[: i.levels + 1])}
 
     def workspace_bytes(self, nrhs=1, prec="fp64") -> int:
         b = ctypes.c_size_t()

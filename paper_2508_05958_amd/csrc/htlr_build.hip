@@ -347,14 +347,12 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
     bd.upload_f32(A.T32, T);
   }
 
-  // Alg. 4.1's QR step (uniform grids: one factor per level).  One rank r
-  // serves every level, the largest level rank; W and R of a level with a
-  // smaller rank are padded with zero columns and rows (exact).
+  // Alg. 4.1's QR step (uniform grids: one factor per level).  Each level
+  // keeps its own rank: QRCP truncates a level's factor to its numerical
+  // rank, and that level's cores become rank^d x rank^d.
   std::vector<std::vector<double>> orthW(A.L + 1), orthR(A.L + 1);
-  int rank = p;
+  std::vector<int> rl(A.L + 1, p);
   if (A.orth) {
-    rank = 0;
-    std::vector<int> rl(A.L + 1, 0);
     std::vector<double> ch(p);
     for (int l = 0; l <= A.L; ++l) {
       if (pl.adm[l].nnz() == 0) continue;
@@ -364,22 +362,9 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
       for (int i = 0; i < m; ++i) xs[i] = (i + 0.5) * A.h;
       lagrange_matrix(xs.data(), m, ch.data(), p, U.data());
       rl[l] = orth_factor(U, m, p, A.orth == 2, A.rank_tol, &orthW[l], &orthR[l]);
-      rank = std::max(rank, rl[l]);
-    }
-    if (rank == 0) rank = p;
-    for (int l = 0; l <= A.L; ++l) {
-      if (rl[l] == 0 || rl[l] == rank) continue;
-      const int m = pl.m[l];
-      std::vector<double> W((size_t)m * rank, 0.0), R((size_t)rank * p, 0.0);
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < rl[l]; ++j) W[(size_t)i * rank + j] = orthW[l][(size_t)i * rl[l] + j];
-      std::copy(orthR[l].begin(), orthR[l].end(), R.begin());
-      orthW[l].swap(W);
-      orthR[l].swap(R);
     }
   }
-  int Pr = 1;
-  for (int k = 0; k < d; ++k) Pr *= rank;
+  int rank_max = 0, P_max = 0;
 
   // admissible leaves, factors and cores per level
   A.levels.clear();
@@ -390,11 +375,16 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
     lv.level = l;
     lv.B = pl.B[l];
     lv.m = pl.m[l];
+    lv.rank = rl[l];
+    lv.P = 1;
+    for (int k = 0; k < d; ++k) lv.P *= lv.rank;
     lv.nbox = 1;
     for (int k = 0; k < d; ++k) lv.nbox *= lv.B;
     lv.npairs = pl.adm[l].nnz();
     if (lv.npairs == 0) continue;
-    const int m = lv.m, B = lv.B;
+    rank_max = std::max(rank_max, lv.rank);
+    P_max = std::max(P_max, lv.P);
+    const int m = lv.m, B = lv.B, rank = lv.rank, Pr = lv.P;
     bd.upload(lv.ptr, pl.adm[l].ptr);
     bd.upload(lv.src, pl.adm[l].src);
     if (A.uniform) {
@@ -518,9 +508,13 @@ static void build_impl(htlr_matrix_impl& A, Builder& bd, const double* a_host) {
       }
     }
   }
-  // products use the stored rank
-  A.rank = rank;
-  A.P = Pr;
+  // the handle's rank and P: the largest over the levels with admissible leaves
+  if (rank_max == 0) {
+    rank_max = p;
+    P_max = P;
+  }
+  A.rank = rank_max;
+  A.P = P_max;
 }
 
 static void init_handle(htlr_matrix_impl& A, const double* points, int kernel, int d, int n, int p,
@@ -615,6 +609,7 @@ htlr_status htlr_info(htlr_matrix A, htlr_info_t* info) {
     for (int l = 0; l <= S.L && l < 16; ++l) {
       info->adm_pairs[l] = S.plan.adm[l].nnz();
       info->unique_cores[l] = S.levels[l].ncore;
+      info->level_rank[l] = S.levels[l].npairs > 0 ? S.levels[l].rank : 0;
     }
     info->near_pairs = S.plan.near.nnz();
     info->device_bytes = A->device_bytes;

@@ -346,11 +346,18 @@ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 
 }  // namespace
 
-// Whether the matrix-core path serves this matrix and precision.
-bool core_mfma_ok(const htlr_matrix_impl& A, int prec) {
-  if (!A.uniform || A.P < 64) return false;
+// Whether the matrix-core path serves this level of the matrix and precision.
+bool core_mfma_ok(const htlr_matrix_impl& A, const LevelData& lv, int prec) {
+  if (!A.uniform || lv.P < 64) return false;
   const int E = prec == HTLR_FP64 ? 2 : (prec == HTLR_FP32 ? 4 : 8);
-  return A.P % E == 0;
+  return lv.P % E == 0;
+}
+
+// Whether it serves at least one level.
+bool core_mfma_any(const htlr_matrix_impl& A, int prec) {
+  for (const LevelData& lv : A.levels)
+    if (lv.npairs > 0 && core_mfma_ok(A, lv, prec)) return true;
+  return false;
 }
 
 // Measured at 128^3 x 16 right-hand sides (level 4): tile-major items make
@@ -541,17 +548,17 @@ static int core_mfma_nb(int nrhs, int bnt) {
 // than 128-row blocks do (192 < p^d <= 224).
 // Cores of at most 64 rows (p^d <= 64, e.g. p = 4 in 3D, p = 8 in 2D) take
 // 64-row tiles: 7 = 64x64, 6 = 64x128 (no padded half of a 128-row tile).
-static int narrow_variant(const htlr_matrix_impl& A, int prec) {
-  if (A.P <= 64) return 7;
-  return (prec == HTLR_FP64 && A.P > 192 && A.P <= 224) ? 4 : 2;
+static int narrow_variant(const LevelData& lv, int prec) {
+  if (lv.P <= 64) return 7;
+  return (prec == HTLR_FP64 && lv.P > 192 && lv.P <= 224) ? 4 : 2;
 }
 
 static int pick_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
   if (A.cur.tile >= 1 && A.cur.tile <= 7) return A.cur.tile;
   const int64_t class_boxes = lv.nbox >> A.d;
-  if (class_boxes * nrhs <= 64) return narrow_variant(A, prec);
-  if (A.P <= 64) return 6;
-  if (prec == HTLR_BF16_CORE && A.P >= 256) return class_boxes * nrhs >= 256 ? 5 : 3;
+  if (class_boxes * nrhs <= 64) return narrow_variant(lv, prec);
+  if (lv.P <= 64) return 6;
+  if (prec == HTLR_BF16_CORE && lv.P >= 256) return class_boxes * nrhs >= 256 ? 5 : 3;
   return 1;
 }
 
@@ -741,7 +748,7 @@ static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& 
 // their columns and the per-pair partial buffer stays modest.
 static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
-  const size_t partial = (size_t)lv.npairs * nrhs * A.P * esz;
+  const size_t partial = (size_t)lv.npairs * nrhs * lv.P * esz;
   if (A.cur.core_mode == 1) return false;
   if (A.cur.core_mode == 2) return partial <= ((size_t)1 << 31);
   const int64_t class_boxes = lv.nbox >> A.d;
@@ -753,7 +760,7 @@ static bool use_offset_major(const htlr_matrix_impl& A, const LevelData& lv, int
 static int offset_major_variant(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, int prec) {
   if (A.cur.tile >= 1 && A.cur.tile <= 7) return A.cur.tile;
   const int64_t avg = lv.npairs / std::max(lv.ncore, 1);
-  return avg * nrhs <= 128 ? narrow_variant(A, prec) : (A.P <= 64 ? 6 : 1);
+  return avg * nrhs <= 128 ? narrow_variant(lv, prec) : (lv.P <= 64 ? 6 : 1);
 }
 
 void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* W, void* H, const void* zero,
@@ -768,10 +775,10 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     int bmt, bnt;
     variant_shape(var, prec, &bmt, &bnt);
     const int nb = core_mfma_nb(nrhs, bnt);
-    const int nmb = (A.P + bmt - 1) / bmt;
+    const int nmb = (lv.P + bmt - 1) / bmt;
     LevelData::OffsetTiles& T = offset_tiles_for(A, lv, nb, nmb, A.ws.frozen);
     const size_t esz = prec == HTLR_FP64 ? 8 : 4;
-    const size_t need = (size_t)T.npairs * nrhs * A.P * esz;
+    const size_t need = (size_t)T.npairs * nrhs * lv.P * esz;
     if (pairs.bytes < need) {
       if (A.ws.frozen) fail(HTLR_ERR_INVALID, "pair buffer exceeds the reserved size");
       pairs.alloc(need);
@@ -779,15 +786,15 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     void* Hp = pairs.ptr;
 #define HTLR_LVO(TE, GPTR)                                                                                         \
   switch (var) {                                                                                                 \
-    case 2: launch_variant_out<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
-    case 4: launch_variant_out<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs,  \
+    case 2: launch_variant_out<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs, lv.B, st); break;   \
+    case 4: launch_variant_out<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs,  \
                                                              lv.B, st); break;                                       \
-    case 5: launch_variant_out<TE, 256, WideCols<TE>::value>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs,   \
+    case 5: launch_variant_out<TE, 256, WideCols<TE>::value>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs,   \
                                                             lv.B, st); break;                                        \
-    case 3: launch_variant_out<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;  \
-    case 6: launch_variant_out<TE, 64, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;   \
-    case 7: launch_variant_out<TE, 64, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break;    \
-    default: launch_variant_out<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, A.P, nrhs, lv.B, st); break; \
+    case 3: launch_variant_out<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs, lv.B, st); break;  \
+    case 6: launch_variant_out<TE, 64, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs, lv.B, st); break;   \
+    case 7: launch_variant_out<TE, 64, 64>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs, lv.B, st); break;    \
+    default: launch_variant_out<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hp, T, lv.P, nrhs, lv.B, st); break; \
   }
     if (prec == HTLR_BF16_CORE) {
       HTLR_LVO(uint16_t, lv.Gm16.as<uint16_t>());
@@ -798,7 +805,7 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
     }
 #undef HTLR_LVO
     HTLR_HIP(hipGetLastError());
-    const int64_t per_box = (int64_t)nrhs * A.P;
+    const int64_t per_box = (int64_t)nrhs * lv.P;
     if (prec == HTLR_FP64)
       hipLaunchKernelGGL(k_reduce_pairs<double>, dim3((unsigned)lv.nbox), dim3(256), 0, st, (const double*)Hp,
                          (double*)H, T.rptr.as<int64_t>(), per_box);
@@ -814,12 +821,12 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
   const int nb = core_mfma_nb(nrhs, bnt);
   LevelData::Tiles& T = tiles_for(A, lv, nb);
   if (T.ntile == 0) return;
-  const int nmb = (A.P + bmt - 1) / bmt;
+  const int nmb = (lv.P + bmt - 1) / bmt;
   const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
   if (T.ntile >= (1 << 19) || nmb > 63) fail(HTLR_ERR_UNSUPPORTED, "matrix-core work list too large");
   LevelData::Tiles::Items& I = items_for(T, ks, nmb, core_item_order(A, prec), A.ws.frozen);
   const size_t esz = prec == HTLR_FP64 ? 8 : 4;
-  const int64_t helems = lv.nbox * (int64_t)nrhs * A.P;
+  const int64_t helems = lv.nbox * (int64_t)nrhs * lv.P;
   void* Hout = H;
   if (ks > 1) {
     const size_t need = (size_t)helems * ks * esz;
@@ -835,19 +842,19 @@ void launch_core_mfma(htlr_matrix_impl& A, LevelData& lv, int prec, const void* 
 #define HTLR_LV(TE, GPTR)                                                                                          \
   switch (var) {                                                                                                 \
     case 2: launch_variant<TE, 128, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
-                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+                                        lv.P, nrhs, nb, lv.B, st); break;                                         \
     case 4: launch_variant<TE, NarrowRows<TE>::value, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
-                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+                                        lv.P, nrhs, nb, lv.B, st); break;                                         \
     case 5: launch_variant<TE, 256, WideCols<TE>::value>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
-                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+                                        lv.P, nrhs, nb, lv.B, st); break;                                         \
     case 3: launch_variant<TE, 256, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems, \
-                                         A.P, nrhs, nb, lv.B, st); break;                                        \
+                                         lv.P, nrhs, nb, lv.B, st); break;                                        \
     case 6: launch_variant<TE, 64, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,  \
-                                        A.P, nrhs, nb, lv.B, st); break;                                         \
+                                        lv.P, nrhs, nb, lv.B, st); break;                                         \
     case 7: launch_variant<TE, 64, 64>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks, helems,   \
-                                       A.P, nrhs, nb, lv.B, st); break;                                          \
+                                       lv.P, nrhs, nb, lv.B, st); break;                                          \
     default: launch_variant<TE, 128, 128>(GPTR, (const TE*)W, (const TE*)zero, Hout, tau, ptr, off, I, ks,       \
-                                          helems, A.P, nrhs, nb, lv.B, st); break;                               \
+                                          helems, lv.P, nrhs, nb, lv.B, st); break;                               \
   }
   if (prec == HTLR_BF16_CORE) {
     HTLR_LV(uint16_t, lv.Gm16.as<uint16_t>());
@@ -882,26 +889,26 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
       A.cur = find_tune(A, c, prec);
       if (use_near_leaves(A, c, prec, false))
         nparts_need = std::max(nparts_need, near_leaves_shape(A, c, prec, false).parts_bytes);
-      if (!A.uniform || !core_mfma_ok(A, HTLR_FP64)) continue;
+      if (!A.uniform) continue;
       const size_t esz = prec == HTLR_FP64 ? 8 : 4;
       for (LevelData& lv : A.levels) {
-        if (lv.npairs == 0) continue;
+        if (lv.npairs == 0 || !core_mfma_ok(A, lv, HTLR_FP64)) continue;
         const int l = lv.level;
         if (use_offset_major(A, lv, c, prec)) {
           int bmt, bnt;
           variant_shape(offset_major_variant(A, lv, c, prec), prec, &bmt, &bnt);
-          offset_tiles_for(A, lv, core_mfma_nb(c, bnt), (A.P + bmt - 1) / bmt, false);
-          pairs_need[l] = std::max(pairs_need[l], (size_t)lv.npairs * c * A.P * esz);
+          offset_tiles_for(A, lv, core_mfma_nb(c, bnt), (lv.P + bmt - 1) / bmt, false);
+          pairs_need[l] = std::max(pairs_need[l], (size_t)lv.npairs * c * lv.P * esz);
           continue;
         }
         int bmt, bnt;
         variant_shape(pick_variant(A, lv, c, prec), prec, &bmt, &bnt);
         LevelData::Tiles& T = tiles_for(A, lv, core_mfma_nb(c, bnt));
         if (T.ntile == 0) continue;
-        const int nmb = (A.P + bmt - 1) / bmt;
+        const int nmb = (lv.P + bmt - 1) / bmt;
         const int ks = pick_ksplit(T.ntile * nmb, T.maxlist, A.cur.ks_target);
         items_for(T, ks, nmb, core_item_order(A, prec), false);
-        if (ks > 1) parts_need[l] = std::max(parts_need[l], (size_t)lv.nbox * c * A.P * ks * esz);
+        if (ks > 1) parts_need[l] = std::max(parts_need[l], (size_t)lv.nbox * c * lv.P * ks * esz);
       }
     }
   }

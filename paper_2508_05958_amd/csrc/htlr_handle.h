@@ -52,6 +52,7 @@ struct DevBuf {
 // One level of the cluster tree that carries admissible leaves.
 struct LevelData {
   int level = 0, B = 0, m = 0;
+  int rank = 0, P = 0;               // Tucker rank of the level's factors and cores (P = rank^d)
   int64_t nbox = 0, npairs = 0;
   DevBuf ptr, src, cid;              // CSR of admissible leaves; core id per entry (uniform)
   DevBuf U64, V64, U32, V32;         // factors: uniform [m][p]; tensor [d][B][m][p]
@@ -176,7 +177,7 @@ struct htlr_matrix_impl {
   int adm_kind = 0, gl_order = 0, precisions = 7;
   int orth = 0;                      // Alg. 4.1's QR step: 0 none, 1 QR, 2 QRCP (truncated)
   double rank_tol = 1e-13;
-  int rank = 0;                      // Tucker rank of stored factors and cores (P = rank^d)
+  int rank = 0;                      // largest level rank (P = rank^d); each level keeps its own
   double h = 0, w0 = 0, D0 = 0;
   int device = 0;
   Grid grid;
@@ -234,7 +235,8 @@ struct ProfScope {
   }
 };
 
-bool core_mfma_ok(const htlr_matrix_impl& A, int prec);
+bool core_mfma_ok(const htlr_matrix_impl& A, const LevelData& lv, int prec);
+bool core_mfma_any(const htlr_matrix_impl& A, int prec);
 // Work-item order of the matrix-core core apply for this precision (the
 // choice in A.cur, or the automatic one).
 int core_item_order(const htlr_matrix_impl& A, int prec);

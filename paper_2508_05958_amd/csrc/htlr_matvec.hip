@@ -1139,9 +1139,9 @@ size_t workspace_bytes(const htlr_matrix_impl& A, int nrhs, int prec) {
   size_t tot = 0;
   for (const LevelData& lv : A.levels) {
     if (lv.npairs == 0) continue;
-    size_t cnt = (size_t)lv.nbox * nrhs * A.P;
+    size_t cnt = (size_t)lv.nbox * nrhs * lv.P;
     tot += 2 * ((cnt * sizeof(double) + 255) & ~size_t(255));
-    tot += up_part_elems(lv, nrhs, A.P, A.d) * sizeof(double);
+    tot += up_part_elems(lv, nrhs, lv.P, A.d) * sizeof(double);
   }
   return tot;
 }
@@ -1162,10 +1162,10 @@ void ensure_workspace(htlr_matrix_impl& A, int nrhs, int prec) {
   ws.bytes = 0;
   for (const LevelData& lv : A.levels) {
     if (lv.npairs == 0) continue;
-    size_t cnt = (size_t)lv.nbox * nrhs * A.P;
+    size_t cnt = (size_t)lv.nbox * nrhs * lv.P;
     ws.W[lv.level].alloc(cnt * sizeof(double));
     ws.H[lv.level].alloc(cnt * sizeof(double));
-    ws.UP[lv.level].alloc(up_part_elems(lv, nrhs, A.P, A.d) * sizeof(double));
+    ws.UP[lv.level].alloc(up_part_elems(lv, nrhs, lv.P, A.d) * sizeof(double));
     ws.bytes += ws.W[lv.level].bytes + ws.H[lv.level].bytes + ws.UP[lv.level].bytes;
   }
   ws.zero.alloc((size_t)A.P * sizeof(double));
@@ -1211,7 +1211,7 @@ TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec) {
 enum UpKind { kUpGeneric = 0, kUpSmall3d = 1, kUpBox2d = 2, kUpRows2d = 3 };
 
 static int up_kind(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, size_t tsize) {
-  const int d = A.d, lm = lv.m, p = A.rank;
+  const int d = A.d, lm = lv.m, p = lv.rank;
   const int nch = level_chunks(lv, nrhs, d);
   if (d == 2 && nch == 1 && lm <= 64) return kUpBox2d;
   const size_t per3 = (size_t)lm * lm * lm + (size_t)lm * lm * p + (size_t)lm * p * p;
@@ -1221,7 +1221,7 @@ static int up_kind(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, siz
 }
 
 static int down_kind(const htlr_matrix_impl& A, const LevelData& lv, int nrhs, size_t tsize) {
-  const int d = A.d, lm = lv.m, p = A.rank, P = A.P;
+  const int d = A.d, lm = lv.m, p = lv.rank, P = lv.P;
   const int nch = level_chunks(lv, nrhs, d);
   const size_t per3d = (size_t)P + (size_t)lm * p * p + (size_t)lm * lm * p;
   if (d == 3 && nch == 1 && lm <= 16 && per3d * tsize <= kLdsBudget) return kUpSmall3d;
@@ -1240,7 +1240,7 @@ static bool groupable_kind(int k) { return k == kUpSmall3d || k == kUpBox2d; }
 template <typename T, typename TW>
 static void launch_up(htlr_matrix_impl& A, LevelData& lv, const T* u, TW* W, T* upart, int nrhs, hipStream_t ls,
                       const ColTab* tab) {
-  const int d = A.d, p = A.rank, P = A.P, n = A.n;
+  const int d = A.d, p = lv.rank, P = lv.P, n = A.n;
   const int lm = lv.m, lB = lv.B;
   const bool f64 = std::is_same<T, double>::value;
   const T* V = f64 ? (const T*)lv.V64.ptr : (const T*)lv.V32.ptr;
@@ -1299,14 +1299,14 @@ static void launch_up(htlr_matrix_impl& A, LevelData& lv, const T* u, TW* W, T* 
 template <typename T>
 static void launch_core(htlr_matrix_impl& A, LevelData& lv, const void* W, T* H, const void* zero, int nrhs, int prec,
                         hipStream_t ls, bool noalloc) {
-  const int d = A.d, p = A.rank, P = A.P, pm1 = A.p - 1;
+  const int d = A.d, p = lv.rank, P = lv.P, pm1 = A.p - 1;
   const int lB = lv.B;
   const bool f64 = std::is_same<T, double>::value;
   if (prec == HTLR_BF16_CORE) {
     if constexpr (!std::is_same<T, double>::value) {
       if (!A.uniform) fail(HTLR_ERR_UNSUPPORTED, "bfloat16 cores need a uniform grid");
       if (!lv.Gm16.ptr) fail(HTLR_ERR_UNSUPPORTED, "matrix built without bfloat16 cores");
-      if (!noalloc && core_mfma_ok(A, prec)) {
+      if (!noalloc && core_mfma_ok(A, lv, prec)) {
         launch_core_mfma(A, lv, prec, W, H, zero, nrhs, ls);
       } else {
         const int rc = pick_rc(nrhs, 0, (size_t)P * sizeof(float));
@@ -1318,7 +1318,7 @@ static void launch_core(htlr_matrix_impl& A, LevelData& lv, const void* W, T* H,
                                                 lv.cid.as<int32_t>(), P, nrhs));
       }
     }
-  } else if (A.uniform && !noalloc && core_mfma_ok(A, prec)) {
+  } else if (A.uniform && !noalloc && core_mfma_ok(A, lv, prec)) {
     launch_core_mfma(A, lv, prec, W, H, zero, nrhs, ls);
   } else if (A.uniform) {
     const T* G = f64 ? (const T*)lv.Gm64.ptr : (const T*)lv.Gm32.ptr;
@@ -1455,7 +1455,7 @@ static void launch_near(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int pre
 template <typename T>
 static void launch_down(htlr_matrix_impl& A, LevelData& lv, const T* H, T* f, int nrhs, hipStream_t st,
                         const ColTab* tab) {
-  const int d = A.d, p = A.rank, P = A.P, n = A.n;
+  const int d = A.d, p = lv.rank, P = lv.P, n = A.n;
   const int lm = lv.m, lB = lv.B;
   const bool f64 = std::is_same<T, double>::value;
   const T* U = f64 ? (const T*)lv.U64.ptr : (const T*)lv.U32.ptr;
@@ -1596,11 +1596,11 @@ static int run_group(const std::vector<htlr_matrix_impl*>& As, const std::vector
   const int64_t N = A0.N;
   for (size_t g = 0; g < G; ++g) {
     const htlr_matrix_impl& A = *As[g];
-    if (A.d != A0.d || A.n != A0.n || A.leaf != A0.leaf || A.rank != A0.rank || A.orth != A0.orth || !A.uniform ||
+    if (A.d != A0.d || A.n != A0.n || A.leaf != A0.leaf || A.orth != A0.orth || !A.uniform ||
         A.quasi || A.levels.size() != A0.levels.size())
       fail(HTLR_ERR_INVALID, "grouped product: matrices do not share their factors");
     for (size_t l = 0; l < A.levels.size(); ++l)
-      if ((A.levels[l].npairs > 0) != (A0.levels[l].npairs > 0))
+      if ((A.levels[l].npairs > 0) != (A0.levels[l].npairs > 0) || A.levels[l].rank != A0.levels[l].rank)
         fail(HTLR_ERR_INVALID, "grouped product: matrices differ in their levels");
     check_shape<T>(A);
     ensure_workspace(*As[g], cols[g], prec);
@@ -1706,10 +1706,10 @@ size_t carve_workview(const htlr_matrix_impl& A, int nrhs, char* base, WorkView*
   };
   for (const LevelData& lv : A.levels) {
     if (lv.npairs == 0) continue;
-    const size_t cnt = (size_t)lv.nbox * nrhs * A.P;
+    const size_t cnt = (size_t)lv.nbox * nrhs * lv.P;
     void* W = take(cnt * sizeof(double));
     void* H = take(cnt * sizeof(double));
-    const size_t up = up_part_elems(lv, nrhs, A.P, A.d) * sizeof(double);
+    const size_t up = up_part_elems(lv, nrhs, lv.P, A.d) * sizeof(double);
     void* UP = up ? take(up) : nullptr;
     if (wv) {
       wv->W[lv.level] = W;
@@ -1784,9 +1784,16 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     htlr_tune_result res{};
     // cache lookup
     char key[256];
+    std::string ranks;                  // level ranks, when the QR step truncated any
+    bool truncated = false;
+    for (const LevelData& lv : A->levels)
+      if (lv.npairs > 0) {
+        ranks += (ranks.empty() ? "_r" : ".") + std::to_string(lv.rank);
+        truncated = truncated || lv.rank != A->p;
+      }
+    if (!truncated) ranks.clear();
     std::snprintf(key, sizeof(key), "d%d_n%d_p%d_leaf%d_k%d_%s_eta%.6g_adm%d_nrhs%d_prec%d%s", A->d, A->n, A->p, A->leaf,
-                  A->kid, A->uniform ? "uniform" : "tensor", A->eta2, A->adm_kind, nrhs, (int)prec,
-                  A->rank != A->p ? ("_r" + std::to_string(A->rank)).c_str() : "");
+                  A->kid, A->uniform ? "uniform" : "tensor", A->eta2, A->adm_kind, nrhs, (int)prec, ranks.c_str());
     const char* cache = std::getenv("HTLR_TUNE_CACHE");
     if (cache && *cache) {
       FILE* fp = std::fopen(cache, "r");
@@ -1859,7 +1866,7 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
     TuneParams best;                    // defaults
     res.ms_default = time_with(best);
     double best_ms = res.ms_default;
-    if (core_mfma_ok(*A, prec)) {
+    if (core_mfma_any(*A, prec)) {
       for (int mode : {1, 2}) {
         TuneParams t = best;
         t.core_mode = mode;

@@ -10,7 +10,9 @@ import sys
 import numpy as np
 import pytest
 
+import htlr_workloads as W
 from oracle import geometry, htlr
+from oracle.tree import block_leaves
 from precision_checks import assert_reduced_close
 
 pytestmark = pytest.mark.gpu
@@ -32,6 +34,19 @@ def torch():
 
 def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _oracle_level_ranks(O, levels):
+    """Per level, the rank O2's QR step keeps for one admissible block of
+    that level (every block of a level has the same factors on a uniform
+    grid); 0 where the level has no admissible block."""
+    out = [0] * (levels + 1)
+    for kind, tau, sigma in block_leaves(O.tree, O.adm):
+        if kind == "A" and out[tau.level] == 0:
+            U, V, G = O.tlr_block(tau, sigma)
+            assert len({x.shape[1] for x in U + V}) == 1
+            out[tau.level] = U[0].shape[1]
+    return out
 
 
 def _gpu_matvec(torch, M, u, prec="fp64"):
@@ -82,9 +97,11 @@ def test_qrcp_exact_truncation(torch, d, n, leaf, p, rank):
     M = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a, orthonormalize="qrcp")
     info = M.info()
     assert (info["p"], info["rank"]) == (p, rank)
+    O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp")
+    assert info["level_rank"] == _oracle_level_ranks(O, info["levels"])
     f = _gpu_matvec(torch, M, u)
     assert _rel(f, htlr.HTLR(g, "inv_r", p, leaf, a).matvec(u)) <= FP64_TOL
-    assert _rel(f, htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp").matvec(u)) <= FP64_TOL
+    assert _rel(f, O.matvec(u)) <= FP64_TOL
     assert_reduced_close(_gpu_matvec(torch, M, u, "fp32"), f, 1e-5)
 
 
@@ -105,6 +122,74 @@ def test_qrcp_truncated_rank_cuts_cores(torch):
     O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp", rank_tol=0.3)
     assert _rel(f, O.matvec(u)) <= FP64_TOL
     assert 1e-5 < _rel(f, _gpu_matvec(torch, Mr, u)) < 5e-2
+
+
+@pytest.mark.parametrize("d,n,leaf,p,tol,ranks", [
+    (2, 64, 4, 6, 1e-13, [0, 0, 6, 6, 4]),      # exact: the finest boxes are 4 < p wide
+    (2, 64, 8, 6, 0.3, [0, 0, 6, 4]),           # loose: only the finest level truncates
+    (3, 32, 4, 6, 1e-13, [0, 0, 6, 4])])        # 3D: 216-row and 64-row cores on the matrix cores
+def test_qrcp_level_ranks(torch, d, n, leaf, p, tol, ranks):
+    """Each level keeps the rank its own factor's QRCP gives (Sec. 2.1): the
+    handle's level ranks are O2's per block, its stored cores shrink level by
+    level, and the product equals O2 built the same way."""
+    import paper_2508_05958_amd as H
+    _say(f"[gpu] QRCP level ranks d={d} n={n} leaf={leaf} p={p} tol={tol}")
+    g = geometry.uniform_grid(d, n)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    rng = np.random.default_rng(24)
+    u = np.asfortranarray(rng.standard_normal((g.N, 2)))
+    M = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a, orthonormalize="qrcp", rank_tol=tol)
+    Mr = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a)
+    info = M.info()
+    assert info["level_rank"] == ranks
+    assert info["rank"] == max(ranks)
+    assert M.info()["device_bytes"] < Mr.info()["device_bytes"]
+    f = _gpu_matvec(torch, M, u)
+    fr = _gpu_matvec(torch, Mr, u)
+    if d == 2:
+        O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp", rank_tol=tol)
+        assert _oracle_level_ranks(O, info["levels"]) == ranks
+        assert _rel(f, O.matvec(u)) <= FP64_TOL
+    else:
+        # 3D n = 32: O2 on sampled leaves (its whole product takes minutes)
+        O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp", rank_tol=tol)
+        leaves = O.tree.leaves()
+        pick = [leaves[i] for i in W.sample_leaves(5, len(leaves), 4)]
+        fo = O.matvec(u, pick)
+        assert _rel(f[O.leaf_rows(pick)], fo) <= FP64_TOL
+    if tol < 1e-10:
+        assert _rel(f, fr) <= 1e-13                 # exact truncation: the same operator
+    else:
+        assert 1e-6 < _rel(f, fr) < 5e-2
+    assert_reduced_close(_gpu_matvec(torch, M, u, "fp32"), f, 1e-5)
+    assert_reduced_close(_gpu_matvec(torch, M, u, "bf16"), f, 5e-3)
+
+
+def test_qrcp_level_ranks_64_cubed(torch):
+    """64^3, p = 6, leaf 8^3, pivot tolerance 0.3: level 2 keeps rank 6 and
+    level 3 drops to 4 (its 8-point boxes), so level 3's cores are 64 x 64
+    instead of 216 x 216.  FP64 against O2 on sampled leaves; FP32 and
+    bfloat16-core against FP64."""
+    import paper_2508_05958_amd as H
+    d, n, leaf, p, tol = 3, 64, 8, 6, 0.3
+    _say(f"[gpu] QRCP level ranks 64^3 p={p} tol={tol}")
+    g = geometry.uniform_grid(d, n)
+    a = np.ones(g.N)
+    u = np.asfortranarray(np.random.default_rng(25).standard_normal((g.N, 4)))
+    M = H.htlr_build(None, "inv_r", d, n, p, leaf, a=a, orthonormalize="qrcp", rank_tol=tol)
+    info = M.info()
+    assert info["level_rank"] == [0, 0, 6, 4]
+    assert info["unique_cores"][3] > 0
+    f = _gpu_matvec(torch, M, u)
+    O = htlr.HTLR(g, "inv_r", p, leaf, a, orthonormalize="qrcp", rank_tol=tol)
+    assert _oracle_level_ranks(O, info["levels"]) == [0, 0, 6, 4]
+    leaves = O.tree.leaves()
+    pick = [leaves[i] for i in W.sample_leaves(6, len(leaves), 3)]
+    fo = O.matvec(u, pick)
+    assert _rel(f[O.leaf_rows(pick)], fo) <= FP64_TOL
+    assert_reduced_close(_gpu_matvec(torch, M, u, "fp32"), f, 1e-5)
+    assert_reduced_close(_gpu_matvec(torch, M, u, "bf16"), f, 5e-3)
+    M.free()
 
 
 def test_orthonormal_needs_uniform_grid(torch):
