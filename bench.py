@@ -398,6 +398,20 @@ PAPER_SHAPES = [
 ]
 
 
+def dense_row_errors(M, torch, w, u64, fs, size=1000):
+    """e_apply;rand as Sec. 5 defines it, for each product in fs: the relative
+    2-norm error against the uncompressed Nystrom product (eq. 1.3-1.4) on
+    `size` seeded rows (all right-hand sides), those rows formed on the GPU
+    by htlr_exact_rows in FP64."""
+    pick = torch.tensor(w.rows(min(size, w.N)), device="cuda")
+    if u64.dim() == 1:
+        ex = M.exact_rows(u64, pick)
+    else:
+        ex = torch.cat([M.exact_rows(u64[:, c:c + 8], pick) for c in range(0, u64.shape[1], 8)], dim=1)
+    nex = torch.linalg.norm(ex)
+    return {k: float(f"{float(torch.linalg.norm(f.double()[pick] - ex) / nex):.3g}") for k, f in fs.items()}
+
+
 def paper_tables_block(H, torch, np):
     """Build time t_c (host planning + GPU construction, synchronised), device
     bytes m_h and the FP64 product time at the paper's shapes.  Accuracy at
@@ -867,6 +881,7 @@ def main():
     roof, per = roofline(info, w, prec, nrhs, prof, ms, w.name)
     f_ref = f.double() if prec != "fp64" else f
     f_host = f_ref.detach().cpu().numpy()
+    dense_fs = {prec: f}
     detail = {"headline": {"workload": w.name, "prec": prec, "ms_per_step": ms, "kernels": per, "roofline": roof,
                            "build_s": build_s, "device_bytes": info["device_bytes"]}}
     out = {
@@ -899,7 +914,8 @@ def main():
                             "err_vs_fp64": float(f"{err:.3g}"), "kernel": r3["kernel"], "frac": r3["frac"],
                             "product_frac": r3["product_frac"]}
             detail[f"headline_{pr}"] = {"ms_per_step": ms3, "kernels": per3, "roofline": r3, "err_vs_fp64": err}
-            del f3, f3d
+            dense_fs[pr] = f3
+            del f3d
         if w.grid == "uniform":
             # Alg. 4.1's QR step with QRCP truncation at pivot tolerance 0.1:
             # each level keeps its own rank (here the finest level drops below p)
@@ -915,9 +931,15 @@ def main():
                                          "kernel": rq["kernel"], "frac": rq["frac"], "product_frac": rq["product_frac"]}
             detail["headline_fp64_qrcp_0.1"] = {"ms_per_step": msq, "kernels": perq, "roofline": rq,
                                                 "level_rank": infq["level_rank"], "err_vs_interpolation": err}
+            dense_fs["fp64_qrcp_0.1"] = fq
             Mq.free()
-            del fq
         out["variants"] = variants
+    # every product of this block against the dense operator on 1000 seeded rows
+    e_dense = dense_row_errors(M, torch, w, u64, dense_fs)
+    out["e_apply_rand"] = e_dense
+    detail["headline"]["e_apply_rand"] = e_dense
+    print(f"[bench]   e_apply;rand on 1000 rows (vs the uncompressed operator): {e_dense}", file=sys.stderr, flush=True)
+    del dense_fs
     M.free()
     del f, f_ref, uh, u64
     torch.cuda.empty_cache()
