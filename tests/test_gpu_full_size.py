@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import htlr_workloads as W
+from level_ranks import oracle_level_ranks as _oracle_level_ranks
 from oracle import dense, geometry, htlr
 
 pytestmark = pytest.mark.gpu
@@ -117,6 +118,41 @@ def test_cfg3_reduced_precision_against_fp64(torch, cfg3, prec, tol):
     assert tot <= tol
     assert col2.max() <= tol
     assert colinf.max() <= tol
+
+
+def test_cfg3_qrcp_truncated_product(torch, cfg3):
+    """The benchmark's QRCP-truncated form of the same workload (Alg. 4.1's
+    QR step with pivot tolerance 0.1, one rank per level: 8, 8, 6 on levels
+    2-4): level ranks as O2's QRCP keeps them, the FP64 product against O2
+    built alike on sampled leaves, and its distance from the interpolation
+    form bounded as the truncation allows."""
+    import paper_2508_05958_amd as H
+    w = cfg3["w"]
+    _say(f"[gpu] {w.name}: QRCP rank_tol 0.1 build and product")
+    M = H.htlr_build(None, w.kernel, 3, w.n, w.p, w.leaf, a=cfg3["a"], precisions=["fp64"],
+                     orthonormalize="qrcp", rank_tol=0.1)
+    info = M.info()
+    u64 = torch.tensor(cfg3["u"].T.copy(), dtype=torch.float64, device="cuda").t()
+    fq = M.matvec(u64, prec="fp64").cpu().numpy()
+    M.free()
+    assert info["level_rank"] == [0, 0, 8, 8, 6]
+    g = geometry.uniform_grid(3, w.n)
+    O = htlr.HTLR(g, w.kernel, w.p, w.leaf, cfg3["a"], orthonormalize="qrcp", rank_tol=0.1)
+    leaves = O.tree.leaves()
+    idx = W.sample_leaves(w.seed, len(leaves), 2)
+    pick = [leaves[i] for i in idx]
+    assert _oracle_level_ranks(O, 4, under=pick[0]) == info["level_rank"]
+    _say(f"[gpu]   vs O2 with QRCP on leaves {list(idx)}")
+    fo = O.matvec(cfg3["u"], pick)
+    fg = fq[O.leaf_rows(pick)]
+    rel = np.linalg.norm(fg - fo) / np.linalg.norm(fo)
+    _say(f"[gpu]   rel err vs O2 {rel:.3e}")
+    assert rel <= 1e-12
+    for c in range(w.nrhs):
+        assert np.max(np.abs(fg[:, c] - fo[:, c])) / np.max(np.abs(fo[:, c])) <= 1e-12
+    trunc = np.linalg.norm(fq - cfg3["f64_host"]) / np.linalg.norm(cfg3["f64_host"])
+    _say(f"[gpu]   distance from the interpolation form {trunc:.2e}")
+    assert 1e-6 < trunc < 1e-3
 
 
 def test_cfg4_full_size_product_and_solve(torch):

@@ -12,7 +12,7 @@ import pytest
 
 import htlr_workloads as W
 from oracle import geometry, htlr
-from oracle.tree import block_leaves
+from level_ranks import oracle_level_ranks as _oracle_level_ranks
 from precision_checks import assert_reduced_close
 
 pytestmark = pytest.mark.gpu
@@ -34,19 +34,6 @@ def torch():
 
 def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
-
-
-def _oracle_level_ranks(O, levels):
-    """Per level, the rank O2's QR step keeps for one admissible block of
-    that level (every block of a level has the same factors on a uniform
-    grid); 0 where the level has no admissible block."""
-    out = [0] * (levels + 1)
-    for kind, tau, sigma in block_leaves(O.tree, O.adm):
-        if kind == "A" and out[tau.level] == 0:
-            U, V, G = O.tlr_block(tau, sigma)
-            assert len({x.shape[1] for x in U + V}) == 1
-            out[tau.level] = U[0].shape[1]
-    return out
 
 
 def _gpu_matvec(torch, M, u, prec="fp64"):
