@@ -11,13 +11,62 @@ namespace htlr {
 
 __device__ __constant__ static const double kPolyADev[3] = {0.50, 0.30, 0.20};
 
+// Double-precision pieces of the kernels, written for their bounded
+// arguments (finite s = r^2 > 0 of normal size; finite x <= 0 for e^x)
+// without the special-case handling of the general library functions.
+//
+// Reciprocal square root: the hardware estimate y0 (about 23 correct bits)
+// and two Newton steps y <- y (3/2 - (s/2) y^2), each doubling the correct
+// bits.
+__device__ __forceinline__ double rsqrt_f64(double s) {
+  const double hs = 0.5 * s;
+  double y = __builtin_amdgcn_rsq(s);
+  y = y * fma(-hs * y, y, 1.5);
+  return y * fma(-hs * y, y, 1.5);
+}
+
+// Square root: r0 = s y0 from the same estimate, then two Newton steps
+// r <- r + (y0/2)(s - r^2) (the residual s - r^2 formed exactly by FMA).
+__device__ __forceinline__ double sqrt_f64(double s) {
+  const double y = __builtin_amdgcn_rsq(s), hy = 0.5 * y;
+  double r = s * y;
+  r = fma(fma(-r, r, s), hy, r);
+  return fma(fma(-r, r, s), hy, r);
+}
+
+// e^x, x <= 0: Cody and Waite's reduction x = k ln 2 + f, k = rint(x / ln 2),
+// with ln 2 split into the double nearest it and the remainder, so that
+// |f| <= ln(2)/2; e^f by its Taylor polynomial of degree 13 (the truncation
+// is below 4e-18 relative), coefficients 1/n!, by Horner's rule; 2^k by
+// ldexp.  k is clamped at -1100, where the result is below 1e-300.
+struct TaylorExpCoeffs {
+  double c[14];
+  constexpr TaylorExpCoeffs() : c{} {
+    c[0] = 1.0;
+    for (int n = 1; n < 14; ++n) c[n] = c[n - 1] / n;
+  }
+};
+
+__device__ __forceinline__ double exp_neg_f64(double x) {
+  constexpr TaylorExpCoeffs T;
+  constexpr double kLog2e = 1.4426950408889634;      // 1 / ln 2
+  constexpr double kLn2 = 0.6931471805599453;        // ln 2, nearest double
+  constexpr double kLn2Lo = 2.3190468138462996e-17;  // ln 2 - kLn2
+  const double k = fmax(__builtin_rint(x * kLog2e), -1100.0);
+  const double f = fma(-k, kLn2Lo, fma(-k, kLn2, x));
+  double p = T.c[13];
+#pragma unroll
+  for (int n = 12; n >= 0; --n) p = fma(p, f, T.c[n]);
+  return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
 // Radial kernels as functions of r^2 (r = |x - y|).
 template <int KID>
 __device__ __forceinline__ double kr2(double r2, int d) {
-  if constexpr (KID == HTLR_K_INV_R) return 1.0 / sqrt(r2);
+  if constexpr (KID == HTLR_K_INV_R) return rsqrt_f64(r2);
   else if constexpr (KID == HTLR_K_NEG_LOG) return -0.5 * log(r2);
-  else if constexpr (KID == HTLR_K_EXP) return exp(-sqrt(r2));
-  else return exp(-r2 / (2.0 * d));
+  else if constexpr (KID == HTLR_K_EXP) return exp_neg_f64(-sqrt_f64(r2));
+  else return exp_neg_f64(r2 * (-0.5 / d));
 }
 
 // Single precision: the hardware reciprocal square root, square root, 2^x
