@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "htlr.h"
 
@@ -60,6 +61,48 @@ __device__ __forceinline__ double exp_neg_f64(double x) {
   return __builtin_amdgcn_ldexp(p, (int)k);
 }
 
+// e^x, x <= 0, by Tang's table-driven method: x = (64 m + j) ln(2)/64 + f
+// with j = 0..63 and |f| <= ln(2)/128, so that e^x = 2^m 2^(j/64) e^f; e^f - 1
+// by its Taylor polynomial of degree 5 (truncation below 4e-17).  tab holds
+// 2^(j/64), j = 0..63 (kExp2Frac64, usually staged in LDS by the caller).
+// The exponent is clamped as in exp_neg_f64.
+__device__ __forceinline__ double exp_neg_f64_tab(double x, const double* tab) {
+  constexpr double k64Log2e = 64.0 * 1.4426950408889634;      // 64 / ln 2
+  constexpr double kLn2_64 = 0.6931471805599453 / 64.0;       // ln(2)/64, high part (exact scaling)
+  constexpr double kLn2Lo_64 = 2.3190468138462996e-17 / 64.0;  // its remainder
+  const double k = fmax(__builtin_rint(x * k64Log2e), -70400.0);
+  const double f = fma(-k, kLn2Lo_64, fma(-k, kLn2_64, x));
+  const int ki = (int)k;
+  double q = fma(f, 1.0 / 120.0, 1.0 / 24.0);
+  q = fma(q, f, 1.0 / 6.0);
+  q = fma(q, f, 0.5);
+  q = fma(q, f, 1.0);
+  q = q * f;                                                  // e^f - 1
+  const double t = tab[ki & 63];
+  return __builtin_amdgcn_ldexp(fma(t, q, t), ki >> 6);
+}
+
+// 2^(j/64), j = 0..63, each the double nearest the exact value (computed to
+// 50 significant digits), and the LDS bytes a kernel stages it in.
+constexpr size_t kExpTabBytes = 64 * sizeof(double);
+__device__ constexpr double kExp2Frac64[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0};
+
 // Radial kernels as functions of r^2 (r = |x - y|).
 template <int KID>
 __device__ __forceinline__ double kr2(double r2, int d) {
@@ -110,6 +153,26 @@ template <int KID, typename T>
 __device__ __forceinline__ T kvec_c12(T dx0, T dx1, T dx2, T c12, int d, int pm1) {
   if constexpr (KID == HTLR_K_POLY_TEST) return kvec<KID, T>(dx0, dx1, dx2, d, pm1);
   else return kr2<KID>(fma(dx0, dx0, c12), d);
+}
+
+// Whether kvec_c12_t reads the table of 2^(j/64) for this kernel and type:
+// the exponential kernels in double precision.
+template <int KID, typename T>
+constexpr bool uses_exp_table() {
+  return std::is_same<T, double>::value && (KID == HTLR_K_EXP || KID == HTLR_K_GAUSS);
+}
+
+// kvec_c12, with e^x of the double-precision exponential kernels taken by
+// exp_neg_f64_tab from etab (the staged kExp2Frac64; unused otherwise).
+template <int KID, typename T>
+__device__ __forceinline__ T kvec_c12_t(T dx0, T dx1, T dx2, T c12, int d, int pm1, const double* etab) {
+  if constexpr (uses_exp_table<KID, T>()) {
+    const double r2 = fma(dx0, dx0, c12);
+    if constexpr (KID == HTLR_K_EXP) return exp_neg_f64_tab(-sqrt_f64(r2), etab);
+    else return exp_neg_f64_tab(r2 * (-0.5 / d), etab);
+  } else {
+    return kvec_c12<KID, T>(dx0, dx1, dx2, c12, d, pm1);
+  }
 }
 
 // bfloat16 stored as uint16_t; round to nearest even.

@@ -380,10 +380,14 @@ __global__ __launch_bounds__(kThreads) void k_near_tensor(
     const int64_t* __restrict__ nptr, const int32_t* __restrict__ nsrc, const double* __restrict__ x,
     const T* __restrict__ wdim, int d, int n, int m, int B, int nrhs, int pm1) {
   extern __shared__ unsigned char smem_raw[];
-  T* cs = reinterpret_cast<T*>(smem_raw);  // [3][m] source coordinates relative to the target box
+  constexpr bool kTab = uses_exp_table<KID, T>();
+  double* etab = reinterpret_cast<double*>(smem_raw);                // [64] 2^(j/64), exponential kernels in FP64
+  T* cs = reinterpret_cast<T*>(smem_raw + (kTab ? kExpTabBytes : 0));  // [3][m] source coordinates relative to the target box
   T* us = cs + 3 * m;                      // [RC][M] weighted source values
   const int M = (d == 3) ? m * m * m : m * m;
   const int tid = threadIdx.x;
+  if constexpr (kTab)
+    for (int i = tid; i < 64; i += kThreads) etab[i] = kExp2Frac64[i];
   const int tau = blockIdx.x;
   const int r0 = blockIdx.y * RC;
   const int64_t N = (d == 3) ? (int64_t)n * n * n : (int64_t)n * n;
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_near_tensor(
           for (int j0 = 0; j0 < m; ++j0, ++jj) {
             if (self && jj == li[q]) continue;
             T dx0 = xi[q][0] - cs[j0];
-            T kv = kvec_c12<KID, T>(dx0, dx1, dx2, c12, d, pm1);
+            T kv = kvec_c12_t<KID, T>(dx0, dx1, dx2, c12, d, pm1, etab);
 #pragma unroll
             for (int r = 0; r < RC; ++r) acc[q][r] += kv * us[r * M + jj];
           }
@@ -1017,10 +1021,14 @@ __global__ __launch_bounds__(kThreads) void k_core_tensor(
     const T* __restrict__ W, T* __restrict__ H, const double* __restrict__ cheb, const int64_t* __restrict__ ptr,
     const int32_t* __restrict__ src, int d, int p, int B, int nrhs, int pm1) {
   extern __shared__ unsigned char smem_raw[];
-  T* ws = reinterpret_cast<T*>(smem_raw);  // [RC][P]
+  constexpr bool kTab = uses_exp_table<KID, T>();
+  double* etab = reinterpret_cast<double*>(smem_raw);                // [64] 2^(j/64), exponential kernels in FP64
+  T* ws = reinterpret_cast<T*>(smem_raw + (kTab ? kExpTabBytes : 0));  // [RC][P]
   const int P = (d == 3) ? p * p * p : p * p;
   T* ce = ws + RC * P;                      // [3][p] source points relative to the target origin
   const int tid = threadIdx.x;
+  if constexpr (kTab)
+    for (int i = tid; i < 64; i += kThreads) etab[i] = kExp2Frac64[i];
   const int tau = blockIdx.x;
   const int r0 = blockIdx.y * RC;
   int tb[3] = {tau % B, (tau / B) % B, d == 3 ? tau / (B * B) : 0};
@@ -1062,7 +1070,7 @@ __global__ __launch_bounds__(kThreads) void k_core_tensor(
           T dx1 = xt[q][1] - ce[p + s1];
           const T c12 = dx1 * dx1 + dx2 * dx2;
           for (int s0 = 0; s0 < p; ++s0, ++s) {
-            T g = kvec_c12<KID, T>(xt[q][0] - ce[s0], dx1, dx2, c12, d, pm1);
+            T g = kvec_c12_t<KID, T>(xt[q][0] - ce[s0], dx1, dx2, c12, d, pm1, etab);
 #pragma unroll
             for (int r = 0; r < RC; ++r) acc[q][r] += g * ws[r * P + s];
           }
@@ -1330,9 +1338,10 @@ static void launch_core(htlr_matrix_impl& A, LevelData& lv, const void* W, T* H,
                                             sh, ls, (const T*)W, H, G, lv.ptr.as<int64_t>(), lv.src.as<int32_t>(),
                                             lv.cid.as<int32_t>(), P, nrhs));
   } else {
-    const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T), (size_t)P * sizeof(T));
+    const size_t tab = f64 ? kExpTabBytes : 0;   // reserved for the double-precision exponential kernels
+    const int rc = pick_rc(nrhs, 3 * (size_t)p * sizeof(T) + tab, (size_t)P * sizeof(T));
     const int nchunk = (nrhs + rc - 1) / rc;
-    size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T);
+    size_t sh = ((size_t)rc * P + 3 * (size_t)p) * sizeof(T) + tab;
     HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_core_tensor<KID, T, RC>), dim3(lv.nbox, nchunk),
                                                                    dim3(kThreads), sh, ls, (const T*)W, H,
                                                                    lv.cheb64.as<double>(), lv.ptr.as<int64_t>(),
@@ -1438,9 +1447,10 @@ static void launch_near(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int pre
   } else {
     const T* D = f64 ? (const T*)A.D64.ptr : (const T*)A.D32.ptr;
     const T* wd = f64 ? (const T*)A.w64.ptr : (const T*)A.w32.ptr;
-    const int rc = pick_rc(nrhs, 3 * (size_t)m * sizeof(T), (size_t)M * sizeof(T));
+    const size_t tab = f64 ? kExpTabBytes : 0;   // reserved for the double-precision exponential kernels
+    const int rc = pick_rc(nrhs, 3 * (size_t)m * sizeof(T) + tab, (size_t)M * sizeof(T));
     const int nchunk = (nrhs + rc - 1) / rc;
-    size_t sh = (3 * (size_t)m + (size_t)M * rc) * sizeof(T);
+    size_t sh = (3 * (size_t)m + (size_t)M * rc) * sizeof(T) + tab;
     HTLR_DISPATCH_KID(A.kid, HTLR_DISPATCH_RC(rc, hipLaunchKernelGGL((k_near_tensor<KID, T, RC>), dim3(nleaf, nchunk),
                                                                    dim3(kThreads), sh, st, u, f, a, D,
                                                                    A.near_ptr.as<int64_t>(), A.near_src.as<int32_t>(),

@@ -67,6 +67,8 @@ CASES = [
     (2, 48, 6, 8, "neg_log", "uniform", 1),       # p > leaf side
     (2, 24, 3, 4, "exp", "warped", 1),
     (3, 12, 3, 3, "inv_r", "warped", 2),
+    (3, 12, 3, 3, "gauss", "warped", 2),          # double-precision exponentials from the 2^(j/64) table
+    (3, 12, 3, 4, "exp", "warped", 5),
     (3, 16, 4, 4, "poly_test", "uniform", 1),
     (2, 24, 3, 4, "poly_test", "warped", 1),
     (3, 32, 8, 4, "inv_r", "uniform", 9),         # matrix-core near field in FP64
