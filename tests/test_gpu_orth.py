@@ -150,6 +150,12 @@ def test_qrcp_level_ranks(torch, d, n, leaf, p, tol, ranks):
         assert 1e-6 < _rel(f, fr) < 5e-2
     assert_reduced_close(_gpu_matvec(torch, M, u, "fp32"), f, 1e-5)
     assert_reduced_close(_gpu_matvec(torch, M, u, "bf16"), f, 5e-3)
+    # the no-allocation product carves its per-level buffers by each level's rank
+    ut = torch.tensor(u.T.copy(), device="cuda").t()
+    fz = torch.empty_like(ut)
+    M.matvec_noalloc(ut, fz, prec="fp64")
+    torch.cuda.synchronize()
+    assert _rel(fz.cpu().numpy(), f) <= 1e-13
 
 
 def test_qrcp_level_ranks_64_cubed(torch):
