@@ -643,7 +643,9 @@ def orth_block(H, torch, np, W, steps=10):
 
 def serve_block(H, np, W, count, rates=(0.5,)):
     """Serving: Poisson arrivals of mixed solve requests (d, n, kernel, p drawn
-    per request, f ~ N(0,1), a = 1 + x_1/2, relative residual 1e-8)."""
+    per request, f ~ N(0,1), a = 1 + x_1/2, relative residual 1e-8 in FP64).
+    Capacity with FP32, bfloat16-core and FP64 inner products (the first two
+    refined in FP64 to the same residual); the arrival-rate sweep with FP32."""
     A = {}
 
     def a_of(d, n):
@@ -696,7 +698,7 @@ def serve_block(H, np, W, count, rates=(0.5,)):
     reqs = W.request_stream(count, rate=1.0)
     fs = [r.rhs() for r in reqs]
     out = {"requests": count, "tol": 1e-8, "max_active": 256, "max_batch": 16}
-    for inner in ("fp32", "fp64"):
+    for inner in ("fp32", "bf16", "fp64"):
         S = H.Server(max_active=256, max_batch=16, inner_prec=inner, use_graphs=True)
         seen = {}
         for r in reqs:
@@ -1013,6 +1015,8 @@ def main():
         cap = vb["inner_fp32"]["capacity"]
         out["serving"] = {"requests": vb["requests"], "solves_per_s": cap["solves_per_s"],
                           "p50_s": cap["p50_latency_s"], "p99_s": cap["p99_latency_s"],
+                          "bf16_inner_solves_per_s": vb["inner_bf16"]["capacity"]["solves_per_s"],
+                          "fp64_inner_solves_per_s": vb["inner_fp64"]["capacity"]["solves_per_s"],
                           "rates": [_short(r, ("x_capacity", "solves_per_s", "p50_latency_s", "p99_latency_s"))
                                     for r in vb["inner_fp32"].get("rates", [])]}
         torch.cuda.empty_cache()

@@ -367,10 +367,15 @@ htlr_status htlr_plan_pairs(const double* points, const double* edges, int d, in
  *    memory_budget; idle structures are evicted least recently used first;
  *  - structures (the HTLR matrices) stay resident across requests, keyed by
  *    (points, kernel, d, n, p, leaf, eta2, admissibility, a);
- *  - every active request advances by one step of GMRES with FP64 iterative
- *    refinement (the method of htlr_solve, with the refinement residual taken
- *    after every GMRES cycle); the products of all requests on one structure
- *    in one tick are fused into a single multi-right-hand-side product,
+ *  - work is scheduled per unit (a group of structures, below, or one
+ *    structure), each idle or with one step in flight: a tick issues, for
+ *    every idle unit, one step of GMRES with FP64 iterative refinement for
+ *    each of its active requests (the method of htlr_solve, with the
+ *    refinement residual taken after every GMRES cycle), then waits until at
+ *    least one unit in flight has finished its step and advances that unit's
+ *    requests; so small structures take many steps while a large one
+ *    computes one product.  The products of all requests of a structure in
+ *    one step are fused into a single multi-right-hand-side product,
  *    optionally replayed from a captured hipGraph;
  *  - structures that share their factors (the uniform grid of the same d,
  *    n, p, leaf, eta2 and admissibility; e.g. different kernels) form a
@@ -428,8 +433,10 @@ typedef struct {
 htlr_status htlr_server_create(const htlr_server_opts* opts, htlr_server* out);
 /* Copies the request; *id identifies it in htlr_server_result. */
 htlr_status htlr_server_submit(htlr_server S, const htlr_request* req, int64_t* id);
-/* One scheduling tick (admission, one fused step per structure, retirement).
- * Returns the number of active and queued requests after the tick. */
+/* One scheduling tick: admission, one fused step issued for every idle unit,
+ * a wait until at least one unit's step has finished, the host updates of
+ * that unit's requests, retirement.  Returns the number of active and queued
+ * requests after the tick. */
 htlr_status htlr_server_step(htlr_server S, int* active, int* queued);
 /* For a finished request: copies u (host, N doubles, may be NULL) and its
  * info, then forgets the request.  For an unfinished one: fills info only

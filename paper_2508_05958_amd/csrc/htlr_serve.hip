@@ -1,17 +1,23 @@
 // Request server: continuous batching of solve requests (see include/htlr.h).
 //
-// Every tick:
+// Work is scheduled per unit: the structures of one group key (structures
+// that share their factors) or one structure alone.  A unit is idle or has
+// one step in flight.  Every tick:
 //   1. admission: queued requests enter first come first served while the
 //      device bytes of resident structures plus request state fit the budget
 //      (idle structures are evicted least recently used first);
-//   2. for each resident structure with active requests, on the structure's
-//      own stream: one fused FP64 product for the requests that need their
-//      refinement residual, and one fused inner-precision product for the
-//      requests in a GMRES cycle, followed by their per-request Arnoldi
-//      updates (classical Gram-Schmidt twice, on the device);
-//   3. one synchronisation per structure, then the host-side Givens updates
-//      and state transitions;
-//   4. finished requests are retired and their memory returned.
+//   2. for each idle unit with active requests, on its streams: one fused
+//      FP64 product for the requests that need their refinement residual, and
+//      one fused inner-precision product for the requests in a GMRES cycle,
+//      followed by their per-request Arnoldi updates (classical Gram-Schmidt
+//      twice, on the device); an event marks the end of the step;
+//   3. the host waits until at least one unit in flight has finished its
+//      step, then makes the host-side Givens updates and state transitions of
+//      the finished units' requests;
+//   4. finished requests are retired; their buffers go to a pool for the
+//      next admissions (freeing device memory would wait for the device).
+// So a unit advances at its own pace: small structures take many steps
+// while a large one computes one product.
 // Fused products gather the requests' vectors into a column-major batch and
 // call the HTLR product with nrhs = batch width; with use_graphs the gather
 // and the product are replayed from a hipGraph captured per (precision,
@@ -27,6 +33,7 @@
 #include <set>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "htlr_handle.h"
@@ -51,6 +58,11 @@ struct PinnedBuf {
   PinnedBuf() = default;
   PinnedBuf(const PinnedBuf&) = delete;
   PinnedBuf& operator=(const PinnedBuf&) = delete;
+  PinnedBuf(PinnedBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  PinnedBuf& operator=(PinnedBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
   void alloc(size_t count) {
     release();
     HTLR_HIP(hipHostMalloc((void**)&p, count * sizeof(double), hipHostMallocDefault));
@@ -86,6 +98,7 @@ struct Req {
   double *df = nullptr, *dx = nullptr, *dr = nullptr, *dd = nullptr, *V = nullptr;
   DevBuf hdev;             // device scalars: h pass 1 [m+1], h pass 2 [m+1], norm, y [m]
   PinnedBuf host;          // pinned mirror of hdev
+  bool ready = false;      // f and x = 0 written to the device (done when its unit is idle)
   // GMRES-IR state
   double fn = 0, rn = 0, beta = 0, rtol = 0;
   int outer = 0, inner = 0, k = 0;
@@ -98,6 +111,7 @@ struct Structure {
   std::string gkey;                // structures with equal gkey share their factors
   std::vector<double> points, a;   // build inputs, compared on a key hit
   hipEvent_t ev = nullptr;         // orders a group's work after this structure's stream
+  hipEvent_t done = nullptr;       // end of the structure's step in flight
   htlr_matrix A = nullptr;
   int64_t N = 0;
   size_t bytes = 0;
@@ -115,6 +129,7 @@ struct Structure {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (A) htlr_free(A);
     if (ev) (void)hipEventDestroy(ev);
+    if (done) (void)hipEventDestroy(done);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -143,6 +158,7 @@ constexpr size_t kMaxGroupGraphs = 64;   // captured compositions kept per group
 
 struct Group {
   hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;       // end of the group's step in flight
   int cols = 0;                    // columns of the batch buffers
   DevBuf U64, F64, U32, F32, ptrs, partial, tabs;
   PinnedBuf hptrs, htabs;
@@ -159,6 +175,7 @@ struct Group {
   ~Group() {
     if (stream) (void)hipStreamSynchronize(stream);
     graphs.clear();
+    if (done) (void)hipEventDestroy(done);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -179,6 +196,30 @@ struct ServerImpl {
   std::map<std::string, std::unique_ptr<Structure>> structs;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   htlr_server_stats_t st{};
+
+  // The step of one unit (the structures of a group key) on the device: the
+  // requests it advances and the events (one per stream used) that end it.
+  struct Flight {
+    std::vector<Req*> reqs;
+    std::vector<hipEvent_t> evs;
+  };
+  std::map<std::string, Flight> flights;   // by group key
+
+  // Buffers of retired requests, reused by later admissions: freeing device
+  // or pinned memory would wait for all work on the device.  The device
+  // bytes of dev_pool stay counted in used until the pool is released.
+  std::multimap<size_t, DevBuf> dev_pool;
+  std::vector<DevBuf> hdev_pool;
+  std::vector<PinnedBuf> host_pool;
+  size_t pooled = 0;
+
+  void release_pool() {
+    used -= pooled;
+    pooled = 0;
+    dev_pool.clear();
+    hdev_pool.clear();
+    host_pool.clear();
+  }
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -280,6 +321,7 @@ struct ServerImpl {
                              q.leaf, &bo, &S->A));
     HTLR_HIP(hipStreamCreate(&S->stream));
     HTLR_HIP(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
+    HTLR_HIP(hipEventCreateWithFlags(&S->done, hipEventDisableTiming));
     S->cap = o.max_batch;
     S->U64.alloc((size_t)S->N * S->cap * sizeof(double));
     S->F64.alloc((size_t)S->N * S->cap * sizeof(double));
@@ -328,7 +370,13 @@ struct ServerImpl {
       }
       Structure* S = it == structs.end() ? nullptr : it->second.get();
       const size_t sb = state_bytes(q.N);
-      size_t need = sb + (S ? 0 : structure_bytes(q));
+      auto pit = dev_pool.find(sb);
+      size_t need = (pit != dev_pool.end() ? 0 : sb) + (S ? 0 : structure_bytes(q));
+      if (used + need > budget && pooled) {
+        release_pool();
+        pit = dev_pool.end();
+        need = sb + (S ? 0 : structure_bytes(q));
+      }
       if (used + need > budget) evict_idle(need);
       if (used + need > budget) {
         if (active == 0 && structs.empty() && !S) {
@@ -351,9 +399,15 @@ struct ServerImpl {
         used += S->bytes;
       }
       q.S = S;
-      q.dev.alloc(sb);
+      if (pit != dev_pool.end()) {
+        q.dev = std::move(pit->second);
+        dev_pool.erase(pit);
+        pooled -= sb;
+      } else {
+        q.dev.alloc(sb);
+        used += sb;
+      }
       q.dev_bytes = sb;
-      used += sb;
       double* base = q.dev.as<double>();
       q.df = base;
       q.dx = base + q.N;
@@ -361,10 +415,19 @@ struct ServerImpl {
       q.dd = base + 3 * q.N;
       q.V = base + 4 * q.N;
       const int m = o.restart;
-      q.hdev.alloc((size_t)(3 * m + 4) * sizeof(double));
-      q.host.alloc((size_t)(3 * m + 4));
-      HTLR_HIP(hipMemcpyAsync(q.df, q.f.data(), q.N * sizeof(double), hipMemcpyHostToDevice, S->stream));
-      hipLaunchKernelGGL(k_zero, dim3(vblocks(q.N)), dim3(256), 0, S->stream, q.dx, q.N);
+      if (!hdev_pool.empty()) {
+        q.hdev = std::move(hdev_pool.back());
+        hdev_pool.pop_back();
+      } else {
+        q.hdev.alloc((size_t)(3 * m + 4) * sizeof(double));
+      }
+      if (!host_pool.empty()) {
+        q.host = std::move(host_pool.back());
+        host_pool.pop_back();
+      } else {
+        q.host.alloc((size_t)(3 * m + 4));
+      }
+      q.ready = false;   // f and x = 0 go to the device when the unit is next idle
       q.H.assign((size_t)(m + 1) * m, 0.0);
       q.cs.assign(m, 0.0);
       q.sn.assign(m, 0.0);
@@ -482,9 +545,19 @@ struct ServerImpl {
     HTLR_HIP(hipMemcpyAsync(q->host.p, hd, (3 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, st));
   }
 
+  // A request's f and x = 0 on the device, on its structure's stream (its
+  // unit is idle, so the copy does not wait behind a step in flight).
+  void init_req(Req* q) {
+    if (q->ready) return;
+    HTLR_HIP(hipMemcpyAsync(q->df, q->f.data(), q->N * sizeof(double), hipMemcpyHostToDevice, q->S->stream));
+    hipLaunchKernelGGL(k_zero, dim3(vblocks(q->N)), dim3(256), 0, q->S->stream, q->dx, q->N);
+    q->ready = true;
+  }
+
   void issue(Structure* S, std::vector<Req*>& members) {
     const int64_t N = S->N;
     double* part = S->partial.as<double>();
+    for (Req* q : members) init_req(q);
     std::vector<Req*> R, K;
     for (Req* q : members) {
       if (q->arnoldi) K.push_back(q);
@@ -539,6 +612,7 @@ struct ServerImpl {
     if (!slot) {
       slot = std::make_unique<Group>();
       HTLR_HIP(hipStreamCreate(&slot->stream));
+      HTLR_HIP(hipEventCreateWithFlags(&slot->done, hipEventDisableTiming));
       slot->ptrs.alloc((size_t)2 * kMaxGroupCols * sizeof(double*));
       slot->hptrs.alloc((size_t)2 * kMaxGroupCols);
       slot->partial.alloc((size_t)kRedB * (o.restart + 2) * sizeof(double));
@@ -636,6 +710,8 @@ struct ServerImpl {
   }
 
   void issue_group(Group* G, const std::vector<Structure*>& Ss, std::map<Structure*, std::vector<Req*>>& by) {
+    for (Structure* S : Ss)
+      for (Req* q : by[S]) init_req(q);
     // after each member's earlier work (refinement updates issued on its stream)
     for (Structure* S : Ss) {
       HTLR_HIP(hipEventRecord(S->ev, S->stream));
@@ -760,13 +836,17 @@ struct ServerImpl {
   void retire(Req& q) {
     Structure* S = q.S;
     q.result.resize(q.N);
+    // on the structure's own stream: a copy on the null stream would wait
+    // for every unit in flight
+    HTLR_HIP(hipMemcpyAsync(q.result.data(), q.dx, q.N * sizeof(double), hipMemcpyDeviceToHost, S->stream));
     HTLR_HIP(hipStreamSynchronize(S->stream));
-    HTLR_HIP(hipMemcpy(q.result.data(), q.dx, q.N * sizeof(double), hipMemcpyDeviceToHost));
     q.t_done = now();
-    q.dev.release();
+    dev_pool.emplace(q.dev_bytes, std::move(q.dev));
+    pooled += q.dev_bytes;
+    if ((int)hdev_pool.size() < o.max_active) hdev_pool.push_back(std::move(q.hdev));
+    if ((int)host_pool.size() < o.max_active) host_pool.push_back(std::move(q.host));
     q.hdev.release();
     q.host.release();
-    used -= q.dev_bytes;
     --S->active;
     S->last_use = q.t_done;
     q.S = nullptr;
@@ -775,37 +855,66 @@ struct ServerImpl {
   void step(int* active, int* queued) {
     ++st.ticks;
     admit();
+    // requests of idle units
     std::map<Structure*, std::vector<Req*>> by;
-    for (auto& kv : reqs)
-      if (kv.second->state == 1) by[kv.second->S].push_back(kv.second.get());
+    for (auto& kv : reqs) {
+      Req* q = kv.second.get();
+      if (q->state == 1 && !flights.count(q->S->gkey)) by[q->S].push_back(q);
+    }
     std::map<std::string, std::vector<Structure*>> bygroup;
     for (auto& g : by) bygroup[g.first->gkey].push_back(g.first);
-    std::vector<Group*> ran;
     for (auto& kv : bygroup) {
+      Flight fl;
       Group* G = (!o.no_group_fusion && kv.second.size() >= 2) ? group_for(kv.first, kv.second, by) : nullptr;
       if (G) {
         issue_group(G, kv.second, by);
-        ran.push_back(G);
-        continue;
+        HTLR_HIP(hipEventRecord(G->done, G->stream));
+        fl.evs.push_back(G->done);
+      } else {
+        for (Structure* S : kv.second) {
+          S->ptr_slot = 0;   // the unit is idle: its earlier pointer uploads are done
+          issue(S, by[S]);
+          HTLR_HIP(hipEventRecord(S->done, S->stream));
+          fl.evs.push_back(S->done);
+        }
       }
-      for (Structure* S : kv.second) {
-        S->ptr_slot = 0;   // the previous tick ended with a synchronisation
-        issue(S, by[S]);
-      }
+      for (Structure* S : kv.second)
+        for (Req* q : by[S]) fl.reqs.push_back(q);
+      flights[kv.first] = std::move(fl);
     }
-    for (auto& g : by) HTLR_HIP(hipStreamSynchronize(g.first->stream));
-    for (Group* G : ran) HTLR_HIP(hipStreamSynchronize(G->stream));
-    for (auto& g : by)
-      for (Req* q : g.second) {
+    // wait until at least one unit has finished its step
+    std::vector<std::string> ready;
+    while (!flights.empty()) {
+      for (auto& kv : flights) {
+        bool done = true;
+        for (hipEvent_t e : kv.second.evs) {
+          const hipError_t r = hipEventQuery(e);
+          if (r == hipErrorNotReady) {
+            done = false;
+            break;
+          }
+          HTLR_HIP(r);
+        }
+        if (done) ready.push_back(kv.first);
+      }
+      if (!ready.empty()) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    for (const std::string& k : ready) {
+      Flight fl = std::move(flights[k]);
+      flights.erase(k);
+      for (Req* q : fl.reqs) {
         finish_one(*q);
         if (q->state >= 2) retire(*q);
       }
+    }
     // batch buffers of groups with fewer than two resident structures go
+    // (not while a step of the group is in flight)
     for (auto it = groups.begin(); it != groups.end();) {
       int resident = 0;
       for (auto& kv : structs)
         if (kv.second->gkey == it->first) ++resident;
-      if (resident < 2) {
+      if (resident < 2 && !flights.count(it->first)) {
         used -= it->second->bytes;
         it = groups.erase(it);
       } else {
