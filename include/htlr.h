@@ -401,6 +401,10 @@ typedef struct {
   int use_graphs;       /* 1: replay fused products from captured hipGraphs */
   int autotune;         /* 1: time kernel variants per (structure, batch width, precision) */
   int no_group_fusion;  /* 1: never fuse the products of different structures */
+  double inner_tol;     /* relative residual an inner GMRES cycle aims at; <= 0: 1e-6 (FP32),
+                           1e-4 (BF16-core), 1e-12 (FP64).  A refinement step stops its
+                           cycle there (or at the request's own tolerance, if looser), or
+                           after restart iterations */
 } htlr_server_opts;
 
 typedef struct {

@@ -328,7 +328,7 @@ class HTLRMatrix:
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_size_t), ("max_active", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("restart", ctypes.c_int), ("inner_prec", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("no_group_fusion", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("no_group_fusion", ctypes.c_int), ("inner_tol", ctypes.c_double)]
 
 
 class _Request(ctypes.Structure):
@@ -374,12 +374,12 @@ class Server:
     """Continuous-batching request server (wraps htlr_server)."""
 
     def __init__(self, memory_budget=0, max_active=64, max_batch=16, restart=30, inner_prec="fp32",
-                 use_graphs=True, autotune=False, group_fusion=True):
+                 use_graphs=True, autotune=False, group_fusion=True, inner_tol=0.0):
         L = lib()
         _declare_server(L)
         o = _ServerOpts(int(memory_budget), max_active, max_batch, restart,
                         PRECISIONS[inner_prec] if isinstance(inner_prec, str) else int(inner_prec),
-                        1 if use_graphs else 0, 1 if autotune else 0, 0 if group_fusion else 1)
+                        1 if use_graphs else 0, 1 if autotune else 0, 0 if group_fusion else 1, float(inner_tol))
         h = _vp()
         _check(L.htlr_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

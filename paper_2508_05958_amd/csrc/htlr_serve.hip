@@ -503,7 +503,7 @@ struct ServerImpl {
   // with the partial-sum buffer part (kRedB x ncols doubles)
   void dots(hipStream_t st, double* part, int64_t N, const double* Vb, int ncols, const double* x, double* dst) {
     hipLaunchKernelGGL(k_dots_partial, dim3(kRedB), dim3(kRB), 0, st, Vb, N, ncols, x, N, part);
-    hipLaunchKernelGGL(k_dots_final, dim3((ncols + 63) / 64), dim3(64), 0, st, part, kRedB, ncols, dst);
+    hipLaunchKernelGGL(k_dots_final, dim3(ncols), dim3(kRB), 0, st, part, kRedB, ncols, dst);
   }
 
   // refinement residual r = f - A x from column col of an FP64 product (col
@@ -950,7 +950,11 @@ htlr_status htlr_server_create(const htlr_server_opts* opts, htlr_server* out) {
     if (S->o.restart > 200) fail(HTLR_ERR_INVALID, "restart too large");
     const int ip = S->o.inner_prec;
     if (ip != HTLR_FP64 && ip != HTLR_FP32 && ip != HTLR_BF16_CORE) fail(HTLR_ERR_INVALID, "unknown inner precision");
-    S->inner_tol = ip == HTLR_FP32 ? 1e-6 : (ip == HTLR_BF16_CORE ? 1e-2 : 1e-12);
+    // bfloat16-core products are within about 1e-5 of FP64 on these grids (the
+    // near field and the factors stay FP32), so a cycle can aim at 1e-4: two
+    // refinement steps reach 1e-8 (1e-2 took four, each with an FP64 product)
+    S->inner_tol = S->o.inner_tol > 0 ? S->o.inner_tol
+                                      : (ip == HTLR_FP32 ? 1e-6 : (ip == HTLR_BF16_CORE ? 1e-4 : 1e-12));
     S->budget = S->o.memory_budget;
     if (!S->budget) {
       size_t fr = 0, tot = 0;

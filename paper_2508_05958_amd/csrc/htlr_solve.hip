@@ -71,8 +71,8 @@ struct Solver {
   // out[c] = <V[:, c], x> for c < ncols (device), copied to host
   void dots(const double* Vb, int ncols, const double* x, double* host) {
     hipLaunchKernelGGL(k_dots_partial, dim3(kRedBlocks), dim3(kRB), 0, st, Vb, N, ncols, x, N, partial.as<double>());
-    hipLaunchKernelGGL(k_dots_final, dim3((ncols + 63) / 64), dim3(64), 0, st, partial.as<double>(), kRedBlocks,
-                       ncols, hdev.as<double>());
+    hipLaunchKernelGGL(k_dots_final, dim3(ncols), dim3(kRB), 0, st, partial.as<double>(), kRedBlocks, ncols,
+                       hdev.as<double>());
     HTLR_HIP(hipGetLastError());
     HTLR_HIP(hipMemcpyAsync(host, hdev.ptr, ncols * sizeof(double), hipMemcpyDeviceToHost, st));
     HTLR_HIP(hipStreamSynchronize(st));

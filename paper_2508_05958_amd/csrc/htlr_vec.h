@@ -34,12 +34,23 @@ __global__ __launch_bounds__(kRB) void k_dots_partial(const double* __restrict__
   }
 }
 
-__global__ void k_dots_final(const double* __restrict__ partial, int nb, int ncols, double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// out[c] = sum over b of partial[b][c]: one block of kRB threads per column,
+// each thread summing partials b = t, t + kRB, ..., then a fixed-order tree
+// in LDS (a thread per column summing all nb partials in turn was a chain of
+// nb dependent loads, tens of microseconds on every Gram-Schmidt step).
+__global__ __launch_bounds__(kRB) void k_dots_final(const double* __restrict__ partial, int nb, int ncols,
+                                                    double* __restrict__ out) {
+  __shared__ double red[kRB];
+  const int c = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * ncols + c];
-  out[c] = s;
+  for (int b = threadIdx.x; b < nb; b += kRB) s += partial[(int64_t)b * ncols + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kRB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
 }
 
 // w -= V[:, 0:ncols] h

@@ -184,6 +184,31 @@ def test_served_answer_equals_direct_solve(torch):
     assert checked == 3
 
 
+def test_bf16_core_inner_products(torch):
+    """Inner products with bfloat16 cores, refined in FP64: every request
+    reaches the FP64 tolerance (recomputed by O2), agrees with its FP32-inner
+    answer to the tolerance, and, with the default inner target 1e-4, takes
+    at most four refinement steps (the bfloat16-core product is far more
+    accurate than bfloat16 itself: factors and near field stay FP32)."""
+    import paper_2508_05958_amd as H
+    _say("[gpu] server: bfloat16-core inner products")
+    reqs = _requests(6)
+    outs = {}
+    for inner in ("fp32", "bf16"):
+        S = H.Server(max_batch=4, inner_prec=inner, use_graphs=True)
+        ids = [S.submit(**r) for r in reqs]
+        res = _drain(S, list(ids))
+        S.close()
+        outs[inner] = [res[i] for i in ids]
+    for k, ((u32, i32), (u16, i16)) in enumerate(zip(outs["fp32"], outs["bf16"])):
+        _say(f"[gpu]   request {k}: outer {i16['outer_iters']}, inner {i16['inner_iters']}, "
+             f"residual {i16['rel_residual']:.2e}")
+        assert i16["status"] == 0 and i16["rel_residual"] <= TOL
+        assert i16["outer_iters"] <= 4
+        assert np.linalg.norm(u16 - u32) / np.linalg.norm(u32) <= 10 * TOL
+        assert _residual(reqs[k], u16) <= 2 * TOL
+
+
 def test_graph_replay_equals_eager(torch):
     import paper_2508_05958_amd as H
     _say("[gpu] server: graphs vs eager")
