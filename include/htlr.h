@@ -397,7 +397,9 @@ typedef struct {
   int max_active;       /* requests in flight; <= 0: 64 */
   int max_batch;        /* requests of one structure fused per product (1..64); <= 0: 16 */
   int restart;          /* GMRES cycle length; <= 0: 30 */
-  int inner_prec;       /* htlr_precision of the inner products */
+  int inner_prec;       /* htlr_precision of the inner products; with HTLR_BF16_CORE,
+                           structures on given points (tensor grids, which have no
+                           bfloat16 cores) take FP32 inner products */
   int use_graphs;       /* 1: replay fused products from captured hipGraphs */
   int autotune;         /* 1: time kernel variants per (structure, batch width, precision) */
   int no_group_fusion;  /* 1: never fuse the products of different structures */

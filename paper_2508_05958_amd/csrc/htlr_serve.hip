@@ -114,6 +114,7 @@ struct Structure {
   hipEvent_t done = nullptr;       // end of the structure's step in flight
   htlr_matrix A = nullptr;
   int64_t N = 0;
+  int inner = HTLR_FP32;           // precision of its inner products (bfloat16 cores need a uniform grid)
   size_t bytes = 0;
   int active = 0;
   double last_use = 0;
@@ -189,7 +190,14 @@ constexpr int kRedB = 512;
 struct ServerImpl {
   htlr_server_opts o{};
   size_t budget = 0, used = 0;
-  double inner_tol = 1e-6;
+  // relative residual an inner GMRES cycle aims at, per inner precision:
+  // bfloat16-core products are within about 1e-5 of FP64 on these grids (the
+  // near field and the factors stay FP32), so a cycle can aim at 1e-4 and
+  // two refinement steps reach 1e-8 (1e-2 took four, each with an FP64 product)
+  double inner_tol_for(int prec) const {
+    if (o.inner_tol > 0) return o.inner_tol;
+    return prec == HTLR_FP32 ? 1e-6 : (prec == HTLR_BF16_CORE ? 1e-4 : 1e-12);
+  }
   int64_t next_id = 1;
   std::deque<int64_t> queue;
   std::map<int64_t, std::unique_ptr<Req>> reqs;
@@ -317,15 +325,20 @@ struct ServerImpl {
     bo.admissibility = q.adm;
     bo.a = q.a.empty() ? nullptr : q.a.data();
     bo.precisions = (1 << HTLR_FP64) | (1 << o.inner_prec);
+    // bfloat16 cores exist on uniform grids only: given points may form a
+    // tensor grid, whose inner products then run in FP32
+    const bool maybe_tensor = o.inner_prec == HTLR_BF16_CORE && !q.points.empty();
+    if (maybe_tensor) bo.precisions |= 1 << HTLR_FP32;
     HTLR_CHECK_ST(htlr_build(q.points.empty() ? nullptr : q.points.data(), (htlr_kernel)q.kernel, q.d, q.n, q.p,
                              q.leaf, &bo, &S->A));
+    S->inner = (maybe_tensor && !S->A->uniform) ? HTLR_FP32 : o.inner_prec;
     HTLR_HIP(hipStreamCreate(&S->stream));
     HTLR_HIP(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
     HTLR_HIP(hipEventCreateWithFlags(&S->done, hipEventDisableTiming));
     S->cap = o.max_batch;
     S->U64.alloc((size_t)S->N * S->cap * sizeof(double));
     S->F64.alloc((size_t)S->N * S->cap * sizeof(double));
-    if (o.inner_prec != HTLR_FP64) {
+    if (S->inner != HTLR_FP64) {
       S->U32.alloc((size_t)S->N * S->cap * sizeof(float));
       S->F32.alloc((size_t)S->N * S->cap * sizeof(float));
     }
@@ -337,7 +350,7 @@ struct ServerImpl {
       // tune the fused product shapes this structure will see
       for (int w = 1; w <= S->cap; w *= 2) {
         HTLR_CHECK_ST(htlr_autotune(S->A, w, HTLR_FP64, nullptr));
-        if (o.inner_prec != HTLR_FP64) HTLR_CHECK_ST(htlr_autotune(S->A, w, (htlr_precision)o.inner_prec, nullptr));
+        if (S->inner != HTLR_FP64) HTLR_CHECK_ST(htlr_autotune(S->A, w, (htlr_precision)S->inner, nullptr));
       }
     }
     {
@@ -574,7 +587,7 @@ struct ServerImpl {
         post_residual(R[i], S->F64.as<double>() + (int64_t)(i - s) * N, S->stream, part);
     }
     // Arnoldi steps: w = A V_k (inner precision), CGS2, norm
-    const int ip = o.inner_prec;
+    const int ip = S->inner;
     for (size_t s = 0; s < K.size(); s += o.max_batch) {
       const size_t e = std::min(K.size(), s + (size_t)o.max_batch);
       std::vector<const double*> src;
@@ -627,13 +640,14 @@ struct ServerImpl {
     if (G->cols < need) {
       const int64_t N = Ss[0]->N;
       const int cols = std::min(kMaxGroupCols, std::max(need, 2 * o.max_batch));
-      const size_t per = (size_t)N * cols * (sizeof(double) * 2 + (o.inner_prec != HTLR_FP64 ? sizeof(float) * 2 : 0));
-      const size_t old = (size_t)N * G->cols * (sizeof(double) * 2 + (o.inner_prec != HTLR_FP64 ? sizeof(float) * 2 : 0));
+      const bool f32 = Ss[0]->inner != HTLR_FP64;
+      const size_t per = (size_t)N * cols * (sizeof(double) * 2 + (f32 ? sizeof(float) * 2 : 0));
+      const size_t old = (size_t)N * G->cols * (sizeof(double) * 2 + (f32 ? sizeof(float) * 2 : 0));
       if (used - old + per > budget) return nullptr;
       G->drop_graphs();
       G->U64.alloc((size_t)N * cols * sizeof(double));
       G->F64.alloc((size_t)N * cols * sizeof(double));
-      if (o.inner_prec != HTLR_FP64) {
+      if (f32) {
         G->U32.alloc((size_t)N * cols * sizeof(float));
         G->F32.alloc((size_t)N * cols * sizeof(float));
       }
@@ -742,7 +756,7 @@ struct ServerImpl {
         }
       }
       if (Q.empty()) continue;
-      const int prec = phase == 0 ? HTLR_FP64 : o.inner_prec;
+      const int prec = phase == 0 ? HTLR_FP64 : Ss[0]->inner;   // members of a group share their grid
       group_product(G, prec, phase, mem, cols, src);
       for (size_t i = 0; i < Q.size(); ++i) {
         if (phase == 0)
@@ -782,7 +796,7 @@ struct ServerImpl {
       // start a GMRES cycle on A d = r
       ++q.outer;
       q.beta = q.rn;
-      q.rtol = std::max(inner_tol, q.tol * q.fn / q.rn);
+      q.rtol = std::max(inner_tol_for(q.S->inner), q.tol * q.fn / q.rn);
       hipLaunchKernelGGL(k_scale_to, dim3(vblocks(N)), dim3(256), 0, S->stream, q.dr, 1.0 / q.beta, q.V, N);
       std::fill(q.g.begin(), q.g.end(), 0.0);
       q.g[0] = q.beta;
@@ -950,11 +964,6 @@ htlr_status htlr_server_create(const htlr_server_opts* opts, htlr_server* out) {
     if (S->o.restart > 200) fail(HTLR_ERR_INVALID, "restart too large");
     const int ip = S->o.inner_prec;
     if (ip != HTLR_FP64 && ip != HTLR_FP32 && ip != HTLR_BF16_CORE) fail(HTLR_ERR_INVALID, "unknown inner precision");
-    // bfloat16-core products are within about 1e-5 of FP64 on these grids (the
-    // near field and the factors stay FP32), so a cycle can aim at 1e-4: two
-    // refinement steps reach 1e-8 (1e-2 took four, each with an FP64 product)
-    S->inner_tol = S->o.inner_tol > 0 ? S->o.inner_tol
-                                      : (ip == HTLR_FP32 ? 1e-6 : (ip == HTLR_BF16_CORE ? 1e-4 : 1e-12));
     S->budget = S->o.memory_budget;
     if (!S->budget) {
       size_t fr = 0, tot = 0;

@@ -209,6 +209,33 @@ def test_bf16_core_inner_products(torch):
         assert _residual(reqs[k], u16) <= 2 * TOL
 
 
+def test_bf16_server_with_a_warped_grid(torch):
+    """A bfloat16-inner server also serves a request on a warped tensor grid
+    (given points, no bfloat16 cores there): that structure takes FP32 inner
+    products, its answer solves O2's system to the tolerance, and the
+    uniform-grid requests beside it still converge."""
+    import paper_2508_05958_amd as H
+    _say("[gpu] server: bfloat16 inner products with a warped-grid request")
+    d, n, p, leaf = 2, 32, 6, 8
+    x = W.warped_nodes(n)
+    g = geometry.tensor_grid([x] * d)
+    a = 1.0 + 0.5 * g.points()[:, 0]
+    f = np.random.default_rng([4, 500]).standard_normal(g.N)
+    warped = dict(f=f, kernel="exp", d=d, n=n, p=p, leaf=leaf, a=a, tol=TOL, points=np.concatenate([x] * d))
+    reqs = _requests(3)
+    S = H.Server(max_batch=4, inner_prec="bf16", use_graphs=True)
+    ids = [S.submit(**r) for r in reqs] + [S.submit(**warped)]
+    res = _drain(S, list(ids))
+    S.close()
+    for rid in ids:
+        assert res[rid][1]["status"] == 0 and res[rid][1]["rel_residual"] <= TOL
+    u = res[ids[-1]][0]
+    O = htlr.HTLR(g, "exp", p, leaf, a)
+    rel = np.linalg.norm(f - O.matvec(u)) / np.linalg.norm(f)
+    _say(f"[gpu]   warped request: O2 residual {rel:.2e}")
+    assert rel <= 2 * TOL
+
+
 def test_graph_replay_equals_eager(torch):
     import paper_2508_05958_amd as H
     _say("[gpu] server: graphs vs eager")
