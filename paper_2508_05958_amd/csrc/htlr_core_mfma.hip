@@ -47,6 +47,24 @@ template <> struct AccT<double> { using type = double; };
 // become generic, and generic loads are also counted by the LDS wait counter,
 // which would make every LDS wait of the MFMA loop wait for the prefetch.
 template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+typedef __attribute__((address_space(3))) void* lds_vptr;
+
+// One direct-to-LDS load: each lane's 16 bytes at src go to LDS byte address
+// lds + 16 * lane (lds wave-uniform).  Written as a statement of its own so
+// that the compiler, which cannot tell which LDS buffer such a load writes,
+// does not make the operand reads of the other buffer wait for it; the
+// caller waits for the load counter before the barrier that publishes the
+// buffer.  The instruction has no register result (its address registers
+// are read at issue).
+// M0 (the LDS base of the load) is written here and declared clobbered; no
+// other code of these kernels keeps a value in M0.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16(const void* src, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
 
 // Source tensor of one staged column for offset o, or the zero tensor when
 // the column is empty or its source box lies outside the domain.
@@ -95,16 +113,31 @@ __global__ __launch_bounds__(core_threads(BMT)) __attribute__((amdgpu_waves_per_
   constexpr int CB = stage_bytes<TE, BMT, BNT>();
   constexpr int PD = prefetch_depth<TE, BMT, BNT>();
   constexpr int KBE = CB / sizeof(TE);    // K elements per stage
-  constexpr int LDW = KBE + E;            // padded LDS row
+  // FP64 128 x 128 tiles stage by direct-to-LDS loads (global loads with an
+  // LDS destination: no register staging, no LDS writes by the waves).  One
+  // such load writes 64 consecutive 16-byte chunks, so the rows are unpadded
+  // (128 bytes) and a row's chunks are XOR-swizzled by (row / 2) mod 8, which
+  // keeps the 16-row operand reads free of bank conflicts.
+  constexpr bool DL = std::is_same<TE, double>::value && BMT == 128 && BNT == 128;
+  constexpr int LDW = DL ? KBE : KBE + E; // LDS row (padded unless DL)
   constexpr int CPR = CB / 16;            // 16-byte chunks per staged row
   constexpr int RPP = NT / CPR;           // rows staged per pass of all threads
   constexpr int NA = (BMT + RPP - 1) / RPP;   // A rows staged per thread (the last pass may be partial)
   constexpr int NBH = BNT / RPP;          // B columns staged per thread
   constexpr int WNC = BNT / 2;            // columns per wave
   static_assert(NA >= 1 && NBH >= 1 && NBH * RPP == BNT, "staging shape");
+  static_assert(!DL || (CPR == 8 && NA * RPP == BMT), "direct-to-LDS staging shape");
   constexpr bool APART = NA * RPP != BMT;     // rows srow + (NA - 1) RPP >= BMT are not staged
-  __shared__ __align__(16) TE As[2][BMT * LDW];
-  __shared__ __align__(16) TE Bs[2][BNT * LDW];
+  // the two buffers of each operand are separate variables, so that the
+  // compiler can tell a direct-to-LDS load into one from reads of the other
+  // (otherwise it waits for the load before the reads)
+  __shared__ __align__(16) TE As0[BMT * LDW], As1[BMT * LDW];
+  __shared__ __align__(16) TE Bs0[BNT * LDW], Bs1[BNT * LDW];
+#define HTLR_AS(BUF) ((BUF) ? As1 : As0)
+  auto lds_addr = [](const TE* p) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)(lds_vptr)(TE*)p);
+  };
+#define HTLR_BS(BUF) ((BUF) ? Bs1 : Bs0)
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // Work item of this workgroup.  Workgroups are dealt to the 8 XCDs round
@@ -119,6 +152,10 @@ __global__ __launch_bounds__(core_threads(BMT)) __attribute__((amdgpu_waves_per_
   const int split = item & 63;
   const int part = tid % CPR;             // 16-byte chunk within a staged row slice
   const int srow = tid / CPR;             // staged row / column, plus multiples of RPP
+  // K chunk this thread loads: with DL the chunk stored at position `part`
+  // of a row (rows srow + i RPP share (row / 2) mod 8 since RPP = 32)
+  const int cpart = DL ? (part ^ ((srow >> 1) & 7)) : part;
+  const int wbase = __builtin_amdgcn_readfirstlane(wv) * 64;   // first chunk of this wave's lanes
 
   // columns staged by this thread: target box (or -1), rhs, box coordinates
   int ct[NBH], cr[NBH], cx[NBH], cy[NBH], cz[NBH];
@@ -198,11 +235,33 @@ __global__ __launch_bounds__(core_threads(BMT)) __attribute__((amdgpu_waves_per_
   {                                                                                                   \
     _Pragma("unroll") for (int i = 0; i < NA; ++i)                                                    \
       if (!APART || srow + i * RPP < BMT)                                                             \
-        *reinterpret_cast<u32x4*>(&As[BUF][(srow + i * RPP) * LDW + part * E]) = RA[i];               \
+        *reinterpret_cast<u32x4*>(&HTLR_AS(BUF)[(srow + i * RPP) * LDW + part * E]) = RA[i];               \
     _Pragma("unroll") for (int h = 0; h < NBH; ++h)                                                   \
-      *reinterpret_cast<u32x4*>(&Bs[BUF][(srow + h * RPP) * LDW + part * E]) = RB[h];                 \
+      *reinterpret_cast<u32x4*>(&HTLR_BS(BUF)[(srow + h * RPP) * LDW + part * E]) = RB[h];                 \
   }
 
+// Direct-to-LDS load of the stage at K0 into LDS buffer BUF: lane l of wave
+// w writes chunk i NT + 64 w + l, i.e. row srow + i RPP, position part.
+#define HTLR_DLOAD(BUF, K0)                                                                              \
+  {                                                                                                      \
+    const int k_ = (K0) + cpart * E;                                                                     \
+    const bool kin_ = k_ < P;                                                                            \
+    _Pragma("unroll") for (int i = 0; i < NA; ++i) {                                                     \
+      const int ar_ = m0 + srow + i * RPP;                                                               \
+      const gptr<TE> pa_ = (kin_ && ar_ < P) ? gA + (int64_t)ar_ * P + k_ : zg;                          \
+      lds_dma16((const void*)pa_, lds_addr(&HTLR_AS(BUF)[(i * NT + wbase) * E]));                        \
+    }                                                                                                    \
+    _Pragma("unroll") for (int h = 0; h < NBH; ++h) {                                                    \
+      const gptr<TE> pb_ = kin_ ? gB[h] + k_ : zg;                                                       \
+      lds_dma16((const void*)pb_, lds_addr(&HTLR_BS(BUF)[(h * NT + wbase) * E]));                        \
+    }                                                                                                    \
+  }
+#define HTLR_DLOAD_NEXT(BUF)                     \
+  {                                              \
+    if (++ksL == ksteps) { ksL = 0; ++eL; }      \
+    if (ksL == 0) HTLR_SET_DELTA(eL);            \
+    HTLR_DLOAD(BUF, ksL * KBE);                  \
+  }
 // Advance (EL, KSL) to the next stage and load it into (RA, RB).
 #define HTLR_LOAD_NEXT(RA, RB)                   \
   {                                              \
@@ -227,10 +286,18 @@ __global__ __launch_bounds__(core_threads(BMT)) __attribute__((amdgpu_waves_per_
       __builtin_amdgcn_sched_group_barrier(0x008, (NM), 0);                                   \
     }                                                                                         \
   }
+// Column of this lane's f64 operand element at K step KK within its LDS row
+// (16 rows x 4 K columns per read; rows r and the swizzle (r / 2) mod 8 =
+// (lane / 2) mod 8, as every wave's rows start at a multiple of 16).
+  const int kswz = DL ? ((lane >> 1) & 7) : 0;
+  auto kcol = [&](int kk) {
+    const int kc = kk + (lane >> 4);
+    return DL ? ((((kc >> 1) ^ kswz) << 1) | (kc & 1)) : kc;
+  };
 #define HTLR_COMPUTE(CUR)                                                                                                        \
   {                                                                                                                        \
-      const TE* Asb = As[CUR] + (wm * WR) * LDW;                                                                           \
-      const TE* Bsb = Bs[CUR] + (wn * WNC) * LDW;                                                                          \
+      const TE* Asb = HTLR_AS(CUR) + (wm * WR) * LDW;                                                                           \
+      const TE* Bsb = HTLR_BS(CUR) + (wn * WNC) * LDW;                                                                          \
       if constexpr (std::is_same<TE, uint16_t>::value) {                                                                   \
 _Pragma("unroll")                                                                                                          \
         for (int kk = 0; kk < KBE; kk += 16) {                                                                             \
@@ -268,9 +335,9 @@ _Pragma("unroll")                                                               
         for (int kk = 0; kk < KBE; kk += 4) {                                                                              \
           double a[TI], b[TJ];                                                                                             \
 _Pragma("unroll")                                                                                                          \
-          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];                        \
+          for (int i = 0; i < TI; ++i) a[i] = Asb[(i * 16 + (lane & 15)) * LDW + kcol(kk)];                                \
 _Pragma("unroll")                                                                                                          \
-          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 16 + (lane & 15)) * LDW + kk + (lane >> 4)];                        \
+          for (int j = 0; j < TJ; ++j) b[j] = Bsb[(j * 16 + (lane & 15)) * LDW + kcol(kk)];                                \
 _Pragma("unroll")                                                                                                          \
           for (int i = 0; i < TI; ++i)                                                                                     \
 _Pragma("unroll")                                                                                                          \
@@ -284,6 +351,12 @@ _Pragma("unroll")                                                               
 // S + 1, (RAF, RBF) receive stage S + 2 (prefetch depth 2).
 #define HTLR_STEP(CUR, RAF, RBF, RAN, RBN, S)                       \
   {                                                                 \
+    if constexpr (DL) {                                             \
+      if ((S) + 1 < nstage) HTLR_DLOAD_NEXT((CUR) ^ 1);             \
+      HTLR_COMPUTE(CUR);                                            \
+      __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0): LDS written */ \
+      __syncthreads();                                              \
+    } else {                                                        \
     if constexpr (PD == 2) {                                        \
       if ((S) + 2 < nstage) HTLR_LOAD_NEXT(RAF, RBF);               \
     } else {                                                        \
@@ -292,14 +365,20 @@ _Pragma("unroll")                                                               
     HTLR_COMPUTE(CUR);                                              \
     if ((S) + 1 < nstage) HTLR_SSTORE(RAN, RBN, (CUR) ^ 1);         \
     __syncthreads();                                                \
+    }                                                               \
   }
 
   if (nstage > 0) {
     int64_t eL = e0;   // position (offset entry, K step) of the last stage loaded
     int ksL = 0;
     HTLR_SET_DELTA(e0);
-    HTLR_GLOAD(ra0, rb0, 0);
-    HTLR_SSTORE(ra0, rb0, 0);
+    if constexpr (DL) {
+      HTLR_DLOAD(0, 0);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    } else {
+      HTLR_GLOAD(ra0, rb0, 0);
+      HTLR_SSTORE(ra0, rb0, 0);
+    }
     if constexpr (PD == 2) {
       if (nstage > 1) HTLR_LOAD_NEXT(ra1, rb1);
     }
@@ -323,6 +402,10 @@ _Pragma("unroll")                                                               
 #undef HTLR_STEP
 #undef HTLR_COMPUTE
 #undef HTLR_LOAD_NEXT
+#undef HTLR_DLOAD_NEXT
+#undef HTLR_DLOAD
+#undef HTLR_AS
+#undef HTLR_BS
 #undef HTLR_SET_DELTA
 #undef HTLR_GLOAD
 #undef HTLR_SSTORE
@@ -382,10 +465,12 @@ bool core_mfma_any(const htlr_matrix_impl& A, int prec) {
 
 // Measured at 128^3 x 16 right-hand sides (level 4): tile-major items make
 // the 64- and 32-bit core applies 4-5% faster (the row blocks of a tile read
-// the same gathered sources together); the bfloat16 one is 3% slower.
+// the same gathered sources together); the bfloat16 one is 3% slower.  Taking
+// the tiles longest list first makes them another 3-4% faster (the launch
+// ends on short boundary tiles instead of an uneven last round).
 int core_item_order(const htlr_matrix_impl& A, int prec) {
   if (A.cur.order >= 0) return A.cur.order;
-  return prec == HTLR_BF16_CORE ? 0 : 1;
+  return prec == HTLR_BF16_CORE ? 0 : 2;
 }
 
 // Work lists for tiles of nb boxes of one parity class, built on first use.
@@ -547,6 +632,7 @@ static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
   T.ntile = (int64_t)ptr.size() - 1;
   T.class_start = class_start;
   T.maxlist = maxlist;
+  for (size_t t = 0; t + 1 < ptr.size(); ++t) T.len.push_back(ptr[t + 1] - ptr[t]);
   T.tau.alloc(tau.size() * sizeof(int32_t));
   T.ptr.alloc(ptr.size() * sizeof(int64_t));
   T.off.alloc(std::max<size_t>(off.size(), 1) * sizeof(int4));
@@ -625,11 +711,17 @@ static LevelData::Tiles::Items& items_for(LevelData::Tiles& T, int ks, int nmb, 
   auto it = T.items.find(key);
   if (it != T.items.end()) return it->second;
   if (frozen) fail(HTLR_ERR_INVALID, "matrix-core work list not reserved");
-  // work items ordered (class, row block, split, tile) or (class, tile, row block, split)
+  // work items ordered (class, row block, split, tile) or (class, tile, row block, split);
+  // order 2 takes each class's tiles from the longest offset list to the
+  // shortest (ties in tile order), so that the launch ends on short items
   std::vector<int32_t> items;
   for (size_t cl = 0; cl + 1 < T.class_start.size(); ++cl) {
-    if (order == 1) {
-      for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t)
+    if (order >= 1) {
+      std::vector<int64_t> ts;
+      for (int64_t t = T.class_start[cl]; t < T.class_start[cl + 1]; ++t) ts.push_back(t);
+      if (order == 2)
+        std::stable_sort(ts.begin(), ts.end(), [&](int64_t a, int64_t b) { return T.len[a] > T.len[b]; });
+      for (int64_t t : ts)
         for (int mb = 0; mb < nmb; ++mb)
           for (int s = 0; s < ks; ++s) items.push_back((int32_t)((t << 12) | (mb << 6) | s));
     } else {

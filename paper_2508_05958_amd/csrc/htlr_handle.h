@@ -68,6 +68,7 @@ struct LevelData {
     DevBuf ptr;                      // [ntile + 1] into off
     DevBuf off;                      // int4 (core id, offset x, y, z) per entry
     std::vector<int64_t> class_start;  // first tile of each parity class
+    std::vector<int64_t> len;          // offset-list length of each tile (host)
     int64_t maxlist = 0;             // longest offset list of a tile
     struct Items {
       DevBuf buf;                    // work items (tile << 12 | row block << 6 | split)
@@ -146,7 +147,9 @@ struct TuneParams {
   int order = -1;                    // matrix-core work items: 0 (class, row block, split, tile),
                                      // 1 (class, tile, row block, split): the row blocks of a tile
                                      // run side by side and share its gathered source tensors in L2;
-                                     // -1 automatic: 1 for 64- and 32-bit cores, 0 for bfloat16
+                                     // 2 as 1 with each class's tiles longest list first (the
+                                     // short boundary tiles fill the end of the launch);
+                                     // -1 automatic: 2 for 64- and 32-bit cores, 0 for bfloat16
 };
 
 // Groups of target leaves for the leaf-column near kernel: lpc leaves per

@@ -1896,11 +1896,15 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
       {
-        TuneParams t = best;
-        const int ord = best.order >= 0 ? best.order : (prec == HTLR_BF16_CORE ? 0 : 1);
-        t.order = 1 - ord;
-        const double ms = time_with(t);
-        if (ms < best_ms) { best_ms = ms; best = t; }
+        const TuneParams base = best;
+        const int ord = base.order >= 0 ? base.order : (prec == HTLR_BF16_CORE ? 0 : 2);
+        for (int o = 0; o <= 2; ++o) {
+          if (o == ord) continue;
+          TuneParams t = base;
+          t.order = o;
+          const double ms = time_with(t);
+          if (ms < best_ms) { best_ms = ms; best = t; }
+        }
       }
     }
     const bool near_rows = A->uniform && A->d == 3 && A->plan.m[A->L] <= 8;
