@@ -143,7 +143,8 @@ struct TuneParams {
   int tile = 0;                      // matrix-core tile: 0 automatic, 1 128x128, 2 128x64, 3 256x128,
                                      // 4 224x64 (FP64), 5 256x256 (BF16), 6 64x128, 7 64x64
   int core_mode = 0;                 // 0 automatic, 1 class tiles, 2 offset-major
-  int serial = 0;                    // 1: every launch on the caller's stream (no level concurrency)
+  int serial = 0;                    // level launches: 1 every launch on the caller's stream, 2 levels on
+                                     // side streams, concurrently; 0 automatic (levels_serial)
   int order = -1;                    // matrix-core work items: 0 (class, row block, split, tile),
                                      // 1 (class, tile, row block, split): the row blocks of a tile
                                      // run side by side and share its gathered source tensors in L2;

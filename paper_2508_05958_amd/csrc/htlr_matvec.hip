@@ -1517,6 +1517,25 @@ static void check_shape(const htlr_matrix_impl& A) {
   if (A.P > 8 * kThreads) fail(HTLR_ERR_UNSUPPORTED, "p^d larger than 2048");
 }
 
+// Whether the levels' launches are issued on the caller's stream one after
+// another rather than concurrently on side streams.  Concurrency fills the
+// chip when launches are small; when one level's core apply is many
+// milliseconds of matrix-core work it fills the chip by itself, and running
+// the other levels beside it only spoils its tail.  Measured at 128^3 x 16
+// right-hand sides (level 4, 1.7e13 flop): serial is 3% faster in FP64 and
+// 2% in FP32; in bfloat16, where the core apply is bound by memory traffic
+// and the near field by the FP32 matrix rate, concurrency is 3% faster.
+static bool levels_serial(const htlr_matrix_impl& A, int serial, int nrhs, int prec) {
+  if (serial == 1) return true;
+  if (serial == 2) return false;
+  if (!A.uniform || prec == HTLR_BF16_CORE) return false;
+  double fl = 0;
+  for (const LevelData& lv : A.levels)
+    if (lv.npairs > 0) fl = std::max(fl, 2.0 * (double)lv.npairs * lv.P * lv.P * nrhs);
+  const double peak = prec == HTLR_FP64 ? 78.6e12 : 157.3e12;   // dense matrix-core flop/s
+  return fl / peak > 20e-3;
+}
+
 template <typename T>
 static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec, hipStream_t st,
                        const WorkView& wv) {
@@ -1531,7 +1550,7 @@ static void run_matvec(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int prec
   for (LevelData& lv : A.levels)
     if (lv.npairs > 0) act.push_back(&lv);
   // (serial while profiling: each recorded duration is then one launch's alone)
-  const bool fork = !wv.noalloc && A.cur.serial == 0 && !A.prof.on && !act.empty();
+  const bool fork = !wv.noalloc && !levels_serial(A, A.cur.serial, nrhs, prec) && !A.prof.on && !act.empty();
   const std::vector<hipStream_t>* side = fork ? &side_streams(A) : nullptr;
   if (fork) {
     HTLR_HIP(hipEventRecord(A.ev_fork, st));
@@ -1947,8 +1966,9 @@ htlr_status htlr_autotune(htlr_matrix A, int nrhs, htlr_precision prec, htlr_tun
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
     {
+      // the other choice of level concurrency than the automatic one
       TuneParams t = best;
-      t.serial = 1;
+      t.serial = levels_serial(*A, best.serial, nrhs, (int)prec) ? 2 : 1;
       const double ms = time_with(t);
       if (ms < best_ms) { best_ms = ms; best = t; }
     }

@@ -153,7 +153,7 @@ def test_level_concurrency_is_bitwise_serial(torch, tmp_path, monkeypatch, prec,
     dt = torch.float64 if prec == "fp64" else torch.float32
     u = torch.randn(nrhs, n ** 3, dtype=dt, generator=torch.Generator().manual_seed(7)).to("cuda").t()
     outs = []
-    for serial in (0, 1):
+    for serial in (2, 1):   # forced concurrent, then serial
         cache = tmp_path / f"tune{serial}.txt"
         key = f"d3_n{n}_p{p}_leaf{leaf}_k0_uniform_eta1_adm0_nrhs{nrhs}_prec{pid}"
         cache.write_text(f"{key} 2048 -1 0 0 0 0 0 0 {serial} 1.0 1.0\n")
