@@ -128,16 +128,14 @@ __global__ __launch_bounds__(core_threads(BMT)) __attribute__((amdgpu_waves_per_
   static_assert(NA >= 1 && NBH >= 1 && NBH * RPP == BNT, "staging shape");
   static_assert(!DL || (CPR == 8 && NA * RPP == BMT), "direct-to-LDS staging shape");
   constexpr bool APART = NA * RPP != BMT;     // rows srow + (NA - 1) RPP >= BMT are not staged
-  // the two buffers of each operand are separate variables, so that the
-  // compiler can tell a direct-to-LDS load into one from reads of the other
-  // (otherwise it waits for the load before the reads)
-  __shared__ __align__(16) TE As0[BMT * LDW], As1[BMT * LDW];
-  __shared__ __align__(16) TE Bs0[BNT * LDW], Bs1[BNT * LDW];
-#define HTLR_AS(BUF) ((BUF) ? As1 : As0)
+  __shared__ __align__(16) TE As[2][BMT * LDW];
+  __shared__ __align__(16) TE Bs[2][BNT * LDW];
+#define HTLR_AS(BUF) (As[BUF])
+#define HTLR_BS(BUF) (Bs[BUF])
+  // LDS byte address of a staging position (wave-uniform)
   auto lds_addr = [](const TE* p) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)(lds_vptr)(TE*)p);
   };
-#define HTLR_BS(BUF) ((BUF) ? Bs1 : Bs0)
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // Work item of this workgroup.  Workgroups are dealt to the 8 XCDs round
