@@ -68,10 +68,11 @@ def test_server_with_autotune(torch):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
-@pytest.mark.parametrize("mode,order", [(1, 0), (1, 1), (2, 0)])
+@pytest.mark.parametrize("mode,order", [(1, 0), (1, 1), (1, 2), (2, 0)])
 def test_every_tile_variant_matches(torch, tmp_path, monkeypatch, prec, tile, mode, order):
     """Force each matrix-core tile shape (128x128, 128x64, 256x128, 224x64, 256x256, 64x128, 64x64) through
-    the tuner's cache file, in class-tile mode with both work-item orders and
+    the tuner's cache file, in class-tile mode with each work-item order
+    (row block major, tile major, tile major with the longest lists first) and
     in offset-major mode, and compare with the oracle (FP64) or with the GPU
     FP64 product (FP32, BF16)."""
     import paper_2508_05958_amd as H
