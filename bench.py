@@ -750,12 +750,14 @@ def summarize_profile(d, command, workload, prec):
     # per launch by position in the product: a serially issued product runs
     # the levels in ascending order, so the k-th launch of a kernel within
     # each product is the same level every time (products are counted by the
-    # near-field launches, one per product)
+    # near-field launches, one per product: its own kernel, or the leaf
+    # gather of the near field on the core apply)
     tr = rows("stats", "*kernel_trace.csv")
     skip = ("build", "downcast", "diag", "core_mode", "rocclr")
     seq = [r for r in sorted(tr, key=lambda r: int(r["Dispatch_Id"]))
            if "htlr" in r["Kernel_Name"] and not any(x in r["Kernel_Name"] for x in skip)]
-    nprod = sum(1 for r in seq if "k_near" in r["Kernel_Name"] and "reduce" not in r["Kernel_Name"])
+    nprod = sum(1 for r in seq if ("k_near" in r["Kernel_Name"] or "k_leaf_gather" in r["Kernel_Name"])
+                and "reduce" not in r["Kernel_Name"])
     if nprod:
         per = {}
         for r in seq:

@@ -490,7 +490,7 @@ static LevelData::Tiles& tiles_for(htlr_matrix_impl& A, LevelData& lv, int nb) {
   for (auto& t : lv.tiles)
     if (t.nb == nb) return t;
   const int d = A.d, B = lv.B;
-  const Csr& cs = A.plan.adm[lv.level];
+  const Csr& cs = lv.csr ? *lv.csr : A.plan.adm[lv.level];
   std::vector<int32_t> tau;
   std::vector<int64_t> ptr{0};
   std::vector<int4> off;
@@ -789,7 +789,7 @@ static LevelData::OffsetTiles& offset_tiles_for(htlr_matrix_impl& A, LevelData& 
     if (t.nb == nb && t.nmb == nmb) return t;
   if (frozen) fail(HTLR_ERR_INVALID, "offset-major work list not reserved");
   const int B = lv.B;
-  const Csr& cs = A.plan.adm[lv.level];
+  const Csr& cs = lv.csr ? *lv.csr : A.plan.adm[lv.level];
   std::map<std::array<int, 3>, int> cid;
   for (int c = 0; c < lv.ncore; ++c)
     cid[{lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2]}] = c;
@@ -1033,5 +1033,149 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs) {
   side_streams(A);
   A.ws.frozen = true;
 }
+
+// ---------------------------------------------------------------------------
+// Near field on the matrix cores through the core apply.
+//
+// On a uniform grid with 8^3-point leaves the near-field block between a
+// target leaf tau and a near leaf sigma (eq. 4.1 restricted to the pair)
+// depends only on the offset Delta = sigma - tau: K_Delta[i][j] = T[|I - J|^2]
+// with I and J the grid indices of target point i and source point j (T the
+// distance table, whose entry 0 is the diagonal term of eq. 1.4).  So the
+// near field is the same implicit GEMM as a level of the far field, with
+// rows = the 512 target points, columns = (leaf, rhs) and K = (Delta, j),
+// run by the class-tile kernel above on u gathered into leaf-major order.
+// The block sums are the near kernels' sums in another order.
+
+namespace {
+
+constexpr int kLeafPts = 512;   // points of an 8^3 leaf, x fastest
+
+__device__ __forceinline__ int64_t leaf_point(int leaf, int j, int n, int B) {
+  const int lx = leaf % B, ly = (leaf / B) % B, lz = leaf / (B * B);
+  return (int64_t)(lx * 8 + (j & 7)) + (int64_t)n * ((ly * 8 + ((j >> 3) & 7)) + (int64_t)n * (lz * 8 + (j >> 6)));
+}
+
+// K_Delta for every near offset: block (512^2 / 256, ncore), 256 threads.
+template <typename T>
+__global__ void k_near_block(const T* __restrict__ tab, const int4* __restrict__ off, T* __restrict__ G) {
+  const int4 o = off[blockIdx.y];
+  const int e = blockIdx.x * 256 + threadIdx.x;   // row i * 512 + column j
+  const int i = e >> 9, j = e & 511;
+  const int dx = (j & 7) + 8 * o.x - (i & 7);
+  const int dy = ((j >> 3) & 7) + 8 * o.y - ((i >> 3) & 7);
+  const int dz = (j >> 6) + 8 * o.z - (i >> 6);
+  G[(int64_t)blockIdx.y * kLeafPts * kLeafPts + e] = tab[dx * dx + dy * dy + dz * dz];
+}
+
+// w[leaf][r][j] = u[r][point j of leaf]: block (leaf, r), 256 threads.
+template <typename T>
+__global__ void k_leaf_gather(const T* __restrict__ u, T* __restrict__ w, int n, int B, int nrhs) {
+  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int64_t N = (int64_t)n * n * n;
+  for (int j = threadIdx.x; j < kLeafPts; j += 256)
+    w[((int64_t)leaf * nrhs + r) * kLeafPts + j] = u[(int64_t)r * N + leaf_point(leaf, j, n, B)];
+}
+
+// f[r][point i of leaf] = h[leaf][r][i] + a_i u[r][i]: block (leaf, r), 256 threads.
+template <typename T>
+__global__ void k_leaf_scatter(const T* __restrict__ h, const T* __restrict__ u, const T* __restrict__ a,
+                               T* __restrict__ f, int n, int B, int nrhs) {
+  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int64_t N = (int64_t)n * n * n;
+  for (int i = threadIdx.x; i < kLeafPts; i += 256) {
+    const int64_t g = leaf_point(leaf, i, n, B);
+    const int64_t o = (int64_t)r * N + g;
+    f[o] = h[((int64_t)leaf * nrhs + r) * kLeafPts + i] + a[g] * u[o];
+  }
+}
+
+}  // namespace
+
+bool near_tiles_ok(const htlr_matrix_impl& A, int nrhs) {
+  return A.uniform && A.d == 3 && A.L >= 1 && A.plan.m[A.L] == 8 && A.kid != HTLR_K_POLY_TEST && A.Tsize > 0 &&
+         nrhs >= 1 && nrhs <= kBNmax && !A.ws.frozen;
+}
+
+// The near level: distinct near offsets and their blocks in both precisions.
+static LevelData& near_level(htlr_matrix_impl& A) {
+  if (A.near_lv) return *A.near_lv;
+  const Plan& pl = A.plan;
+  const Csr& cs = pl.near;
+  auto nl = std::make_unique<LevelData>();
+  LevelData& lv = *nl;
+  lv.level = A.L + 1;
+  lv.B = pl.B[A.L];
+  lv.m = 8;
+  lv.P = kLeafPts;
+  lv.rank = 8;
+  lv.nbox = A.levels[A.L].nbox;
+  lv.npairs = cs.nnz();
+  lv.csr = &cs;
+  const int B = lv.B;
+  std::map<std::array<int, 3>, int> cid;
+  for (int64_t t = 0; t < lv.nbox; ++t)
+    for (int64_t e = cs.ptr[t]; e < cs.ptr[t + 1]; ++e) {
+      const int64_t sg = cs.src[e];
+      const std::array<int, 3> o{(int)(sg % B) - (int)(t % B), (int)((sg / B) % B) - (int)((t / B) % B),
+                                 (int)(sg / ((int64_t)B * B)) - (int)(t / ((int64_t)B * B))};
+      if (cid.emplace(o, (int)cid.size()).second) lv.offsets.insert(lv.offsets.end(), o.begin(), o.end());
+    }
+  lv.ncore = (int)cid.size();
+  if (lv.ncore == 0) fail(HTLR_ERR_UNSUPPORTED, "no near leaves");
+  // every table index of a block must lie in the table
+  for (int c = 0; c < lv.ncore; ++c) {
+    int64_t d2 = 0;
+    for (int k = 0; k < 3; ++k) {
+      const int64_t dm = 8 * (int64_t)std::abs(lv.offsets[3 * c + k]) + 7;
+      d2 += dm * dm;
+    }
+    if (d2 >= A.Tsize) fail(HTLR_ERR_UNSUPPORTED, "near block outside the distance table");
+  }
+  std::vector<int4> off(lv.ncore);
+  for (int c = 0; c < lv.ncore; ++c)
+    off[c] = make_int4(lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2], 0);
+  DevBuf doff;
+  doff.alloc(off.size() * sizeof(int4));
+  HTLR_HIP(hipMemcpy(doff.ptr, off.data(), off.size() * sizeof(int4), hipMemcpyHostToDevice));
+  const size_t blk = (size_t)lv.ncore * kLeafPts * kLeafPts;
+  const dim3 grid(kLeafPts * kLeafPts / 256, lv.ncore);
+  lv.Gm64.alloc(blk * sizeof(double));
+  lv.Gm32.alloc(blk * sizeof(float));
+  hipLaunchKernelGGL(k_near_block<double>, grid, dim3(256), 0, 0, A.T64.as<double>(), doff.as<int4>(),
+                     lv.Gm64.as<double>());
+  hipLaunchKernelGGL(k_near_block<float>, grid, dim3(256), 0, 0, A.T32.as<float>(), doff.as<int4>(),
+                     lv.Gm32.as<float>());
+  HTLR_HIP(hipGetLastError());
+  HTLR_HIP(hipDeviceSynchronize());
+  A.near_zero.alloc(kLeafPts * sizeof(double));
+  HTLR_HIP(hipMemset(A.near_zero.ptr, 0, A.near_zero.bytes));
+  A.device_bytes += lv.Gm64.bytes + lv.Gm32.bytes + A.near_zero.bytes;
+  A.near_lv = std::move(nl);
+  return *A.near_lv;
+}
+
+template <typename T>
+void launch_near_tiles(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st) {
+  if (!near_tiles_ok(A, nrhs)) fail(HTLR_ERR_UNSUPPORTED, "near field on the core apply does not serve this product");
+  LevelData& lv = near_level(A);
+  const bool f64 = std::is_same<T, double>::value;
+  const size_t need = (size_t)lv.nbox * nrhs * kLeafPts * sizeof(T);
+  if (A.near_w.bytes < need) {
+    A.near_w.alloc(need);
+    A.near_h.alloc(need);
+  }
+  const int n = A.n, B = lv.B;
+  const T* a = f64 ? (const T*)A.a64.ptr : (const T*)A.a32.ptr;
+  const dim3 grid((unsigned)lv.nbox, nrhs);
+  hipLaunchKernelGGL(k_leaf_gather<T>, grid, dim3(256), 0, st, u, (T*)A.near_w.ptr, n, B, nrhs);
+  HTLR_HIP(hipGetLastError());
+  launch_core_mfma(A, lv, f64 ? HTLR_FP64 : HTLR_FP32, A.near_w.ptr, A.near_h.ptr, A.near_zero.ptr, nrhs, st);
+  hipLaunchKernelGGL(k_leaf_scatter<T>, grid, dim3(256), 0, st, (const T*)A.near_h.ptr, u, a, f, n, B, nrhs);
+  HTLR_HIP(hipGetLastError());
+}
+
+template void launch_near_tiles<double>(htlr_matrix_impl&, const double*, double*, int, hipStream_t);
+template void launch_near_tiles<float>(htlr_matrix_impl&, const float*, float*, int, hipStream_t);
 
 }  // namespace htlr

@@ -55,6 +55,8 @@ struct LevelData {
   int rank = 0, P = 0;               // Tucker rank of the level's factors and cores (P = rank^d)
   int64_t nbox = 0, npairs = 0;
   DevBuf ptr, src, cid;              // CSR of admissible leaves; core id per entry (uniform)
+  const Csr* csr = nullptr;          // pair lists of the matrix-core work lists (nullptr: the
+                                     // plan's admissible leaves of this level)
   DevBuf U64, V64, U32, V32;         // factors: uniform [m][p]; tensor [d][B][m][p]
   DevBuf cheb64, cheb32;             // tensor grids: Chebyshev points [d][B][p]
   int ncore = 0;                     // uniform grids: one core per offset
@@ -136,6 +138,8 @@ struct TuneParams {
   int near_kind = -1;                // -1 automatic, 0 VALU row kernel, 1 matrix-core kernel with
                                      // right-hand sides as columns, 2 with target leaves as columns,
                                      // 3 the generic uniform-grid kernel (no row reuse)
+                                     // 4 the near field as class tiles of the matrix-core core
+                                     // apply (one 512 x 512 block per near offset)
   int near_nw = 0;                   // VALU row kernel: waves per leaf (0 automatic)
   int near_ks = 0;                   // leaf-column near kernel: K splits (0 automatic)
   int near_tpw = 0;                  // leaf-column near kernel: 16-row tiles per wave, 4 or 8 (0 = 8)
@@ -194,6 +198,11 @@ struct htlr_matrix_impl {
   int Tsize = 0;
   std::vector<LevelData> levels;     // index = level
   std::vector<NearGroups> ngroups;   // leaf-column near kernel work lists, per leaves per group
+  // near field as class tiles of the matrix-core core apply (uniform 3D grids,
+  // 8^3-point leaves): one 512 x 512 block per near offset, built on first use,
+  // as a level of its own (index L + 1, so its K-split buffer is its own)
+  std::unique_ptr<LevelData> near_lv;
+  DevBuf near_w, near_h, near_zero;  // leaf-major u and near result [leaf][rhs][512]; zero tensor
   size_t device_bytes = 0;
   std::mutex ws_mu;
   Workspace ws;
@@ -258,6 +267,12 @@ void reserve_workspace(htlr_matrix_impl& A, int nrhs);
 // Choices for a product of this shape: exact match, else the nearest tuned
 // smaller width of the same precision, else the defaults.
 TuneParams find_tune(const htlr_matrix_impl& A, int nrhs, int prec);
+// Near field on the matrix-core core apply (uniform 3D grids, 8^3-point
+// leaves, radial kernels): whether it serves a product of this shape, and the
+// product's near field and diagonal term (overwrites f).
+bool near_tiles_ok(const htlr_matrix_impl& A, int nrhs);
+template <typename T>
+void launch_near_tiles(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st);
 // Leaf-column near field (uniform 3D grids, 8^3-point leaves, radial kernels, nrhs <= 16).
 bool near_leaves_ok(const htlr_matrix_impl& A, int nrhs, int prec);
 NearLeavesShape near_leaves_shape(htlr_matrix_impl& A, int nrhs, int prec, bool frozen);
