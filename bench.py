@@ -753,7 +753,7 @@ def summarize_profile(d, command, workload, prec):
     # near-field launches, one per product: its own kernel, or the leaf
     # gather of the near field on the core apply)
     tr = rows("stats", "*kernel_trace.csv")
-    skip = ("build", "downcast", "diag", "core_mode", "rocclr")
+    skip = ("build", "near_block", "downcast", "diag", "core_mode", "rocclr")
     seq = [r for r in sorted(tr, key=lambda r: int(r["Dispatch_Id"]))
            if "htlr" in r["Kernel_Name"] and not any(x in r["Kernel_Name"] for x in skip)]
     nprod = sum(1 for r in seq if ("k_near" in r["Kernel_Name"] or "k_leaf_gather" in r["Kernel_Name"])
