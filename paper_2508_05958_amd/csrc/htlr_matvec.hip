@@ -1363,9 +1363,12 @@ static void launch_near(htlr_matrix_impl& A, const T* u, T* f, int nrhs, int pre
   const int64_t nleaf = A.levels[A.L].nbox;
   const bool mfma_ok = A.uniform && d == 3 && m == 8 && A.kid != HTLR_K_POLY_TEST &&
                        (((size_t)A.Tsize + 3) & ~size_t(3)) * sizeof(T) + (size_t)256 * 16 * sizeof(T) <= kLdsBudget;
-  // 16 or more right-hand sides: the near field as class tiles of the core
-  // apply (128^3 x 16: FP64 59.4 -> about 51 ms, FP32 33.3 -> about 28 ms)
-  if (!noalloc && near_tiles_ok(A, nrhs) && (A.cur.near_kind == 4 || (A.cur.near_kind < 0 && nrhs >= 16))) {
+  // two or more right-hand sides: the near field as class tiles of the core
+  // apply.  Measured at 128^3 (FP64): 16 RHS 59.4 -> 49.9 ms against the
+  // table kernel; 12 RHS 59.9 -> 55.4; 8 RHS 32.5 -> 29.4, 4 RHS 16.7 ->
+  // 15.9, 2 RHS 8.3 -> 7.9 against the automatic choice before it.  One
+  // right-hand side keeps the leaf-column kernel (a tile would span 128 leaves).
+  if (!noalloc && near_tiles_ok(A, nrhs) && (A.cur.near_kind == 4 || (A.cur.near_kind < 0 && nrhs >= 2))) {
     launch_near_tiles<T>(A, u, f, nrhs, st);
     return;
   }

@@ -46,8 +46,9 @@ def _build(H, monkeypatch, tmp_path, n, p, nrhs, near_kind, tag):
 
 
 # 32^3: 4^3 leaves (every leaf touches the boundary); 64^3: 8^3 leaves;
-# 20 right-hand sides: tiles of 4 leaves x 20 columns, the rest of the 128 empty
-@pytest.mark.parametrize("n,p,nrhs", [(32, 4, 16), (64, 4, 16), (64, 4, 20)])
+# 20 right-hand sides: tiles of 4 leaves x 20 columns, the rest of the 128 empty;
+# 2 and 5: tiles of 64 and 16 leaves
+@pytest.mark.parametrize("n,p,nrhs", [(32, 4, 16), (64, 4, 16), (64, 4, 20), (64, 4, 2), (32, 4, 5)])
 def test_near_tiles_match_oracle_and_table_kernel(torch, tmp_path, monkeypatch, n, p, nrhs):
     import paper_2508_05958_amd as H
     from oracle import htlr
@@ -63,7 +64,7 @@ def test_near_tiles_match_oracle_and_table_kernel(torch, tmp_path, monkeypatch, 
         M.free()
     f4, f4s = out[4]
     f1, _ = out[1]
-    # the automatic choice at 16 or more right-hand sides is the tiled near field
+    # the automatic choice at two or more right-hand sides is the tiled near field
     assert np.array_equal(out[-1][0], f4) and np.array_equal(out[-1][1], f4s)
     # same sums as the on-the-fly kernel, in another order
     assert np.linalg.norm(f4 - f1) / np.linalg.norm(f1) <= 1e-13
