@@ -188,7 +188,15 @@ htlr_status htlr_footprint(const double* points, htlr_kernel kernel, int d, int 
                            int leaf, const htlr_build_opts* opts, size_t* bytes);
 
 /* Device bytes of the work buffers a product with nrhs right-hand sides in
- * precision prec needs (allocated inside the handle on first use). */
+ * precision prec needs (allocated inside the handle on first use).  Not
+ * included: on uniform 3D grids with 8^3-point leaves and radial kernels, a
+ * product with nrhs >= 2 on a handle whose workspace is not reserved runs the
+ * near field on the matrix-core core apply.  On first use it builds one
+ * 512 x 512 block per near offset in FP64 and FP32 (3 MB per offset; 117
+ * offsets at 16^3 leaves) and leaf-major copies of u and of the near
+ * result (2 N nrhs values) plus their K-split partial sums, and keeps them
+ * with the handle.  Reserved workspaces (the server) and
+ * htlr_matvec_noalloc use the table kernel instead. */
 htlr_status htlr_workspace_bytes(htlr_matrix A, int nrhs, htlr_precision prec, size_t* bytes);
 
 /* f = A u (overwrites f) by the HTLR product (Alg. 4.2, eq. 4.3).
