@@ -1097,9 +1097,14 @@ bool near_tiles_ok(const htlr_matrix_impl& A, int nrhs) {
          nrhs >= 1 && nrhs <= kBNmax && !A.ws.frozen;
 }
 
-// The near level: distinct near offsets and their blocks in both precisions.
-static LevelData& near_level(htlr_matrix_impl& A) {
-  if (A.near_lv) return *A.near_lv;
+// The near level: distinct near offsets (host lists, built once) and their
+// blocks in the precision asked for (each built on first use).
+static void near_blocks(htlr_matrix_impl& A, LevelData& lv, bool f64);
+static LevelData& near_level(htlr_matrix_impl& A, bool f64) {
+  if (A.near_lv) {
+    near_blocks(A, *A.near_lv, f64);
+    return *A.near_lv;
+  }
   const Plan& pl = A.plan;
   const Csr& cs = pl.near;
   auto nl = std::make_unique<LevelData>();
@@ -1135,31 +1140,38 @@ static LevelData& near_level(htlr_matrix_impl& A) {
   std::vector<int4> off(lv.ncore);
   for (int c = 0; c < lv.ncore; ++c)
     off[c] = make_int4(lv.offsets[3 * c], lv.offsets[3 * c + 1], lv.offsets[3 * c + 2], 0);
-  DevBuf doff;
-  doff.alloc(off.size() * sizeof(int4));
-  HTLR_HIP(hipMemcpy(doff.ptr, off.data(), off.size() * sizeof(int4), hipMemcpyHostToDevice));
-  const size_t blk = (size_t)lv.ncore * kLeafPts * kLeafPts;
-  const dim3 grid(kLeafPts * kLeafPts / 256, lv.ncore);
-  lv.Gm64.alloc(blk * sizeof(double));
-  lv.Gm32.alloc(blk * sizeof(float));
-  hipLaunchKernelGGL(k_near_block<double>, grid, dim3(256), 0, 0, A.T64.as<double>(), doff.as<int4>(),
-                     lv.Gm64.as<double>());
-  hipLaunchKernelGGL(k_near_block<float>, grid, dim3(256), 0, 0, A.T32.as<float>(), doff.as<int4>(),
-                     lv.Gm32.as<float>());
-  HTLR_HIP(hipGetLastError());
-  HTLR_HIP(hipDeviceSynchronize());
+  A.near_off.alloc(off.size() * sizeof(int4));
+  HTLR_HIP(hipMemcpy(A.near_off.ptr, off.data(), off.size() * sizeof(int4), hipMemcpyHostToDevice));
   A.near_zero.alloc(kLeafPts * sizeof(double));
   HTLR_HIP(hipMemset(A.near_zero.ptr, 0, A.near_zero.bytes));
-  A.device_bytes += lv.Gm64.bytes + lv.Gm32.bytes + A.near_zero.bytes;
+  A.device_bytes += A.near_off.bytes + A.near_zero.bytes;
   A.near_lv = std::move(nl);
+  near_blocks(A, *A.near_lv, f64);
   return *A.near_lv;
+}
+
+static void near_blocks(htlr_matrix_impl& A, LevelData& lv, bool f64) {
+  DevBuf& G = f64 ? lv.Gm64 : lv.Gm32;
+  if (G.ptr) return;
+  const size_t blk = (size_t)lv.ncore * kLeafPts * kLeafPts;
+  const dim3 grid(kLeafPts * kLeafPts / 256, lv.ncore);
+  G.alloc(blk * (f64 ? sizeof(double) : sizeof(float)));
+  if (f64)
+    hipLaunchKernelGGL(k_near_block<double>, grid, dim3(256), 0, 0, A.T64.as<double>(), A.near_off.as<int4>(),
+                       G.as<double>());
+  else
+    hipLaunchKernelGGL(k_near_block<float>, grid, dim3(256), 0, 0, A.T32.as<float>(), A.near_off.as<int4>(),
+                       G.as<float>());
+  HTLR_HIP(hipGetLastError());
+  HTLR_HIP(hipDeviceSynchronize());
+  A.device_bytes += G.bytes;
 }
 
 template <typename T>
 void launch_near_tiles(htlr_matrix_impl& A, const T* u, T* f, int nrhs, hipStream_t st) {
   if (!near_tiles_ok(A, nrhs)) fail(HTLR_ERR_UNSUPPORTED, "near field on the core apply does not serve this product");
-  LevelData& lv = near_level(A);
   const bool f64 = std::is_same<T, double>::value;
+  LevelData& lv = near_level(A, f64);
   const size_t need = (size_t)lv.nbox * nrhs * kLeafPts * sizeof(T);
   if (A.near_w.bytes < need) {
     A.near_w.alloc(need);

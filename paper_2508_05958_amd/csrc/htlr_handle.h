@@ -203,6 +203,7 @@ struct htlr_matrix_impl {
   // as a level of its own (index L + 1, so its K-split buffer is its own)
   std::unique_ptr<LevelData> near_lv;
   DevBuf near_w, near_h, near_zero;  // leaf-major u and near result [leaf][rhs][512]; zero tensor
+  DevBuf near_off;                   // int4 near offsets, for building each precision's blocks
   size_t device_bytes = 0;
   std::mutex ws_mu;
   Workspace ws;
